@@ -1,0 +1,150 @@
+"""Seeded synthetic graphs in simple undirected CSR form.
+
+Inputs for both the GPU library and the CPU checker come from here.  The
+module holds no step of the colouring method: it draws random graphs
+(Erdos-Renyi, R-MAT, Chung-Lu) from counter-based SplitMix64 streams and
+builds a symmetric CSR without self-loops or duplicate entries, rows sorted.
+
+Every function returns ``(row_ptr, col_idx)`` as numpy arrays
+(``int64[n+1]``, ``int32[nnz]``).
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+from . import _build
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        lib = ctypes.CDLL(_build.LIB)
+        vp, i64, u64, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+        lib.gg_n.restype = i64
+        lib.gg_n.argtypes = [vp]
+        lib.gg_nnz.restype = i64
+        lib.gg_nnz.argtypes = [vp]
+        lib.gg_copy.restype = None
+        lib.gg_copy.argtypes = [vp, vp, vp]
+        lib.gg_free.restype = None
+        lib.gg_free.argtypes = [vp]
+        lib.gg_from_edges.restype = vp
+        lib.gg_from_edges.argtypes = [i64, i64, vp, vp]
+        lib.gg_erdos_renyi.restype = vp
+        lib.gg_erdos_renyi.argtypes = [i64, f64, u64]
+        lib.gg_rmat.restype = vp
+        lib.gg_rmat.argtypes = [ctypes.c_int, i64, f64, f64, f64, u64]
+        lib.gg_chung_lu.restype = vp
+        lib.gg_chung_lu.argtypes = [i64, f64, f64, u64]
+        lib.gg_chung_lu_weights.restype = ctypes.c_int
+        lib.gg_chung_lu_weights.argtypes = [i64, f64, f64, vp]
+        lib.gg_splitmix64_draw.restype = u64
+        lib.gg_splitmix64_draw.argtypes = [u64, u64]
+        lib.gg_num_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _take(h):
+    if not h:
+        raise ValueError("graph generation failed (bad arguments or out of memory)")
+    lib = _load()
+    try:
+        n, nnz = lib.gg_n(h), lib.gg_nnz(h)
+        rp = np.empty(n + 1, dtype=np.int64)
+        col = np.empty(nnz, dtype=np.int32)
+        lib.gg_copy(h, rp.ctypes.data, col.ctypes.data)
+    finally:
+        lib.gg_free(h)
+    return rp, col
+
+
+def from_edges(n, src, dst):
+    """Simple undirected CSR spanned by the listed edges (either direction,
+    repeats allowed, self-loops dropped)."""
+    src = np.ascontiguousarray(src, dtype=np.int32)
+    dst = np.ascontiguousarray(dst, dtype=np.int32)
+    if src.shape != dst.shape:
+        raise ValueError("src and dst differ in length")
+    return _take(_load().gg_from_edges(int(n), int(src.size), src.ctypes.data, dst.ctypes.data))
+
+
+def erdos_renyi(n, p, seed):
+    """G(n, p): each unordered pair independently with probability p."""
+    return _take(_load().gg_erdos_renyi(int(n), float(p), int(seed) & (2**64 - 1)))
+
+
+def rmat(scale, edge_factor=16, a=0.57, b=0.19, c=0.19, seed=0):
+    """R-MAT on 2^scale vertices with edge_factor * 2^scale edge draws."""
+    ne = int(edge_factor) << int(scale)
+    return _take(_load().gg_rmat(int(scale), ne, float(a), float(b), float(c), int(seed) & (2**64 - 1)))
+
+
+def chung_lu(n, mean_deg, gamma=2.3, seed=0):
+    """Chung-Lu expected-degree graph with power-law weights (exponent gamma)."""
+    return _take(_load().gg_chung_lu(int(n), float(mean_deg), float(gamma), int(seed) & (2**64 - 1)))
+
+
+def chung_lu_weights(n, mean_deg, gamma=2.3):
+    w = np.empty(int(n), dtype=np.float64)
+    if _load().gg_chung_lu_weights(int(n), float(mean_deg), float(gamma), w.ctypes.data) != 0:
+        raise ValueError("bad Chung-Lu parameters")
+    return w
+
+
+def splitmix64_draw(key, i):
+    """i-th output (0-based) of the SplitMix64 stream started at state key."""
+    return int(_load().gg_splitmix64_draw(int(key) & (2**64 - 1), int(i)))
+
+
+def stream_seed(seed, *path):
+    """Derive a deterministic 64-bit seed for a sub-case (e.g. graph g of a
+    batch) from a base seed, using SplitMix64 outputs."""
+    k = int(seed) & (2**64 - 1)
+    for p in path:
+        k = splitmix64_draw(k ^ (int(p) & (2**64 - 1)), 0)
+    return k
+
+
+def log_uniform_int(rng_u01, lo, hi):
+    """Map a uniform draw in [0,1) to an integer log-uniform in [lo, hi]."""
+    x = math.exp(math.log(lo) + rng_u01 * (math.log(hi + 1) - math.log(lo)))
+    return max(lo, min(hi, int(x)))
+
+
+def uniform01(key, i):
+    return (splitmix64_draw(key, i) >> 11) * (1.0 / 9007199254740992.0)
+
+
+# ---------------------------------------------------------------------------
+# Named workloads (shapes of the paper's inputs; see the design notes).
+
+def er_config(n=10_000, mean_deg=10.0, seed=1):
+    """G(n, p = mean_deg / n)."""
+    return erdos_renyi(n, mean_deg / n, seed)
+
+
+def rmat_config(scale, seed, edge_factor=16):
+    return rmat(scale, edge_factor, 0.57, 0.19, 0.19, seed)
+
+
+def batched_config(num_graphs=4096, seed=4, n_lo=100, n_hi=50_000, deg_lo=8.0, deg_hi=32.0,
+                   gamma=2.3, size_scale=1.0):
+    """Per-graph (n, mean degree, generator seed) of the batched workload:
+    n log-uniform in [n_lo, n_hi], mean degree uniform in [deg_lo, deg_hi],
+    Chung-Lu exponent gamma.  size_scale shrinks n for quick tests."""
+    key = stream_seed(seed, 0xBA7C)
+    specs = []
+    for g in range(num_graphs):
+        n = log_uniform_int(uniform01(key, 3 * g), n_lo, n_hi)
+        n = max(2, int(n * size_scale))
+        k = deg_lo + (deg_hi - deg_lo) * uniform01(key, 3 * g + 1)
+        k = min(k, n - 1.0)
+        specs.append((n, k, stream_seed(seed, 0xC1, g)))
+    return specs

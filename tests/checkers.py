@@ -1,0 +1,164 @@
+"""Definition-level verifiers, written from the paper independently of the
+oracle (numpy, non-incremental).  They pin the oracle, and check GPU output at
+sizes the oracle's own run would make slow.
+
+* check_adg: the output of ADG (Algorithm 1) is fixed round by round by its
+  selection rule: with U_l = {v : rho(v) >= l}, deg_U the degree inside
+  G[U_l], |U_l| and cnt = sum of deg_U over U_l, a vertex of U_l is removed in
+  round l exactly when deg_U(v) <= (1 + p/q) * cnt / |U_l| (evaluated as
+  q |U| deg <= (q + p) cnt).  Every degree is recomputed from the graph, so
+  incremental bookkeeping errors (wrong vertices decremented, missed
+  decrements, wrong counts) show up.
+* check_jp: a JP colouring for the total order <rho_ADG, rho_R> is proper and
+  gives every vertex the smallest colour >= 1 not used by its higher-priority
+  neighbours (GetColor in Algorithm 3).
+"""
+import numpy as np
+
+MASK64 = (1 << 64) - 1
+
+
+def splitmix64_first(s):
+    """SplitMix64 (Steele, Lea, Flood 2014), first output from state s."""
+    z = (s + 0x9E3779B97F4A7C15) & MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def fmix32_np(x):
+    """MurmurHash3 32-bit finaliser on a uint32 array."""
+    x = np.asarray(x, dtype=np.uint64) & 0xFFFFFFFF
+    x ^= x >> 16
+    x = (x * 0x85EBCA6B) & 0xFFFFFFFF
+    x ^= x >> 13
+    x = (x * 0xC2B2AE35) & 0xFFFFFFFF
+    x ^= x >> 16
+    return x.astype(np.uint32)
+
+
+def tiebreak_np(seed, n):
+    k = splitmix64_first(int(seed) & MASK64) & 0xFFFFFFFF
+    return fmix32_np(np.arange(n, dtype=np.uint64) ^ np.uint64(k))
+
+
+def priority_keys(rho, seed):
+    rho = np.asarray(rho, dtype=np.uint64)
+    return (rho << np.uint64(32)) | tiebreak_np(seed, rho.size).astype(np.uint64)
+
+
+def _src(row_ptr):
+    n = row_ptr.size - 1
+    return np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
+
+
+def check_csr(row_ptr, col):
+    """Simple undirected graph in CSR: symmetric, no loops, no duplicates."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    n = row_ptr.size - 1
+    assert row_ptr[0] == 0 and row_ptr[-1] == col.size
+    assert np.all(np.diff(row_ptr) >= 0)
+    if col.size == 0:
+        return
+    assert col.min() >= 0 and col.max() < n
+    src = _src(row_ptr)
+    assert not np.any(src == col), "self-loop"
+    fwd = src * n + col
+    assert np.unique(fwd).size == fwd.size, "duplicate entry"
+    assert np.array_equal(np.sort(fwd), np.sort(col * n + src)), "not symmetric"
+
+
+def check_adg(row_ptr, col, p, q, rho, L):
+    """Raise AssertionError unless rho is exactly ADG's output (see module doc).
+    Returns the per-round thresholds' data for further checks."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    rho = np.asarray(rho, dtype=np.int64)
+    n = row_ptr.size - 1
+    if n == 0:
+        assert L == 0
+        return []
+    assert rho.min() >= 1 and rho.max() == L
+    src = _src(row_ptr)
+    rounds = []
+    for l in range(1, L + 1):
+        inU = rho >= l
+        sizeU = int(inU.sum())
+        assert sizeU > 0
+        edge_in = inU[src] & inU[col]
+        degU = np.bincount(src[edge_in], minlength=n)
+        cnt = int(degU[inU].sum())
+        # exact: q*|U|*deg <= (q+p)*cnt ; python ints avoid overflow
+        lhs_scale = q * sizeU
+        rhs = (q + p) * cnt
+        sel = np.array([lhs_scale * int(d) <= rhs for d in degU[inU]]) if sizeU < 4096 else (
+            (degU[inU].astype(object) * lhs_scale) <= rhs)
+        removed = rho[inU] == l
+        assert np.array_equal(sel.astype(bool), removed), "round %d selection mismatch" % l
+        assert removed.any(), "empty round %d" % l
+        rounds.append((sizeU, cnt, degU))
+    return rounds
+
+
+def check_jp(row_ptr, col, rho, seed, color):
+    """Proper, and colour(v) = smallest colour >= 1 not used by pred(v)."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    color = np.asarray(color, dtype=np.int64)
+    n = row_ptr.size - 1
+    if n == 0:
+        return
+    assert color.min() >= 1
+    src = _src(row_ptr)
+    assert not np.any(color[src] == color[col]), "improper colouring"
+    key = priority_keys(rho, seed)
+    pred = key[col] > key[src]  # col is a predecessor of src
+    # pred colours below colour(v), distinct per v: must be exactly colour(v)-1 of them
+    s, c = src[pred], color[col[pred]]
+    low = c < color[s]
+    pairs = np.unique(s[low] * (int(color.max()) + 2) + c[low])
+    have = np.bincount(pairs // (int(color.max()) + 2), minlength=n)
+    assert np.array_equal(have, color - 1), "colour is not the smallest free colour over pred(v)"
+
+
+def pred_count(row_ptr, col, rho, seed):
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    n = row_ptr.size - 1
+    key = priority_keys(rho, seed)
+    src = _src(row_ptr)
+    return np.bincount(src[key[col] > key[src]], minlength=n)
+
+
+def edges_to_csr(n, edges):
+    """Tiny helper: symmetric CSR from an undirected edge list (no generator)."""
+    adj = [set() for _ in range(n)]
+    for u, v in edges:
+        if u != v:
+            adj[u].add(v)
+            adj[v].add(u)
+    rp = np.zeros(n + 1, dtype=np.int64)
+    cols = []
+    for v in range(n):
+        nb = sorted(adj[v])
+        cols.extend(nb)
+        rp[v + 1] = rp[v] + len(nb)
+    return rp, np.array(cols, dtype=np.int32)
+
+
+def brute_degeneracy(n, edges):
+    """max over non-empty vertex subsets S of the minimum degree in G[S]."""
+    nb = [0] * n
+    for u, v in edges:
+        nb[u] |= 1 << v
+        nb[v] |= 1 << u
+    best = 0
+    for S in range(1, 1 << n):
+        mn = None
+        for v in range(n):
+            if S >> v & 1:
+                d = bin(nb[v] & S).count("1")
+                mn = d if mn is None or d < mn else mn
+        best = max(best, mn)
+    return best

@@ -1,0 +1,296 @@
+"""Pins for the CPU oracle: it is checked against what the paper and the
+mathematics fix, never against itself or the GPU path.
+
+* definition-level checks of ADG's selection rule (Algorithm 1) and JP's
+  smallest-free-colour rule (Algorithm 3, GetColor) on every labelled graph
+  with up to 6 vertices and on seeded random graphs;
+* closed forms worked out by hand from Algorithm 1 and 3 (edgeless graph,
+  K_n, star, complete bipartite, path, very large eps = JP-R);
+* exact degeneracy by brute force over vertex subsets (definition in
+  "Degeneracy, Coreness, and Related Concepts");
+* the paper's bounds: round count (proof of the ADG depth lemma), the
+  per-round shrink factor, the partial 2(1+eps)-approximate degeneracy order
+  (ADG approximation lemma) and the colour bound 2(1+eps)d + 1 (JP-ADG colour
+  corollary);
+* published test vectors of the hash building blocks (SplitMix64,
+  MurmurHash3's fmix32) and the bijectivity of the tie-break hash.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from checkers import (brute_degeneracy, check_adg, check_jp, edges_to_csr, fmix32_np, pred_count,
+                      priority_keys, splitmix64_first, tiebreak_np)
+
+EPS = [(0, 1), (1, 100), (1, 10), (1, 2), (1, 1), (10**6, 1)]
+
+
+# ---------------------------------------------------------------- hash pins
+
+def test_splitmix64_published_sequence():
+    # First three outputs of SplitMix64 from state 0 (reference sequence of
+    # Steele, Lea and Flood's generator).
+    expect = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    assert oracle.splitmix64_first(0) == expect[0]
+    assert [graphgen.splitmix64_draw(0, i) for i in range(3)] == expect
+    assert splitmix64_first(0) == expect[0]
+
+
+def test_fmix32_murmur3_vectors():
+    # MurmurHash3_x86_32 of the empty key reduces to fmix32(seed); its
+    # published verification values for seeds 1 and 0xffffffff:
+    assert oracle.fmix32(1) == 0x514E28B7
+    assert oracle.fmix32(0xFFFFFFFF) == 0x81F16F39
+    assert oracle.fmix32(0) == 0
+    assert int(fmix32_np([1])[0]) == 0x514E28B7
+
+
+def _fmix32_inverse(h):
+    # Each step of fmix32 is invertible mod 2^32: xorshift by s is undone by
+    # repeated xorshift, multiplication by an odd constant by its inverse.
+    def unxorshift(x, s):
+        y = x
+        for _ in range(32 // s + 1):
+            y = x ^ (y >> s)
+        return y & 0xFFFFFFFF
+    inv1 = pow(0x85EBCA6B, -1, 1 << 32)
+    inv2 = pow(0xC2B2AE35, -1, 1 << 32)
+    h = unxorshift(h, 16)
+    h = (h * inv2) & 0xFFFFFFFF
+    h = unxorshift(h, 13)
+    h = (h * inv1) & 0xFFFFFFFF
+    return unxorshift(h, 16)
+
+
+def test_tiebreak_is_bijection():
+    rng = np.random.default_rng(7)
+    xs = [0, 1, 2, 0xFFFFFFFF, 0x80000000] + [int(x) for x in rng.integers(0, 2**32, 2000)]
+    for x in xs:
+        assert _fmix32_inverse(oracle.fmix32(x)) == x
+    for seed in [0, 1, 2, 12345678901234567]:
+        n = 5000
+        h = oracle.tiebreak_array(seed, n)
+        assert np.unique(h).size == n
+        assert np.array_equal(h, tiebreak_np(seed, n))
+
+
+# ---------------------------------------------------------------- degeneracy
+
+def test_degeneracy_matches_brute_force():
+    rng = np.random.default_rng(3)
+    for trial in range(120):
+        n = int(rng.integers(1, 10))
+        p = float(rng.uniform(0.1, 0.9))
+        edges = [(u, v) for u in range(n) for v in range(u + 1, n) if rng.random() < p]
+        rp, col = edges_to_csr(n, edges)
+        assert oracle.degeneracy(rp, col) == brute_degeneracy(n, edges), (n, edges)
+
+
+def test_degeneracy_closed_forms():
+    for n in range(1, 9):
+        rp, col = edges_to_csr(n, [(u, v) for u in range(n) for v in range(u + 1, n)])
+        assert oracle.degeneracy(rp, col) == n - 1  # K_n
+    rp, col = edges_to_csr(10, [(i, i + 1) for i in range(9)])
+    assert oracle.degeneracy(rp, col) == 1  # path (a tree)
+    rp, col = edges_to_csr(6, [(i, (i + 1) % 6) for i in range(6)])
+    assert oracle.degeneracy(rp, col) == 2  # cycle
+
+
+# ---------------------------------------------------------------- helpers
+
+def _bounds_hold(rp, col, p, q, rho, L, color, k, seed):
+    n = rp.size - 1
+    d = oracle.degeneracy(rp, col)
+    rounds = check_adg(rp, col, p, q, rho, L)
+    # per-round shrink: |U_{l+1}| (1+eps) < |U_l| unless U_{l+1} is empty
+    sizes = [r[0] for r in rounds] + [0]
+    for a, b in zip(sizes, sizes[1:]):
+        assert b == 0 or b * (q + p) < a * q
+    if n >= 2 and p > 0:
+        assert L <= math.ceil(math.log(n) / math.log1p(p / q) + 1)
+    # partial 2(1+eps)-approximate degeneracy order: neighbours with equal or
+    # higher round, at most 2(1+eps)d
+    src = np.repeat(np.arange(n), np.diff(rp))
+    ge = np.bincount(src[rho[col] >= rho[src]], minlength=n) if n else np.zeros(0)
+    assert np.all(q * ge <= (q + p) * 2 * d)
+    check_jp(rp, col, rho, seed, color)
+    npred = pred_count(rp, col, rho, seed)
+    assert k == (color.max() if n else 0)
+    assert k <= (npred.max() + 1 if n else 0)
+    # JP-ADG colour bound, integer form: k <= floor(2(1+eps)d) + 1
+    assert k <= (q + p) * 2 * d // q + 1
+    deg = np.diff(rp)
+    assert k <= (deg.max() + 1 if n else 0)
+
+
+# ---------------------------------------------------------------- exhaustive small graphs
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 4, 5])
+def test_all_graphs_up_to_5_vertices(n):
+    pairs = [(u, v) for u in range(n) for v in range(u + 1, n)]
+    for mask in range(1 << len(pairs)):
+        edges = [pairs[i] for i in range(len(pairs)) if mask >> i & 1]
+        rp, col = edges_to_csr(n, edges)
+        for (p, q) in EPS:
+            color, k, rho, L, _ = oracle.color_graph(rp, col, p, q, seed=mask)
+            _bounds_hold(rp, col, p, q, rho, L, color, k, mask)
+
+
+def test_all_graphs_with_6_vertices_two_eps():
+    n = 6
+    pairs = [(u, v) for u in range(n) for v in range(u + 1, n)]
+    rng = np.random.default_rng(11)
+    masks = range(1 << len(pairs))
+    for mask in masks:
+        edges = [pairs[i] for i in range(len(pairs)) if mask >> i & 1]
+        rp, col = edges_to_csr(n, edges)
+        p, q = EPS[int(rng.integers(0, len(EPS)))]
+        rho, L, _ = oracle.adg(rp, col, p, q)
+        check_adg(rp, col, p, q, rho, L)
+        color, k = oracle.jp(rp, col, rho, mask)
+        check_jp(rp, col, rho, mask, color)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_graphs_medium(seed):
+    rng = np.random.default_rng(100 + seed)
+    for trial in range(6):
+        n = int(rng.integers(20, 400))
+        kind = trial % 3
+        if kind == 0:
+            rp, col = graphgen.erdos_renyi(n, float(rng.uniform(0.01, 0.2)), seed * 10 + trial)
+        elif kind == 1:
+            rp, col = graphgen.chung_lu(n, float(rng.uniform(2, 12)), 2.3, seed * 10 + trial)
+        else:
+            rp, col = graphgen.rmat(int(np.log2(n)) + 1, 8, 0.57, 0.19, 0.19, seed * 10 + trial)
+        for (p, q) in [(0, 1), (1, 100), (1, 10), (1, 2)]:
+            color, k, rho, L, st = oracle.color_graph(rp, col, p, q, seed=trial)
+            _bounds_hold(rp, col, p, q, rho, L, color, k, trial)
+            assert st["sum_active"] >= rp.size - 1
+
+
+# ---------------------------------------------------------------- closed forms
+
+def test_edgeless():
+    for n in [1, 2, 7, 100]:
+        rp, col = edges_to_csr(n, [])
+        for (p, q) in EPS:
+            color, k, rho, L, _ = oracle.color_graph(rp, col, p, q, 5)
+            assert L == 1 and np.all(rho == 1) and np.all(color == 1) and k == 1
+
+
+def test_empty_graph():
+    rp = np.zeros(1, dtype=np.int64)
+    col = np.zeros(0, dtype=np.int32)
+    color, k, rho, L, _ = oracle.color_graph(rp, col, 1, 10, 1)
+    assert L == 0 and k == 0 and color.size == 0
+
+
+def test_complete_graph_colours_by_hash_rank():
+    for n in [2, 3, 5, 17, 64]:
+        rp, col = edges_to_csr(n, list(itertools.combinations(range(n), 2)))
+        for (p, q) in EPS:
+            for seed in [0, 9]:
+                color, k, rho, L, _ = oracle.color_graph(rp, col, p, q, seed)
+                assert L == 1 and np.all(rho == 1)
+                h = tiebreak_np(seed, n).astype(np.int64)
+                rank = np.array([int((h > h[v]).sum()) for v in range(n)])
+                assert np.array_equal(color, rank + 1) and k == n
+
+
+def test_star():
+    for k in [2, 3, 10, 50]:
+        n = k + 1
+        rp, col = edges_to_csr(n, [(0, i) for i in range(1, n)])
+        for (p, q) in EPS:
+            color, nc, rho, L, _ = oracle.color_graph(rp, col, p, q, 3)
+            if q * k > q + 2 * p:  # k > 1 + 2 eps: leaves first, centre in round 2
+                assert L == 2 and rho[0] == 2 and np.all(rho[1:] == 1)
+                assert color[0] == 1 and np.all(color[1:] == 2)
+            else:
+                assert L == 1 and np.all(rho == 1)
+            assert nc == 2
+
+
+def test_complete_bipartite():
+    for a, b in [(1, 3), (2, 5), (3, 4), (4, 9), (5, 5)]:
+        n = a + b
+        rp, col = edges_to_csr(n, [(i, a + j) for i in range(a) for j in range(b)])
+        for (p, q) in EPS:
+            color, nc, rho, L, _ = oracle.color_graph(rp, col, p, q, 8)
+            if q * b > a * (q + 2 * p):  # b > a(1+2eps): side B peeled first
+                assert L == 2 and np.all(rho[:a] == 2) and np.all(rho[a:] == 1)
+                assert np.all(color[:a] == 1) and np.all(color[a:] == 2)
+            else:
+                assert L == 1
+                # JP-R on K_{a,b}: the side holding the top-priority vertex gets 1
+                top = int(np.argmax(tiebreak_np(8, n)))
+                side = slice(0, a) if top < a else slice(a, n)
+                assert np.all(color[side] == 1)
+            assert nc == 2
+
+
+def test_path_many_rounds():
+    for n in [2, 3, 4, 9, 10, 31, 64]:
+        rp, col = edges_to_csr(n, [(i, i + 1) for i in range(n - 1)])
+        p, q = 1, 10 * n  # eps < 1/(n-1): only the two ends go each round
+        color, nc, rho, L, _ = oracle.color_graph(rp, col, p, q, 4)
+        v = np.arange(n)
+        assert np.array_equal(rho, np.minimum(v + 1, n - v))
+        assert L == (n + 1) // 2
+        assert nc == (2 if n >= 2 else 1)
+        if n % 2 == 1:
+            c = (n - 1) // 2
+            assert np.array_equal(color, 1 + (np.abs(v - c) % 2))
+
+
+def test_huge_eps_is_jp_random():
+    # eps >= n * Delta forces a single round, so JP-ADG = JP-R: greedy by
+    # decreasing hash (the eps -> infinity limit of the trade-off discussion).
+    rng = np.random.default_rng(5)
+    for trial in range(20):
+        n = int(rng.integers(2, 60))
+        rp, col = graphgen.erdos_renyi(n, 0.3, trial)
+        if col.size == 0:
+            continue
+        delta = int(np.diff(rp).max())
+        color, nc, rho, L, _ = oracle.color_graph(rp, col, n * delta, 1, trial)
+        assert L == 1
+        h = tiebreak_np(trial, n)
+        order = np.argsort(-h.astype(np.int64), kind="stable")
+        want = np.zeros(n, dtype=np.int64)
+        for v in order:
+            used = {int(want[u]) for u in col[rp[v]:rp[v + 1]] if want[u] > 0}
+            c = 1
+            while c in used:
+                c += 1
+            want[v] = c
+        assert np.array_equal(color, want)
+
+
+def test_adjacency_order_invariance():
+    rng = np.random.default_rng(9)
+    rp, col = graphgen.chung_lu(3000, 12, 2.3, 77)
+    col2 = col.copy()
+    for v in range(rp.size - 1):
+        seg = col2[rp[v]:rp[v + 1]]
+        rng.shuffle(seg)
+    a = oracle.color_graph(rp, col, 1, 10, 3)
+    b = oracle.color_graph(rp, col2, 1, 10, 3)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2]) and a[1] == b[1] and a[3] == b[3]
+
+
+def test_pred_counts_match_definition():
+    rp, col = graphgen.rmat(10, 8, 0.57, 0.19, 0.19, 1)
+    rho, L, _ = oracle.adg(rp, col, 1, 10)
+    assert np.array_equal(oracle.pred_counts(rp, col, rho, 6), pred_count(rp, col, rho, 6))
+
+
+def test_priority_key_orientation():
+    # higher round => higher priority regardless of hash
+    k = priority_keys(np.array([1, 2]), 0)
+    assert k[1] > k[0]
