@@ -1,0 +1,134 @@
+/*
+ * adg.h -- C ABI of libadg_hip.so: approximate degeneracy ordering (ADG) and
+ * Jones-Plassmann colouring under the ADG order (JP-ADG) on AMD MI355X
+ * (gfx950).
+ *
+ * Method: Besta et al., "High-Performance Parallel Graph Coloring with Strong
+ * Guarantees on Work, Depth, and Quality" (SC 2020, arXiv 2008.11321).
+ *   - adg_order:   ADG, Algorithm 1 ("Parallel Approximate Degeneracy
+ *                  Ordering").
+ *   - jp_color:    JP, Algorithm 3, with priority rho = <rho_ADG, rho_R>
+ *                  ("Graph Coloring by Color Scheduling (JP-ADG)").
+ *   - color_graph: JP-ADG end to end, with JP's Part 1 (the DAG G_rho: pred /
+ *                  succ sets and |pred|) fused into ADG's UPDATE, the
+ *                  "Combining JP and ADG" optimisation of the section
+ *                  "Optimizations and Implementation".
+ *   - color_graph_batched: many independent graphs in one call.
+ *
+ * Conventions shared by every entry point:
+ *   - Graphs are simple and undirected (symmetric adjacency, no self-loops,
+ *     no duplicate entries) in CSR: row_ptr[n+1] (int64, row_ptr[0] = 0,
+ *     non-decreasing, row_ptr[n] = nnz) and col_idx[nnz] (int32 in [0, n)).
+ *     Vertices are numbered 0..n-1.  Row order inside a row is free: results
+ *     do not depend on it.  Preconditions are not checked by the compute
+ *     calls; adg_validate_csr checks them.
+ *   - eps = eps_num / eps_den with eps_num >= 0, eps_den >= 1.  A vertex u
+ *     is removed in an ADG round when D[u] <= (1 + eps) * avg, evaluated
+ *     exactly in integers (no floating point anywhere).
+ *   - Rounds are numbered 1..L.  A higher round means a higher JP priority
+ *     (peeled later, coloured earlier).  Ties inside a round are broken by
+ *     rho_R(v) = fmix32(v XOR k), k = low 32 bits of the first SplitMix64
+ *     output from state `seed` (larger wins); fmix32 is the MurmurHash3
+ *     finaliser, a bijection, so the order is total.
+ *   - Colours are 1-based; num_colors = max colour (0 for an empty graph).
+ *   - Every array argument is a DEVICE pointer owned by the caller; the
+ *     library never allocates device memory.  Scratch space is the
+ *     caller-provided workspace of at least *_workspace_bytes() bytes,
+ *     256-byte aligned; its contents on entry are ignored.
+ *   - Calls are issued on `stream` (a hipStream_t; NULL = default stream).
+ *     adg_order and color_graph wait on the stream a few times to learn when
+ *     the round loop has ended (the number of rounds is data dependent), so
+ *     they return only after the ADG phase has finished on the device; the
+ *     JP phase and jp_color are fully asynchronous.  Outputs are valid once
+ *     the stream is synchronised.
+ *   - Return value: ADG_OK (0) or a negative ADG_ERR_* code; no exception
+ *     crosses the ABI.  adg_error_string() names a code.
+ */
+#ifndef ADG_H_
+#define ADG_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ADG_OK = 0,
+  ADG_ERR_ARG = -1,         /* null pointer, negative size, bad eps, n >= 2^31 */
+  ADG_ERR_WORKSPACE = -2,   /* workspace missing, misaligned or too small */
+  ADG_ERR_HIP = -3,         /* a HIP runtime call failed */
+  ADG_ERR_INTERNAL = -4,    /* round-count watchdog tripped or device-side check failed */
+  ADG_ERR_UNSUPPORTED = -5  /* input outside the supported range (see entry point) */
+};
+
+/* CSR view of one graph; all pointers are device pointers. */
+typedef struct adg_csr {
+  int64_t n;               /* number of vertices, 0 <= n < 2^31 */
+  int64_t nnz;             /* number of directed entries = 2m */
+  const int64_t* row_ptr;  /* [n+1] */
+  const int32_t* col_idx;  /* [nnz] */
+} adg_csr_t;
+
+/* Counters of the last call on a workspace, read back by adg_get_stats. */
+typedef struct adg_stats {
+  int64_t num_rounds;      /* L */
+  int64_t num_colors;      /* max colour (0 if JP did not run) */
+  int64_t sum_active;      /* sum over rounds of |U_l| */
+  int64_t cut_edges;       /* decrements that hit a vertex staying in U */
+  int64_t frontier;        /* vertices without predecessors in G_rho */
+  int64_t overflow;        /* vertices whose colour needed the wide path */
+  int64_t error;           /* device-side error flag (0 = none) */
+} adg_stats_t;
+
+/* Workspace size in bytes for adg_order / jp_color / color_graph on a graph
+ * with n vertices and nnz entries.  Returns 0 for invalid sizes. */
+size_t adg_workspace_bytes(int64_t n, int64_t nnz);
+
+/* ADG (Algorithm 1).  Writes round_out[v] in 1..L for every vertex and L to
+ * num_rounds_out[0] (device int32).  Each round l: |U| and the degree sum
+ * over U give the average; R = {u in U : D[u] <= (1+eps) avg}; every v in R
+ * gets round l; D[w] is decremented once for every edge between R and U \ R.
+ * Errors: ADG_ERR_ARG, ADG_ERR_WORKSPACE, ADG_ERR_HIP, ADG_ERR_INTERNAL
+ * (round count above n or above ceil(log n / log(1+eps)) + 2). */
+int adg_order(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, int32_t* round_out,
+              int32_t* num_rounds_out, void* workspace, size_t ws_bytes, void* stream);
+
+/* JP (Algorithm 3) under rho = <round[v], rho_R(v)>.  round[] may be any
+ * positive int32 ranking (normally adg_order's output).  Writes
+ * color_out[v] >= 1 and num_colors_out[0] (device int32).  The colouring
+ * equals sequential greedy colouring in decreasing priority order: each v
+ * gets the smallest colour not used by its higher-priority neighbours.
+ * Errors: ADG_ERR_ARG, ADG_ERR_WORKSPACE, ADG_ERR_HIP, ADG_ERR_UNSUPPORTED
+ * (a vertex with 2^24 or more higher-priority neighbours). */
+int jp_color(const adg_csr_t* g, const int32_t* round, uint64_t seed, int32_t* color_out,
+             int32_t* num_colors_out, void* workspace, size_t ws_bytes, void* stream);
+
+/* JP-ADG: adg_order then jp_color, with JP Part 1 fused into ADG's update.
+ * round_out and num_rounds_out may be NULL (then ADG's rounds are kept in the
+ * workspace only).  Results are identical to adg_order followed by jp_color.
+ * Errors: as adg_order and jp_color. */
+int color_graph(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_t seed,
+                int32_t* color_out, int32_t* round_out, int32_t* num_colors_out,
+                int32_t* num_rounds_out, void* workspace, size_t ws_bytes, void* stream);
+
+/* Copy the counters of the last adg_order / jp_color / color_graph call on
+ * this workspace to host memory.  Synchronises `stream`. */
+int adg_get_stats(const void* workspace, size_t ws_bytes, adg_stats_t* host_out, void* stream);
+
+/* Check that g is a simple undirected graph in CSR form: row_ptr monotone
+ * with row_ptr[0] = 0 and row_ptr[n] = nnz, col_idx in range, no self-loop,
+ * no duplicate entry, symmetric.  Needs rows sorted by neighbour id to check
+ * duplicates and symmetry (binary search).  Returns ADG_OK, ADG_ERR_ARG if a
+ * check fails, or another error code.  Synchronises `stream`. */
+int adg_validate_csr(const adg_csr_t* g, void* workspace, size_t ws_bytes, void* stream);
+
+/* Human-readable name of an ADG_* code (static string). */
+const char* adg_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADG_H_ */

@@ -1,0 +1,57 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+that include/adg.h declares, and rejects bad arguments before touching the
+device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2008_11321_amd as pkg
+
+HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "adg.h")
+
+
+def declared_functions():
+    txt = open(HDR).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", txt, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "return")))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for f in ["adg_workspace_bytes", "adg_order", "jp_color", "color_graph", "adg_get_stats", "adg_validate_csr",
+              "adg_error_string"]:
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = pkg.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_workspace_size_and_errors_without_gpu():
+    L = pkg.lib()
+    assert L.adg_workspace_bytes(-1, 0) == 0
+    small = L.adg_workspace_bytes(10, 20)
+    big = L.adg_workspace_bytes(10_000, 100_000)
+    assert 0 < small < big
+    assert L.adg_error_string(0) == b"ok"
+    assert L.adg_error_string(-1) == b"invalid argument"
+    # null graph pointer and bad eps are rejected on the host
+    assert L.adg_order(None, 1, 10, None, None, None, 0, None) == -1
+    csr = pkg._Csr(5, 0, 0, 0)
+    assert L.adg_order(ctypes.byref(csr), -1, 10, None, None, None, 0, None) == -1
+    assert L.adg_order(ctypes.byref(csr), 1, 0, None, None, None, 0, None) == -1
+    assert L.color_graph(ctypes.byref(csr), 1, 10, 0, None, None, None, None, None, 0, None) == -1
+
+
+def test_no_cpu_fallback():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    g = None
+    with pytest.raises(RuntimeError):
+        pkg.Graph([0, 0], [])

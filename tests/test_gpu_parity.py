@@ -1,0 +1,165 @@
+"""Parity of the HIP path with the CPU oracle (bit-exact: rounds, colours,
+round count, colour count), through the C ABI.  GPU only."""
+import itertools
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from checkers import check_jp, edges_to_csr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import paper_2008_11321_amd as pkg
+    import torch
+    assert torch.cuda.is_available()
+    return pkg
+
+
+def _gpu_color(pkg, rp, col, p, q, seed):
+    import torch
+    g = pkg.Graph(rp, col)
+    ws = torch.empty(pkg.workspace_bytes(g.n, g.nnz), dtype=torch.uint8, device="cuda")
+    color, nc, rnd, nr = pkg.color_graph(g, p, q, seed, workspace=ws)
+    torch.cuda.synchronize()
+    st = pkg.get_stats(ws)
+    return color.cpu().numpy(), int(nc.item()), rnd.cpu().numpy(), int(nr.item()), st
+
+
+def _compare(pkg, rp, col, p, q, seed, label=""):
+    print("case", label, "n", rp.size - 1, "nnz", col.size, "eps", p, q, "seed", seed, flush=True)
+    color, k, rho, L, st = oracle.color_graph(rp, col, p, q, seed)
+    gc, gk, gr, gL, gst = _gpu_color(pkg, rp, col, p, q, seed)
+    assert gL == L, (label, gL, L)
+    assert np.array_equal(gr, rho), label
+    assert gk == k, (label, gk, k)
+    assert np.array_equal(gc, color), label
+    assert gst["sum_active"] == st["sum_active"]
+    assert gst["cut_edges"] == st["cut_edges"]
+    assert gst["error"] == 0
+    return gst
+
+
+SMALL_CASES = [
+    ("K1", 1, []),
+    ("K2", 2, [(0, 1)]),
+    ("edgeless7", 7, []),
+    ("K17", 17, list(itertools.combinations(range(17), 2))),
+    ("star50", 51, [(0, i) for i in range(1, 51)]),
+    ("K4_9", 13, [(i, 4 + j) for i in range(4) for j in range(9)]),
+    ("path31", 31, [(i, i + 1) for i in range(30)]),
+    ("path64", 64, [(i, i + 1) for i in range(63)]),
+    ("two_triangles_isolated", 9, [(0, 1), (1, 2), (0, 2), (5, 6), (6, 7), (5, 7)]),
+]
+
+
+@pytest.mark.parametrize("name,n,edges", SMALL_CASES)
+@pytest.mark.parametrize("eps", [(0, 1), (1, 100), (1, 10), (1, 2), (10**6, 1)])
+def test_small_closed_form_graphs(dev, name, n, edges, eps):
+    rp, col = edges_to_csr(n, edges)
+    _compare(dev, rp, col, eps[0], eps[1], 3, name)
+
+
+def test_path_many_rounds(dev):
+    n = 257
+    rp, col = edges_to_csr(n, [(i, i + 1) for i in range(n - 1)])
+    _compare(dev, rp, col, 1, 10 * n, 4, "path257")  # 129 rounds
+
+
+def test_empty_graph(dev):
+    import torch
+    g = dev.Graph(np.zeros(1, np.int64), np.zeros(0, np.int32))
+    color, nc, rnd, nr = dev.color_graph(g, 1, 10, 1)
+    torch.cuda.synchronize()
+    assert int(nc.item()) == 0 and int(nr.item()) == 0 and color.numel() == 0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_small_graphs(dev, seed):
+    rng = np.random.default_rng(seed)
+    for trial in range(5):
+        n = int(rng.integers(50, 3000))
+        kind = trial % 3
+        if kind == 0:
+            rp, col = graphgen.erdos_renyi(n, float(rng.uniform(0.002, 0.05)), seed * 10 + trial)
+        elif kind == 1:
+            rp, col = graphgen.chung_lu(n, float(rng.uniform(2, 30)), 2.3, seed * 10 + trial)
+        else:
+            rp, col = graphgen.rmat(int(np.log2(n)) + 1, 16, 0.57, 0.19, 0.19, seed * 10 + trial)
+        for (p, q) in [(0, 1), (1, 100), (1, 10), (1, 2)]:
+            _compare(dev, rp, col, p, q, trial, "rand%d/%d" % (seed, trial))
+
+
+def test_er_config_bit_exact(dev):
+    rp, col = graphgen.er_config(10_000, 10.0, seed=1)
+    _compare(dev, rp, col, 1, 100, 1, "ER n=1e4 eps=0.01 seed=1")
+
+
+@pytest.mark.parametrize("scale,eps", [(14, (1, 100)), (16, (1, 10)), (18, (1, 2))])
+def test_rmat_mid(dev, scale, eps):
+    rp, col = graphgen.rmat_config(scale, seed=2)
+    _compare(dev, rp, col, eps[0], eps[1], 2, "rmat%d" % scale)
+
+
+def test_chung_lu_hubs(dev):
+    rp, col = graphgen.chung_lu(200_000, 32, 2.3, seed=9)
+    _compare(dev, rp, col, 1, 10, 4, "chung-lu 2e5")
+
+
+def test_rmat22_config_bit_exact(dev):
+    rp, col = graphgen.rmat_config(22, seed=2)
+    st = _compare(dev, rp, col, 1, 10, 2, "rmat22 eps=0.1 seed=2")
+    print("stats", st)
+
+
+def test_adg_order_and_jp_color_separately(dev):
+    import torch
+    rp, col = graphgen.rmat_config(15, seed=5)
+    rho, L, _ = oracle.adg(rp, col, 1, 10)
+    g = dev.Graph(rp, col)
+    rnd, nr = dev.adg_order(g, 1, 10)
+    torch.cuda.synchronize()
+    assert int(nr.item()) == L and np.array_equal(rnd.cpu().numpy(), rho)
+    color, k = oracle.jp(rp, col, rho, 11)
+    gc, gk = dev.jp_color(g, rnd, 11)
+    torch.cuda.synchronize()
+    assert int(gk.item()) == k and np.array_equal(gc.cpu().numpy(), color)
+    # JP on an arbitrary ranking (all equal = JP-R; and degree ranking = JP-LF)
+    for ranking in [np.ones(rp.size - 1, np.int32), np.diff(rp).astype(np.int32) + 1]:
+        color, k = oracle.jp(rp, col, ranking, 12)
+        gc, gk = dev.jp_color(g, torch.from_numpy(ranking).cuda(), 12)
+        torch.cuda.synchronize()
+        assert int(gk.item()) == k and np.array_equal(gc.cpu().numpy(), color)
+        check_jp(rp, col, ranking, 12, gc.cpu().numpy())
+
+
+def test_repeatable(dev):
+    import torch
+    rp, col = graphgen.rmat_config(17, seed=7)
+    outs = [_gpu_color(dev, rp, col, 1, 10, 7) for _ in range(3)]
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[2], outs[0][2])
+
+
+def test_adjacency_order_does_not_matter(dev):
+    rp, col = graphgen.chung_lu(20_000, 16, 2.3, seed=3)
+    rng = np.random.default_rng(0)
+    col2 = col.copy()
+    for v in range(rp.size - 1):
+        seg = col2[rp[v]:rp[v + 1]]
+        rng.shuffle(seg)
+    a = _gpu_color(dev, rp, col, 1, 10, 5)
+    b = _gpu_color(dev, rp, col2, 1, 10, 5)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
+
+
+def test_validate_csr(dev):
+    rp, col = graphgen.rmat_config(12, seed=1)
+    assert dev.validate_csr(dev.Graph(rp, col))
+    bad = col.copy()
+    bad[0] = 0  # vertex 0 lists itself or breaks symmetry
+    assert not dev.validate_csr(dev.Graph(rp, bad))
