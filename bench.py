@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark: edges coloured per second by JP-ADG (ADG + JP) on one MI355X.
+
+Default workload: R-MAT scale 22, edge factor 16, (a, b, c) = (0.57, 0.19,
+0.19), symmetrised and deduplicated, eps = 1/10, seed 2 -- the single-graph
+configuration the headline metric is quoted on.  One step = one color_graph
+call (all of ADG and JP) on the graph already resident in HBM.
+
+Prints one JSON line.  Extra fields:
+  roofline      the dominant kernel's algorithmic bytes per launch over its
+                average launch time, measured with HIP events on the launch
+                stream during the timed steps, against the 8 TB/s HBM peak;
+  cpu_baseline  the CPU oracle (serial C) on the same graph, one run.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "edges colored/sec (ADG+JP) + HBM GB/s; batched/served vs plain per-graph"
+
+WORKLOADS = {
+    "rmat22": dict(kind="rmat", scale=22, edge_factor=16, eps=(1, 10), seed=2),
+    "rmat26": dict(kind="rmat", scale=26, edge_factor=16, eps=(1, 10), seed=3),
+    "rmat26_e001": dict(kind="rmat", scale=26, edge_factor=16, eps=(1, 100), seed=3),
+    "rmat26_e05": dict(kind="rmat", scale=26, edge_factor=16, eps=(1, 2), seed=3),
+    "er": dict(kind="er", n=10_000, mean_deg=10.0, eps=(1, 100), seed=1),
+}
+
+
+def make_graph(w):
+    import graphgen
+    if w["kind"] == "rmat":
+        return graphgen.rmat_config(w["scale"], seed=w["seed"], edge_factor=w["edge_factor"])
+    return graphgen.er_config(w["n"], w["mean_deg"], seed=w["seed"])
+
+
+def algorithmic_bytes(cls, n, nnz, st):
+    """Bytes the method itself must move in one step, per kernel class.
+    update: per vertex the R-list entry (4), its row_ptr pair (16), |pred| and
+      the JP word (12); per adjacency entry the neighbour id (4), its status
+      byte (1) and the partitioned copy (4); per cut edge a 4-byte D
+      read-modify-write (8).
+    jp: per vertex the row_ptr pair (16), |pred| (4), the colour write (4) and
+      a queue entry (4); per successor edge (m of them) the partitioned
+      neighbour id (4) and the 8-byte word read-modify-write (16)."""
+    m = nnz // 2
+    if cls == "update":
+        return 32 * n + 9 * nnz + 8 * st["cut_edges"]
+    if cls == "jp":
+        return 28 * n + 20 * m
+    return None
+
+
+def source_digest():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2008_11321_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh).get("%s/%s" % (kernel, workload))
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_digest") != source_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(rp, col, eps, seed, m):
+    import oracle
+    t0 = time.perf_counter()
+    oracle.color_graph(rp, col, eps[0], eps[1], seed)
+    dt = time.perf_counter() - t0
+    return {"value": m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": "whole graph, one serial run of the C oracle (ADG then greedy JP), %.2f s" % dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--breakdown", action="store_true", help="print per-kernel-class times to stderr")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2008_11321_amd as adg
+
+    w = WORKLOADS[args.workload]
+    t0 = time.time()
+    rp, col = make_graph(w)
+    gen_s = time.time() - t0
+    n, nnz = rp.size - 1, col.size
+    m = nnz // 2
+    print("workload %s: n=%d nnz=%d (generated in %.1f s)" % (args.workload, n, nnz, gen_s), file=sys.stderr,
+          flush=True)
+    g = adg.Graph(rp, col, device="cuda:0")
+    ws = torch.empty(adg.workspace_bytes(n, nnz), dtype=torch.uint8, device="cuda:0")
+    out = (torch.empty(n, dtype=torch.int32, device="cuda:0"), torch.empty(n, dtype=torch.int32, device="cuda:0"),
+           torch.zeros(1, dtype=torch.int32, device="cuda:0"), torch.zeros(1, dtype=torch.int32, device="cuda:0"))
+    p, q = w["eps"]
+    seed = w["seed"]
+
+    def step():
+        adg.color_graph(g, p, q, seed, workspace=ws, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    st = adg.get_stats(ws)
+    adg.profile_read()  # drop anything recorded so far
+    adg.profile_enable(["update", "jp", "jp_narrow"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    adg.profile_enable([])
+    prof = adg.profile_read()
+    st = adg.get_stats(ws)
+    ms_per_step = dt * 1000 / args.steps
+    value = m / (dt / args.steps)
+
+    # dominant kernel class: largest share of the timed region.  JP runs as
+    # single-block steps (jp_narrow) and grid-wide steps (jp); its algorithmic
+    # bytes are charged to the two together.
+    jp_ms = prof.get("jp", (0, 0))[0] + prof.get("jp_narrow", (0, 0))[0]
+    jp_launches = prof.get("jp", (0, 0))[1] + prof.get("jp_narrow", (0, 0))[1]
+    upd_ms, upd_launches = prof.get("update", (0.0, 0))
+    if jp_ms >= upd_ms:
+        dom, tot_ms, launches = "jp", jp_ms, jp_launches
+    else:
+        dom, tot_ms, launches = "update", upd_ms, upd_launches
+    per_launch_ms = tot_ms / launches
+    launches_per_step = launches / args.steps
+    step_bytes = algorithmic_bytes(dom, n, nnz, st)
+    bytes_per_launch = step_bytes / launches_per_step
+    achieved = bytes_per_launch / (per_launch_ms * 1e-3) / 1e9
+    kname = "k_jp_narrow+k_jp_grid" if dom == "jp" else "k_update"
+    traffic = measured_traffic(kname, args.workload)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
+                "avg_launch_ms": round(per_launch_ms, 4), "launches_per_step": launches_per_step,
+                "algorithmic_bytes_per_launch": int(bytes_per_launch),
+                "phase_ms_per_step": {"update": round(upd_ms / args.steps, 3), "jp": round(jp_ms / args.steps, 3)}}
+    if args.breakdown:
+        adg.profile_enable(adg.KERNEL_CLASSES)
+        step()
+        torch.cuda.synchronize()
+        adg.profile_enable([])
+        for k, (ms, cnt) in sorted(adg.profile_read().items(), key=lambda kv: -kv[1][0]):
+            print("  %-8s %8.3f ms  %4d launches" % (k, ms, cnt), file=sys.stderr)
+        print("  stats", st, file=sys.stderr)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(rp, col, w["eps"], seed, m)
+
+    cfg = {"workload": args.workload, "graph": w["kind"], "n": n, "nnz": nnz, "m": m, "eps": "%d/%d" % (p, q),
+           "seed": seed, "rounds": st["num_rounds"], "colors": st["num_colors"]}
+    if w["kind"] == "rmat":
+        cfg.update(scale=w["scale"], edge_factor=w["edge_factor"], abcd=[0.57, 0.19, 0.19, 0.05])
+    rec = {"metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int32", "data": "synthetic", "config": cfg, "roofline": roofline,
+           "cpu_baseline": cpu}
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -77,8 +77,8 @@ typedef struct adg_stats {
   int64_t num_colors;      /* max colour (0 if JP did not run) */
   int64_t sum_active;      /* sum over rounds of |U_l| */
   int64_t cut_edges;       /* decrements that hit a vertex staying in U */
-  int64_t frontier;        /* vertices without predecessors in G_rho */
-  int64_t overflow;        /* vertices whose colour needed the wide path */
+  int64_t frontier;        /* vertices that started a JP level (all preds done) */
+  int64_t jp_levels;       /* JP levels processed, summed over rounds */
   int64_t error;           /* device-side error flag (0 = none) */
 } adg_stats_t;
 
@@ -123,6 +123,24 @@ int adg_get_stats(const void* workspace, size_t ws_bytes, adg_stats_t* host_out,
  * duplicates and symmetry (binary search).  Returns ADG_OK, ADG_ERR_ARG if a
  * check fails, or another error code.  Synchronises `stream`. */
 int adg_validate_csr(const adg_csr_t* g, void* workspace, size_t ws_bytes, void* stream);
+
+/* Optional timing of the library's own kernels, for measurement tools.
+ * adg_profile_enable(mask) makes every later launch of a kernel class whose
+ * bit is set in `mask` (classes: 0 init, 1 stats, 2 count, 3 scan,
+ * 4 scatter, 5 update, 6 part1, 7 jp_prep, 8 jp (grid-wide JP steps),
+ * 9 finish, 10 batched, 11 jp_narrow (single-block JP steps))
+ * record a pair of HIP events on its launch stream; 0 disables it.
+ * adg_profile_read waits for the recorded events, adds up the elapsed time
+ * and launch count per class into *out and forgets the records.  Process-wide,
+ * guarded by a mutex. */
+#define ADG_PROFILE_CLASSES 16
+typedef struct adg_profile {
+  double ms[ADG_PROFILE_CLASSES];
+  int64_t launches[ADG_PROFILE_CLASSES];
+} adg_profile_t;
+int adg_profile_enable(uint32_t class_mask);
+int adg_profile_read(adg_profile_t* out);
+const char* adg_kernel_class_name(int cls);
 
 /* Human-readable name of an ADG_* code (static string). */
 const char* adg_error_string(int code);

@@ -17,7 +17,8 @@ from . import _build
 
 __all__ = [
     "AdgError", "lib", "workspace_bytes", "adg_order", "jp_color", "color_graph", "color_graph_batched",
-    "batched_workspace_bytes", "get_stats", "validate_csr", "error_string", "Graph",
+    "batched_workspace_bytes", "get_stats", "validate_csr", "error_string", "Graph", "profile_enable",
+    "profile_read",
 ]
 
 ADG_OK = 0
@@ -38,8 +39,15 @@ class _Csr(ctypes.Structure):
 
 class _Stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in
-                ("num_rounds", "num_colors", "sum_active", "cut_edges", "frontier", "overflow", "error")]
+                ("num_rounds", "num_colors", "sum_active", "cut_edges", "frontier", "jp_levels", "error")]
 
+
+class _Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 16), ("launches", ctypes.c_int64 * 16)]
+
+
+KERNEL_CLASSES = ["init", "stats", "count", "scan", "scatter", "update", "part1", "jp_prep", "jp", "finish",
+                  "batched", "jp_narrow"]
 
 _lib = None
 
@@ -68,6 +76,12 @@ def lib():
     L.adg_validate_csr.argtypes = [P(_Csr), vp, sz, vp]
     L.adg_error_string.restype = ctypes.c_char_p
     L.adg_error_string.argtypes = [ctypes.c_int]
+    L.adg_profile_enable.restype = ctypes.c_int
+    L.adg_profile_enable.argtypes = [ctypes.c_uint32]
+    L.adg_profile_read.restype = ctypes.c_int
+    L.adg_profile_read.argtypes = [P(_Profile)]
+    L.adg_kernel_class_name.restype = ctypes.c_char_p
+    L.adg_kernel_class_name.argtypes = [ctypes.c_int]
     if hasattr(L, "color_graph_batched"):
         L.adg_batched_workspace_bytes.restype = sz
         L.adg_batched_workspace_bytes.argtypes = [i32, i64, i64, i64]
@@ -216,3 +230,20 @@ def batched_workspace_bytes(num_graphs, total_n, total_nnz, max_n):
 def color_graph_batched(*args, **kwargs):
     from .batched import color_graph_batched as f
     return f(*args, **kwargs)
+
+
+def profile_enable(classes):
+    """Time every later launch of the named kernel classes with HIP events on
+    their launch stream (see adg_profile_enable)."""
+    mask = 0
+    for c in classes:
+        mask |= 1 << KERNEL_CLASSES.index(c)
+    _check(lib().adg_profile_enable(mask), "adg_profile_enable")
+
+
+def profile_read():
+    """{class: (total_ms, launches)} for the launches recorded since the last read."""
+    pr = _Profile()
+    _check(lib().adg_profile_read(ctypes.byref(pr)), "adg_profile_read")
+    return {KERNEL_CLASSES[i]: (pr.ms[i], int(pr.launches[i])) for i in range(len(KERNEL_CLASSES))
+            if pr.launches[i]}

@@ -77,7 +77,7 @@ constexpr uint64_t JP_MASK = (uint64_t(1) << JP_MASK_BITS) - 1;
 constexpr uint64_t JP_ONE = uint64_t(1) << JP_MASK_BITS;
 constexpr int64_t JP_MAX_PRED = (int64_t(1) << (64 - JP_MASK_BITS)) - 1;
 
-__device__ __forceinline__ uint64_t agent_load_u64(const uint64_t* p) {
+__device__ __forceinline__ unsigned long long agent_load_u64(const unsigned long long* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ int agent_load_i32(const int* p) {
@@ -89,7 +89,20 @@ __device__ __forceinline__ unsigned agent_load_u32(const unsigned* p) {
 __device__ __forceinline__ void agent_store_i32(int* p, int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
-__device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+__device__ __forceinline__ void agent_store_u64(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Ordering point for the JP worklist: wait until every memory operation this
+// wavefront has issued has completed, and keep the compiler from moving memory
+// accesses across the point.  All data that JP wavefronts exchange is accessed
+// with device-coherent atomics (read-modify-writes, and loads/stores at agent
+// scope), which the hardware performs at the device's coherence point; a
+// completed one is visible to every later device-coherent access.  Waiting for
+// completion therefore orders a wavefront's own exchanges (e.g. a colour bit
+// before the count decrement that releases a successor) without the agent-scope
+// release fence, whose whole-L2 write-back costs ~100 us per fence when many
+// wavefronts issue them.
+__device__ __forceinline__ void order_point() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 }  // namespace adg
