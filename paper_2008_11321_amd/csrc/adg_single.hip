@@ -55,7 +55,7 @@ constexpr int FB_CAP = 2048;            // per-block staging of level lists (LDS
 constexpr int JP_SMALL = 32;            // lane-per-vertex successor loops
 constexpr int JP_UNROLL = 4;
 constexpr int JP_CHUNK = WAVE * JP_UNROLL;   // successors per wavefront step / fan-out chunk
-constexpr int PUSH_BIG = 16 * JP_CHUNK;      // push ranges longer than this are chunked
+constexpr int FAN_LDS = 2048;                // fan-out list entries a grid block stages in LDS
 constexpr int NARROW_BS = 1024;              // threads of the single-block JP kernel
 constexpr int JP_NARROW_MAX = 2048;          // level size the single block takes
 constexpr int JP_NARROW_EDGES = 1 << 14;     // level edges the single block takes
@@ -780,7 +780,7 @@ __device__ __forceinline__ int jp_colour(const Params& P, bool act, int v) {
 }
 
 // ---- level lists
-// Level l's vertices with at most JP_CHUNK same-round successors are in
+// Level l's vertices with at most JP_SMALL same-round successors are in
 // F[l & 1] (count fcnt[l % 3]); the others ("fan-out" vertices) are in
 // H[l & 1] as (first chunk, vertex), their same-round successors cut into
 // chunks of JP_CHUNK that different wavefronts process (hctr[l % 3]: entries
@@ -805,7 +805,7 @@ __device__ __forceinline__ void jp_append(const Params& P, JpStage& st, int l, b
     unsigned long long es = wave_sum((unsigned long long)ns);
     if (lane_id() == 0 && es) add64<S>(&st.ecnt[(l + 1) % 3], es);
   }
-  const bool fan = rdy && ns > JP_CHUNK;
+  const bool fan = rdy && ns > JP_SMALL;
   if (fan) {
     unsigned long long nch = (unsigned long long)((ns + JP_CHUNK - 1) / JP_CHUNK);
     unsigned long long old = add64<S>(&st.hctr[(l + 1) % 3], (nch << 32) | 1ull);
@@ -869,16 +869,36 @@ __device__ __forceinline__ void jp_succ_range(const Params& P, JpStage& st, int 
   }
 }
 
-// Fan-out chunk k of a list sorted by first chunk: its entry (binary search).
+// Fan-out chunk k of a list sorted by first chunk: its entry (binary search,
+// in the block's LDS copy `lds` when the list was staged there).
 template <int S>
-__device__ __forceinline__ unsigned long long fan_entry(const unsigned long long* Hl, unsigned nh, unsigned k) {
+__device__ __forceinline__ unsigned long long fan_entry(const unsigned long long* Hl, unsigned nh, unsigned k,
+                                                        const unsigned long long* lds) {
   unsigned lo = 0, hi = nh;
+  if (lds) {
+    while (hi - lo > 1) {
+      unsigned mid = (lo + hi) >> 1;
+      if ((unsigned)(lds[mid] >> 32) <= k) lo = mid;
+      else hi = mid;
+    }
+    return lds[lo];
+  }
   while (hi - lo > 1) {
     unsigned mid = (lo + hi) >> 1;
     if ((unsigned)(ld64<S>(&Hl[mid]) >> 32) <= k) lo = mid;
     else hi = mid;
   }
   return ld64<S>(&Hl[lo]);
+}
+
+// Block-wide: stage a fan-out list in LDS if it fits (returns the copy or null).
+template <int S>
+__device__ __forceinline__ const unsigned long long* fan_stage(const unsigned long long* Hl, unsigned nh,
+                                                               unsigned long long* lds) {
+  if (nh > (unsigned)FAN_LDS) return nullptr;
+  for (unsigned i = threadIdx.x; i < nh; i += blockDim.x) lds[i] = ld64<S>(&Hl[i]);
+  __syncthreads();
+  return lds;
 }
 
 __device__ __forceinline__ long long succ_begin(const Params& P, int v) { return P.rp[v] + P.npred[v]; }
@@ -888,7 +908,7 @@ __device__ __forceinline__ long long succ_begin(const Params& P, int v) { return
 // more than JP_SMALL successors), then the fan-out chunks.
 template <int S>
 __device__ void jp_level_items(const Params& P, JpStage& st, int l, unsigned nf, unsigned long long hc, long long gw,
-                               long long gstride) {
+                               long long gstride, const unsigned long long* hlds) {
   const unsigned lane = lane_id();
   const unsigned nh = (unsigned)hc;
   const unsigned nch = (unsigned)(hc >> 32);
@@ -897,6 +917,7 @@ __device__ void jp_level_items(const Params& P, JpStage& st, int l, unsigned nf,
   const long long groups = ((long long)nf + WAVE - 1) / WAVE;
   for (long long it = gw; it < groups + (long long)nch; it += gstride) {
     if (it < groups) {
+      // plain vertices: at most JP_SMALL same-round successors, a lane each
       const long long idx = it * WAVE + lane;
       const bool act = idx < nf;
       const int v = act ? (int)ld32<S>(&Fl[idx]) : 0;
@@ -907,13 +928,12 @@ __device__ void jp_level_items(const Params& P, JpStage& st, int l, unsigned nf,
         b = succ_begin(P, v);
         e = b + P.nsr[v];
       }
-      const bool small = act && (e - b) <= JP_SMALL;
-      for (long long j = b; ballot(small && j < e); j += JP_UNROLL) {
+      for (long long j = b; ballot(act && j < e); j += JP_UNROLL) {
         int u[JP_UNROLL];
         bool ok[JP_UNROLL];
 #pragma unroll
         for (int t = 0; t < JP_UNROLL; ++t) {
-          ok[t] = small && j + t < e;
+          ok[t] = act && j + t < e;
           u[t] = ok[t] ? P.dag[j + t] : 0;
         }
         bool rdy[JP_UNROLL];
@@ -922,15 +942,9 @@ __device__ void jp_level_items(const Params& P, JpStage& st, int l, unsigned nf,
 #pragma unroll
         for (int t = 0; t < JP_UNROLL; ++t) jp_append<S>(P, st, l, rdy[t], u[t]);
       }
-      uint64_t mid = ballot(act && !small);
-      while (mid) {
-        int L = __ffsll((long long)mid) - 1;
-        mid &= mid - 1;
-        jp_succ_range<S>(P, st, l, readlane_i(col, L), readlane_i64(b, L), readlane_i64(e, L));
-      }
     } else {
       const unsigned k = (unsigned)(it - groups);
-      const unsigned long long ent = fan_entry<S>(Hl, nh, k);
+      const unsigned long long ent = fan_entry<S>(Hl, nh, k, hlds);
       const int v = (int)(unsigned)ent;
       const unsigned first = (unsigned)(ent >> 32);
       const int col = jp_colour<S>(P, true, v);
@@ -952,8 +966,8 @@ __device__ __forceinline__ long long seg_size(const Params& P, int r) {
 __device__ __forceinline__ int seg_vertex(const Params& P, long long i) { return P.ord_identity ? (int)i : P.ORD[i]; }
 
 // Level 0 of round r: its vertices whose count is already zero.  Also lists
-// the round's vertices with long earlier-round successor ranges for the push
-// (chunked across wavefronts), in PH with its counter phctr.
+// the round's vertices with more than JP_SMALL earlier-round successors for
+// the push (chunked across wavefronts), in PH with its counter phctr.
 template <int S>
 __device__ void jp_frontier_items(const Params& P, JpStage& st, int r, long long gw, long long gstride) {
   const long long b = seg_begin(P, r), sz = seg_size(P, r);
@@ -966,8 +980,8 @@ __device__ void jp_frontier_items(const Params& P, JpStage& st, int r, long long
     jp_append<S>(P, st, -1, rdy, v);
     if (ok && !P.ord_identity) {
       long long sb = succ_begin(P, v) + P.nsr[v], se = P.rp[v + 1];
-      if (se - sb > PUSH_BIG) {
-        unsigned long long nch = (unsigned long long)((se - sb - PUSH_BIG + JP_CHUNK - 1) / JP_CHUNK);
+      if (se - sb > JP_SMALL) {
+        unsigned long long nch = (unsigned long long)((se - sb + JP_CHUNK - 1) / JP_CHUNK);
         unsigned long long old = add64<S>(st.phctr, (nch << 32) | 1ull);
         unsigned pos = (unsigned)old;
         if (pos < P.hub_cap) st64<S>(&P.PH[pos], (old & 0xffffffff00000000ull) | (unsigned)v);
@@ -978,11 +992,11 @@ __device__ void jp_frontier_items(const Params& P, JpStage& st, int r, long long
 }
 
 // Bulk push of round r's colours to earlier-round successors.  Items: groups
-// of 64 vertices of the round (a lane each for short ranges, the whole wave
-// for the first PUSH_BIG successors of longer ones), then the chunks beyond
-// PUSH_BIG of the long ranges listed in PH.
+// of 64 vertices of the round (a lane each, for at most JP_SMALL successors),
+// then the JP_CHUNK-sized chunks of the longer ranges listed in PH.
 template <int S>
-__device__ void jp_push_items(const Params& P, int r, unsigned long long phc, long long gw, long long gstride) {
+__device__ void jp_push_items(const Params& P, int r, unsigned long long phc, long long gw, long long gstride,
+                              const unsigned long long* plds) {
   const long long b = seg_begin(P, r), sz = seg_size(P, r);
   const unsigned lane = lane_id();
   const long long groups = (sz + WAVE - 1) / WAVE;
@@ -997,34 +1011,28 @@ __device__ void jp_push_items(const Params& P, int r, unsigned long long phc, lo
       if (act) {
         s0 = succ_begin(P, v) + P.nsr[v];
         s1 = P.rp[v + 1];
-        col = ldi<S>(&P.color[v]);
+        act = s1 - s0 <= JP_SMALL;  // longer ranges are chunks
+        if (act) col = ldi<S>(&P.color[v]);
       }
-      const bool small = act && (s1 - s0) <= JP_SMALL;
-      for (long long j = s0; ballot(small && j < s1); j += JP_UNROLL) {
+      for (long long j = s0; ballot(act && j < s1); j += JP_UNROLL) {
 #pragma unroll
         for (int t = 0; t < JP_UNROLL; ++t)
-          if (small && j + t < s1) jp_push_one<S>(P, P.dag[j + t], col);
-      }
-      uint64_t mid = ballot(act && !small);
-      while (mid) {
-        int L = __ffsll((long long)mid) - 1;
-        mid &= mid - 1;
-        const long long bb = readlane_i64(s0, L);
-        long long ee = readlane_i64(s1, L);
-        if (ee - bb > PUSH_BIG) ee = bb + PUSH_BIG;
-        const int cc = readlane_i(col, L);
-        for (long long j = bb + lane; j < ee; j += WAVE) jp_push_one<S>(P, P.dag[j], cc);
+          if (act && j + t < s1) jp_push_one<S>(P, P.dag[j + t], col);
       }
     } else {
       const unsigned k = (unsigned)(it - groups);
-      const unsigned long long ent = fan_entry<S>(P.PH, nh, k);
+      const unsigned long long ent = fan_entry<S>(P.PH, nh, k, plds);
       const int v = (int)(unsigned)ent;
       const unsigned first = (unsigned)(ent >> 32);
-      const long long sb = succ_begin(P, v) + P.nsr[v] + PUSH_BIG, se = P.rp[v + 1];
+      const long long sb = succ_begin(P, v) + P.nsr[v], se = P.rp[v + 1];
       const long long s0 = sb + (long long)(k - first) * JP_CHUNK;
       const long long s1 = s0 + JP_CHUNK < se ? s0 + JP_CHUNK : se;
       const int cc = ldi<S>(&P.color[v]);
-      for (long long j = s0 + lane; j < s1; j += WAVE) jp_push_one<S>(P, P.dag[j], cc);
+#pragma unroll
+      for (int t = 0; t < JP_UNROLL; ++t) {
+        long long j = s0 + t * WAVE + lane;
+        if (j < s1) jp_push_one<S>(P, P.dag[j], cc);
+      }
     }
   }
 }
@@ -1246,7 +1254,7 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_narrow(Params P, int max_steps
       if (work > NARROW_PUSH_WORK) {
         handed = OP_PUSH;
       } else {
-        if (work > 0) jp_push_items<SC_WG>(P, r, S.phctr, gw, gstride);
+        if (work > 0) jp_push_items<SC_WG>(P, r, S.phctr, gw, gstride, nullptr);
         order_point();
         __syncthreads();
         if (threadIdx.x == 0) jp_begin_round(S, r - 1);
@@ -1269,6 +1277,7 @@ __global__ __launch_bounds__(BS) void k_jp_grid(Params P) {
   if (c->js.done || op == OP_NONE || c->grid_ran) return;
   __shared__ unsigned fbuf[FB_CAP];
   __shared__ unsigned fcnt;
+  __shared__ unsigned long long flds[FAN_LDS];
   if (threadIdx.x == 0) fcnt = 0;
   __syncthreads();
   JpStage st{fbuf, &fcnt, c->js.fcnt, c->js.hctr, c->js.ecnt, &c->js.phctr};
@@ -1280,10 +1289,14 @@ __global__ __launch_bounds__(BS) void k_jp_grid(Params P) {
     jp_stage_flush<SC_AGENT>(P, st, -1);
   } else if (op == OP_LEVEL) {
     const int l = c->js.level;
-    jp_level_items<SC_AGENT>(P, st, l, c->js.fcnt[l % 3], c->js.hctr[l % 3], gw, gstride);
+    const unsigned long long hc = c->js.hctr[l % 3];
+    const unsigned long long* hl = fan_stage<SC_AGENT>(P.H[l & 1], (unsigned)hc, flds);
+    jp_level_items<SC_AGENT>(P, st, l, c->js.fcnt[l % 3], hc, gw, gstride, hl);
     jp_stage_flush<SC_AGENT>(P, st, l);
   } else {
-    jp_push_items<SC_AGENT>(P, r, c->js.phctr, gw, gstride);
+    const unsigned long long phc = c->js.phctr;
+    const unsigned long long* pl = fan_stage<SC_AGENT>(P.PH, (unsigned)phc, flds);
+    jp_push_items<SC_AGENT>(P, r, phc, gw, gstride, pl);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) c->grid_ran = 1;
 }
@@ -1464,9 +1477,9 @@ Layout make_layout(int64_t n, int64_t nnz) {
   L.word = take(8 * nn);
   L.F0 = take(4 * nn);
   L.F1 = take(4 * nn);
-  // fan-out entries: vertices with more than JP_CHUNK (level lists) or
-  // PUSH_BIG (push list) successors, at most m / JP_CHUNK of them
-  L.hub_cap = (size_t)nnz / (2 * JP_CHUNK) + 64;
+  // fan-out entries: vertices with more than JP_SMALL successors in the
+  // range concerned (level lists, push list), at most m / JP_SMALL of them
+  L.hub_cap = (size_t)nnz / (2 * JP_SMALL) + 64;
   L.H0 = take(8 * L.hub_cap);
   L.H1 = take(8 * L.hub_cap);
   L.PH = take(8 * L.hub_cap);
