@@ -99,6 +99,9 @@ def main():
     ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--breakdown", action="store_true", help="print per-kernel-class times to stderr")
+    ap.add_argument("--calib-mib", type=int, default=256,
+                    help="size of a plain device copy issued before the run, so that profiler byte counters "
+                         "can be scaled against a kernel of known traffic (0 = none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -127,6 +130,14 @@ def main():
 
     def step():
         adg.color_graph(g, p, q, seed, workspace=ws, out=out)
+
+    if args.calib_mib > 0:
+        # reference for counter scaling: reads and writes calib_mib MiB once
+        ca = torch.ones(args.calib_mib << 20, dtype=torch.uint8, device="cuda:0")
+        cb = torch.empty_like(ca)
+        cb.copy_(ca)
+        torch.cuda.synchronize()
+        del ca, cb
 
     for _ in range(args.warmup):
         step()
