@@ -47,6 +47,8 @@ def _load():
         lib.gg_splitmix64_draw.restype = u64
         lib.gg_splitmix64_draw.argtypes = [u64, u64]
         lib.gg_num_threads.restype = ctypes.c_int
+        lib.gg_chung_lu_many.restype = None
+        lib.gg_chung_lu_many.argtypes = [i64, vp, vp, f64, vp, vp]
         _lib = lib
     return _lib
 
@@ -89,6 +91,33 @@ def rmat(scale, edge_factor=16, a=0.57, b=0.19, c=0.19, seed=0):
 def chung_lu(n, mean_deg, gamma=2.3, seed=0):
     """Chung-Lu expected-degree graph with power-law weights (exponent gamma)."""
     return _take(_load().gg_chung_lu(int(n), float(mean_deg), float(gamma), int(seed) & (2**64 - 1)))
+
+
+def chung_lu_many(specs, gamma=2.3):
+    """[(row_ptr, col_idx)] for a list of (n, mean_deg, seed): the same graphs
+    as chung_lu, generated one graph per thread."""
+    G = len(specs)
+    n = np.array([s[0] for s in specs], dtype=np.int64)
+    k = np.array([s[1] for s in specs], dtype=np.float64)
+    seeds = np.array([int(s[2]) & (2**64 - 1) for s in specs], dtype=np.uint64)
+    handles = (ctypes.c_void_p * max(G, 1))()
+    _load().gg_chung_lu_many(G, n.ctypes.data, k.ctypes.data, float(gamma), seeds.ctypes.data, handles)
+    out = []
+    try:
+        for g in range(G):
+            out.append(_take(handles[g]))
+            handles[g] = None
+    finally:
+        for g in range(G):
+            if handles[g]:
+                _load().gg_free(handles[g])
+    return out
+
+
+def batched_graphs(num_graphs=4096, seed=4, size_scale=1.0):
+    """The graphs of the batched workload (see batched_config)."""
+    specs = batched_config(num_graphs=num_graphs, seed=seed, size_scale=size_scale)
+    return chung_lu_many([(n, min(k, n - 1.0), s) for n, k, s in specs], 2.3)
 
 
 def chung_lu_weights(n, mean_deg, gamma=2.3):

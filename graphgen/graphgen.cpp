@@ -354,6 +354,16 @@ void* gg_chung_lu(int64_t n, double mean_deg, double gamma, uint64_t seed) {
   return build_csr(n, m, src.data(), dst.data());
 }
 
+// Many Chung-Lu graphs at once (graph g: n[g] vertices, mean degree k[g],
+// seed seeds[g]), one graph per thread; out[g] receives its handle (null on
+// failure).  Each graph is exactly gg_chung_lu's: rows use their own
+// sub-streams and the weights are computed serially either way.
+void gg_chung_lu_many(int64_t G, const int64_t* n, const double* k, double gamma, const uint64_t* seeds,
+                      void** out) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t g = 0; g < G; ++g) out[g] = gg_chung_lu(n[g], k[g], gamma, seeds[g]);
+}
+
 // Raw stream access, so that tests can pin the generator to SplitMix64's
 // published output sequence.
 uint64_t gg_splitmix64_draw(uint64_t key, uint64_t i) { return draw(key, i); }

@@ -13,7 +13,8 @@
  *                  succ sets and |pred|) fused into ADG's UPDATE, the
  *                  "Combining JP and ADG" optimisation of the section
  *                  "Optimizations and Implementation".
- *   - color_graph_batched: many independent graphs in one call.
+ *   - color_graph_batched: JP-ADG on many independent graphs in one
+ *                  persistent launch, each graph coloured exactly as alone.
  *
  * Conventions shared by every entry point:
  *   - Graphs are simple and undirected (symmetric adjacency, no self-loops,
@@ -112,6 +113,73 @@ int jp_color(const adg_csr_t* g, const int32_t* round, uint64_t seed, int32_t* c
 int color_graph(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_t seed,
                 int32_t* color_out, int32_t* round_out, int32_t* num_colors_out,
                 int32_t* num_rounds_out, void* workspace, size_t ws_bytes, void* stream);
+
+/* ---- Many independent graphs in one call.
+ *
+ * The batch is one concatenated CSR: graph g owns global vertex slots
+ * vtx_off[g] .. vtx_off[g+1]-1 and the entries row_ptr[vtx_off[g]] ..
+ * row_ptr[vtx_off[g+1]]-1 of col_idx; row_ptr holds ABSOLUTE offsets into
+ * col_idx, and col_idx holds LOCAL vertex ids (0 .. n_g - 1).  Each graph is
+ * coloured exactly as a standalone color_graph call on it would colour it
+ * (same eps, same seed, local ids): ADG's average degree is per graph, since
+ * ADG on the disjoint union would select different rounds (Algorithm 1 takes
+ * the average over the whole remaining graph). */
+typedef struct adg_batch {
+  int32_t num_graphs;      /* G >= 0 */
+  int64_t total_n;         /* vtx_off[G] (host copy), < 2^31 */
+  int64_t total_nnz;       /* row_ptr[total_n] (host copy) */
+  const int64_t* vtx_off;  /* device [G+1], non-decreasing, vtx_off[0] = 0 */
+  const int64_t* row_ptr;  /* device [total_n+1], absolute */
+  const int32_t* col_idx;  /* device [total_nnz], local ids */
+} adg_batch_t;
+
+/* Launch shape of the persistent batched kernel: threads per workgroup
+ * (256, 512 or 1024), resident workgroups per compute unit (1..32, with
+ * block_threads * blocks_per_cu <= 2048 to be useful), and the order in which
+ * workgroups take graphs (ADG_SCHED_LPT: largest work class first;
+ * ADG_SCHED_NATURAL: batch order).  Results do not depend on it. */
+enum { ADG_SCHED_LPT = 0, ADG_SCHED_NATURAL = 1 };
+typedef struct adg_batch_config {
+  int32_t block_threads;
+  int32_t blocks_per_cu;
+  int32_t schedule;
+} adg_batch_config_t;
+
+/* Workspace bytes for color_graph_batched; 0 for invalid sizes. */
+size_t adg_batched_workspace_bytes(int32_t num_graphs, int64_t total_n, int64_t total_nnz);
+
+/* The launch shape used when color_graph_batched gets config = NULL. */
+adg_batch_config_t adg_batched_default_config(void);
+
+/* JP-ADG (Algorithms 1 and 3, as color_graph) on every graph of the batch, in
+ * one persistent launch: each workgroup colours whole graphs, one after the
+ * other, taking them from a device-side queue.  Writes color_out[total_n]
+ * (colour of local vertex v of graph g at vtx_off[g] + v), round_out[total_n]
+ * (nullable), num_colors_out[G] and num_rounds_out[G] (nullable), all device
+ * int32.  config may be NULL.  Fully asynchronous: no host synchronisation,
+ * no memset, so the call can be recorded by stream capture.  Device-side
+ * errors (a broken DAG, a round-count overrun) are reported by
+ * adg_batched_error.  Errors returned: ADG_ERR_ARG, ADG_ERR_WORKSPACE,
+ * ADG_ERR_HIP. */
+int color_graph_batched(const adg_batch_t* b, int32_t eps_num, int32_t eps_den, uint64_t seed,
+                        int32_t* color_out, int32_t* round_out, int32_t* num_colors_out,
+                        int32_t* num_rounds_out, const adg_batch_config_t* config, void* workspace,
+                        size_t ws_bytes, void* stream);
+
+/* Device-side error flag of the last color_graph_batched call on this
+ * workspace (0 = none, else an ADG_ERR_* code).  Synchronises `stream`. */
+int adg_batched_error(const void* workspace, size_t ws_bytes, int32_t* host_error, void* stream);
+
+/* Launch-shape autotuner: runs color_graph_batched on this batch once per
+ * candidate shape (block_threads x blocks_per_cu, then the schedule order for
+ * the best), times each with HIP events on `stream`, and writes the fastest
+ * to *best_out (and its time to *best_ms_out, nullable).  The outputs hold a
+ * valid result afterwards.  The choice is cached per batch shape class
+ * (G, and total_n, total_nnz rounded to powers of two) for later calls with
+ * `reuse` != 0.  Synchronises `stream`. */
+int adg_batched_autotune(const adg_batch_t* b, int32_t eps_num, int32_t eps_den, uint64_t seed,
+                         int32_t* color_out, int32_t* num_colors_out, void* workspace, size_t ws_bytes,
+                         void* stream, int32_t reuse, adg_batch_config_t* best_out, float* best_ms_out);
 
 /* Copy the counters of the last adg_order / jp_color / color_graph call on
  * this workspace to host memory.  Synchronises `stream`. */

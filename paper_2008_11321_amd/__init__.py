@@ -82,11 +82,6 @@ def lib():
     L.adg_profile_read.argtypes = [P(_Profile)]
     L.adg_kernel_class_name.restype = ctypes.c_char_p
     L.adg_kernel_class_name.argtypes = [ctypes.c_int]
-    if hasattr(L, "color_graph_batched"):
-        L.adg_batched_workspace_bytes.restype = sz
-        L.adg_batched_workspace_bytes.argtypes = [i32, i64, i64, i64]
-        L.color_graph_batched.restype = ctypes.c_int
-        L.color_graph_batched.argtypes = [i32, vp, vp, vp, i32, i32, u64, vp, vp, vp, vp, vp, sz, vp]
     _lib = L
     return L
 
@@ -220,14 +215,13 @@ def validate_csr(g, workspace=None, stream=None):
     return True
 
 
-def batched_workspace_bytes(num_graphs, total_n, total_nnz, max_n):
-    L = lib()
-    if not hasattr(L, "color_graph_batched"):
-        raise RuntimeError("batched entry point not built")
-    return L.adg_batched_workspace_bytes(int(num_graphs), int(total_n), int(total_nnz), int(max_n))
+def batched_workspace_bytes(num_graphs, total_n, total_nnz):
+    from .batched import batched_workspace_bytes as f
+    return f(num_graphs, total_n, total_nnz)
 
 
 def color_graph_batched(*args, **kwargs):
+    """See batched.color_graph_batched."""
     from .batched import color_graph_batched as f
     return f(*args, **kwargs)
 

@@ -1,0 +1,774 @@
+// JP-ADG on many independent graphs in one persistent launch
+// (color_graph_batched in include/adg.h).
+//
+// Paper: Besta et al., "High-Performance Parallel Graph Coloring with Strong
+// Guarantees on Work, Depth, and Quality" -- ADG (Algorithm 1) and JP
+// (Algorithm 3) under rho = <rho_ADG, rho_R>.
+//
+// Each graph of the batch is coloured by ONE workgroup from start to end, so
+// ADG's average degree, threshold and rounds stay per graph (ADG on a disjoint
+// union would use the union's average degree and give different rounds).  A
+// fixed grid of workgroups pulls graphs from a device-side queue, largest
+// first (a coarse longest-processing-time order built by a prep kernel), and
+// loops until the queue is empty: one launch for the whole batch, no host
+// round trip, and nothing a stream capture cannot record.
+//
+// Inside a workgroup, per graph:
+//   ADG   round l: T_l = floor((q+p) S_l / (q |U_l|)) from the cached degree
+//         sum; one pass over U_l splits it stably into R_l and U_{l+1}
+//         (block prefix sums) and sums D over U_{l+1}; one pass over R_l does
+//         UPDATE (decrement D[w] for neighbours w that stay in U) fused with
+//         JP's Part 1: v's row is rewritten as [pred | succ] in the DAG array,
+//         |pred(v)| and v's JP word are stored, and v joins JP's first level
+//         when it has no predecessor.  S_{l+1} = (sum over U_{l+1}) - (number
+//         of decrements).  Block barriers separate the passes.
+//   JP    level-synchronous over the whole DAG: a level's vertices have final
+//         colours; their successor edges are spread evenly over the block
+//         (prefix sum of successor counts, binary search for the owner); each
+//         edge ORs the colour into the successor's word and takes one count
+//         unit off it; the edge that takes the last unit knows the complete
+//         mask from the atomic's return value, colours the successor and
+//         appends it to the next level.
+// All memory a workgroup touches for a graph belongs to that graph, so every
+// atomic is workgroup-scoped.  Values changed by atomics (D, the extension
+// words) are read back with device-coherent loads, which bypass the CU's L1.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/adg.h"
+#include "adg_device.h"
+#include "adg_host.h"
+
+namespace adg {
+namespace batched {
+
+constexpr int SMALL_ROW = 32;         // lane-per-vertex rows up to this length
+constexpr int SCHED_BS = 1024;        // threads of the schedule kernel
+constexpr int SCHED_BUCKETS = 64;     // work classes (floor(log2(work)))
+constexpr int WG = __HIP_MEMORY_SCOPE_WORKGROUP;
+
+struct BCtrl {
+  unsigned int next;   // queue head: graphs claimed so far
+  int error;           // ADG_ERR_* raised on the device
+  unsigned int pad[62];
+};
+
+struct BParams {
+  int G;
+  const long long* vo;          // [G+1] vertex offsets
+  const long long* rp;          // [total_n + 1] absolute offsets into col
+  const int* col;               // local vertex ids
+  unsigned long long p, q;      // eps = p / q
+  uint32_t hkey;
+  BCtrl* ctrl;
+  int* sched;                   // [G] graph ids, largest work first
+  int* round;                   // [total_n] rho_ADG (caller's or workspace)
+  int* D;                       // [total_n]
+  int* UL0;                     // [total_n] active lists, double-buffered
+  int* UL1;
+  int* RL;                      // [total_n] R_l lists (R_1 | R_2 | ...)
+  int* dag;                     // [total_nnz] rows as [pred | succ]
+  int* npred;                   // [total_n]
+  int* eoff;                    // [total_n] extension-word offset inside the graph's region
+  unsigned long long* word;     // [total_n] JP word (adg_device.h)
+  unsigned long long* F0;       // [total_n] level lists: (colour << 32) | vertex
+  unsigned long long* F1;
+  unsigned long long* ext;      // extension words; graph g's region starts at rp[vo[g]] / 64 + g
+  int* color;                   // [total_n]
+  int* num_colors;              // [G]
+  int* num_rounds;              // [G] (nullable)
+};
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ int ld_dev(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_dev64(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void dec_wg(int* p) { __hip_atomic_fetch_add(p, -1, __ATOMIC_RELAXED, WG); }
+__device__ __forceinline__ void or_wg(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, WG);
+}
+__device__ __forceinline__ unsigned long long sub_wg(unsigned long long* p, unsigned long long v) {
+  return __hip_atomic_fetch_add(p, (unsigned long long)(-(long long)v), __ATOMIC_RELAXED, WG);
+}
+
+// Extension words of a vertex with `np` predecessors: colours 41 .. np + 1.
+__device__ __forceinline__ int ext_words(int np) {
+  int over = np + 1 - JP_MASK_BITS;
+  return over > 0 ? (over + 63) / 64 : 0;
+}
+
+// Block-wide exclusive prefix sum of `x`; returns the prefix and sets *total.
+// `red` holds one slot per wavefront (+1); ends with a barrier so `red` can be
+// reused right away.
+template <int BB>
+__device__ __forceinline__ long long block_scan(long long x, long long* red, long long* total) {
+  constexpr int NW = BB / WAVE;
+  const unsigned lane = lane_id();
+  const int w = threadIdx.x / WAVE;
+  long long incl = x;
+#pragma unroll
+  for (int off = 1; off < WAVE; off <<= 1) {
+    long long o = __shfl_up(incl, off, WAVE);
+    if ((int)lane >= off) incl += o;
+  }
+  if (lane == WAVE - 1) red[w] = incl;
+  __syncthreads();
+  long long pre = 0, tot = 0;
+#pragma unroll 4
+  for (int k = 0; k < NW; ++k) {
+    long long t = red[k];
+    pre += k < w ? t : 0;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + incl - x;
+}
+
+template <int BB>
+__device__ __forceinline__ long long block_sum(long long x, long long* red) {
+  long long t;
+  (void)block_scan<BB>(x, red, &t);
+  return t;
+}
+
+template <int BB>
+__device__ __forceinline__ long long block_max(long long x, long long* red) {
+  constexpr int NW = BB / WAVE;
+  x = wave_max(x);
+  if (lane_id() == 0) red[threadIdx.x / WAVE] = x;
+  __syncthreads();
+  long long m = red[0];
+#pragma unroll 4
+  for (int k = 1; k < NW; ++k) m = red[k] > m ? red[k] : m;
+  __syncthreads();
+  return m;
+}
+
+// ---------------------------------------------------------------- schedule
+
+// One block: clears the control block and orders the graphs by decreasing
+// work class floor(log2(n_g + nnz_g)), so the largest graphs start first.
+__global__ __launch_bounds__(SCHED_BS) void k_sched(BParams P, int natural) {
+  __shared__ unsigned hist[SCHED_BUCKETS];
+  __shared__ unsigned base[SCHED_BUCKETS];
+  if (threadIdx.x < SCHED_BUCKETS) hist[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    P.ctrl->next = 0;
+    P.ctrl->error = 0;
+  }
+  __syncthreads();
+  if (natural) {
+    for (int g = threadIdx.x; g < P.G; g += SCHED_BS) P.sched[g] = g;
+    return;
+  }
+  auto bucket = [&](int g) {
+    long long n = P.vo[g + 1] - P.vo[g];
+    long long e = P.rp[P.vo[g + 1]] - P.rp[P.vo[g]];
+    unsigned long long w = (unsigned long long)(n + e) + 1;
+    return SCHED_BUCKETS - 1 - (63 - __clzll((long long)w));  // larger work -> smaller bucket
+  };
+  for (int g = threadIdx.x; g < P.G; g += SCHED_BS) atomicAdd(&hist[bucket(g)], 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned run = 0;
+    for (int b = 0; b < SCHED_BUCKETS; ++b) {
+      base[b] = run;
+      run += hist[b];
+    }
+  }
+  __syncthreads();
+  for (int g = threadIdx.x; g < P.G; g += SCHED_BS) P.sched[atomicAdd(&base[bucket(g)], 1u)] = g;
+}
+
+// ---------------------------------------------------------------- ADG + Part 1
+
+struct GraphCtx {
+  long long vo;      // first global vertex
+  int n;             // vertices
+  long long e0;      // first entry in col / dag
+  long long nnz;     // entries
+  long long ebase;   // first extension word of the graph's region
+  long long ecap;    // extension words of the region
+};
+
+template <int BB>
+struct Lds {
+  long long red[BB / WAVE + 1];
+  long long start[BB + 1];   // JP: successor prefix of the chunk's vertices
+  long long sb[BB];          // JP: first successor entry of each vertex
+  int cl[BB];                // JP: colour of each vertex
+  int big[BB];               // UPDATE: rows handled by a whole wavefront
+  unsigned nbig;
+  unsigned f0;               // JP level-0 vertices found during ADG
+  unsigned fnext;            // next level's size
+  unsigned extc;             // extension words handed out
+  int gid;
+};
+
+// Classify neighbour w of v (removed in round l): 1 = predecessor (w has a
+// higher priority), 0 = successor.  A neighbour still in U loses one degree.
+__device__ __forceinline__ bool visit(const BParams& P, const GraphCtx& C, int w, int l, uint32_t hv,
+                                      long long& x) {
+  const int rw = P.round[C.vo + w];
+  if (rw == 0) {
+    dec_wg(&P.D[C.vo + w]);
+    ++x;
+    return true;
+  }
+  if (rw == l) return tiebreak(P.hkey, (uint32_t)w) > hv;
+  return false;
+}
+
+template <int BB>
+__device__ __forceinline__ void finish_row(const BParams& P, const GraphCtx& C, Lds<BB>& S, int v, int np) {
+  const long long gv = C.vo + v;
+  P.npred[gv] = np;
+  P.word[gv] = (unsigned long long)np << JP_MASK_BITS;
+  const int E = ext_words(np);
+  int eo = 0;
+  if (E > 0) {
+    eo = (int)atomicAdd(&S.extc, (unsigned)E);
+    if ((long long)eo + E > C.ecap) {  // cannot happen (see the region size); marks are then dropped
+      atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
+      eo = -1;
+    } else {
+      for (int k = 0; k < E; ++k) P.ext[C.ebase + eo + k] = 0;
+    }
+  }
+  P.eoff[gv] = eo;
+  if (np == 0) {
+    unsigned pos = atomicAdd(&S.f0, 1u);
+    if (pos < (unsigned)C.n) P.F0[C.vo + pos] = (1ull << 32) | (unsigned)v;
+  }
+}
+
+// ADG on graph C; returns the number of rounds.
+template <int BB>
+__device__ int adg_graph(const BParams& P, const GraphCtx& C, Lds<BB>& S) {
+  const int tid = threadIdx.x;
+  const int wid = tid / WAVE;
+  const unsigned lane = lane_id();
+  constexpr int NW = BB / WAVE;
+  unsigned long long N = (unsigned long long)C.n;
+  unsigned long long Ssum = (unsigned long long)C.nnz;
+  int* Uin = P.UL0 + C.vo;
+  int* Uout = P.UL1 + C.vo;
+  long long rpos = 0;   // R lists fill RL[vo ..] in round order
+  int l = 1;
+  for (;; ++l) {
+    if (l > C.n) {  // every round removes at least one vertex
+      if (tid == 0) atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
+      return l - 1;
+    }
+    const unsigned long long T = ((P.q + P.p) * Ssum) / (P.q * N);
+    // ---- selection: U_l -> R_l | U_{l+1}, stable
+    long long nr = 0, nu = 0, sstay = 0;
+    for (long long b = 0; b < (long long)N; b += BB) {
+      const long long i = b + tid;
+      const bool valid = i < (long long)N;
+      int u = 0;
+      long long d = 0;
+      if (valid) {
+        if (l == 1) {
+          u = (int)i;
+          d = P.rp[C.vo + i + 1] - P.rp[C.vo + i];
+        } else {
+          u = Uin[i];
+          d = ld_dev(&P.D[C.vo + u]);
+        }
+      }
+      const bool inR = valid && (unsigned long long)d <= T;
+      const bool stay = valid && !inR;
+      // two prefix sums packed in one: R count low, stay count high
+      long long tot;
+      const long long pre = block_scan<BB>((inR ? 1LL : 0LL) | (stay ? (1LL << 32) : 0LL), S.red, &tot);
+      if (inR) {
+        P.RL[C.vo + rpos + nr + (pre & 0xffffffffLL)] = u;
+        P.round[C.vo + u] = l;
+      } else if (stay) {
+        Uout[nu + (pre >> 32)] = u;
+        if (l == 1) {
+          P.round[C.vo + u] = 0;
+          P.D[C.vo + u] = (int)d;
+        }
+        sstay += d;
+      }
+      nr += tot & 0xffffffffLL;
+      nu += tot >> 32;
+    }
+    sstay = block_sum<BB>(sstay, S.red);   // barrier: round[] and RL complete
+    // ---- UPDATE fused with JP Part 1 over R_l
+    const int* R = P.RL + C.vo + rpos;
+    long long x = 0;
+    for (long long b = 0; b < nr; b += BB) {
+      if (tid == 0) S.nbig = 0;
+      __syncthreads();
+      const long long i = b + tid;
+      if (i < nr) {
+        const int v = R[i];
+        const long long r0 = P.rp[C.vo + v], r1 = P.rp[C.vo + v + 1];
+        if (r1 - r0 <= SMALL_ROW) {
+          const uint32_t hv = tiebreak(P.hkey, (uint32_t)v);
+          int np = 0, ns = 0;
+          for (long long e = r0; e < r1; ++e) {
+            const int w = P.col[e];
+            if (visit(P, C, w, l, hv, x)) P.dag[r0 + np++] = w;
+            else P.dag[r1 - 1 - ns++] = w;
+          }
+          finish_row<BB>(P, C, S, v, np);
+        } else {
+          S.big[atomicAdd(&S.nbig, 1u)] = v;
+        }
+      }
+      __syncthreads();
+      const unsigned nbig = S.nbig;
+      for (unsigned k = wid; k < nbig; k += NW) {
+        const int v = S.big[k];
+        const long long r0 = P.rp[C.vo + v], r1 = P.rp[C.vo + v + 1];
+        const uint32_t hv = tiebreak(P.hkey, (uint32_t)v);
+        long long np = 0, ns = 0;
+        for (long long e0 = r0; e0 < r1; e0 += WAVE) {
+          const long long e = e0 + lane;
+          const bool valid = e < r1;
+          int w = 0;
+          bool isp = false;
+          if (valid) {
+            w = P.col[e];
+            isp = visit(P, C, w, l, hv, x);
+          }
+          const uint64_t pm = ballot(valid && isp);
+          const uint64_t sm = ballot(valid && !isp);
+          if (valid) {
+            if (isp) P.dag[r0 + np + lanes_below(pm)] = w;
+            else P.dag[r1 - 1 - ns - lanes_below(sm)] = w;
+          }
+          np += __popcll(pm);
+          ns += __popcll(sm);
+        }
+        if (lane == 0) finish_row<BB>(P, C, S, v, (int)np);
+      }
+      __syncthreads();   // big[] and nbig are rewritten by the next chunk
+    }
+    x = block_sum<BB>(x, S.red);   // barrier: D decrements done
+    rpos += nr;
+    if (nu == 0) return l;
+    N = (unsigned long long)nu;
+    Ssum = (unsigned long long)(sstay - x);
+    int* t = Uin;
+    Uin = Uout;
+    Uout = t;
+  }
+}
+
+// ---------------------------------------------------------------- JP
+
+// Colour of a vertex whose predecessors took all of colours 1..40: the first
+// clear bit of its extension words.  Called a level after its last
+// predecessor, so every mark is complete.
+__device__ int ext_colour(const BParams& P, const GraphCtx& C, int v) {
+  const long long gv = C.vo + v;
+  const int eo = P.eoff[gv];
+  const int E = eo < 0 ? 0 : ext_words(P.npred[gv]);
+  const long long e0 = C.ebase + eo;
+  for (int k = 0; k < E; ++k) {
+    const unsigned long long wd = ld_dev64(&P.ext[e0 + k]);
+    if (~wd) return JP_MASK_BITS + 1 + k * 64 + __ffsll((long long)~wd) - 1;
+  }
+  atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
+  return JP_MASK_BITS + 1 + E * 64;
+}
+
+// Record colour c of a predecessor at successor u; true if u has no
+// uncoloured predecessor left, with *mask = u's complete colour mask.
+__device__ __forceinline__ bool touch(const BParams& P, const GraphCtx& C, int u, int c, unsigned long long* mask) {
+  const long long gu = C.vo + u;
+  unsigned long long bit = 0;
+  if (c <= JP_MASK_BITS) {
+    bit = 1ull << (c - 1);
+    or_wg(&P.word[gu], bit);
+  } else {
+    const int k = (c - JP_MASK_BITS - 1) >> 6;
+    const int eo = P.eoff[gu];
+    if (eo >= 0 && k < ext_words(P.npred[gu]))
+      or_wg(&P.ext[C.ebase + eo + k], 1ull << ((c - JP_MASK_BITS - 1) & 63));
+  }
+  const unsigned long long old = sub_wg(&P.word[gu], JP_ONE);
+  *mask = (old | bit) & JP_MASK;
+  return (old >> JP_MASK_BITS) == 1;
+}
+
+template <int BB>
+__device__ int jp_graph(const BParams& P, const GraphCtx& C, Lds<BB>& S, unsigned nf) {
+  const int tid = threadIdx.x;
+  unsigned long long* Fc = P.F0 + C.vo;
+  unsigned long long* Fn = P.F1 + C.vo;
+  long long cmax = 0;
+  long long done = 0;
+  if (nf > (unsigned)C.n) {
+    if (tid == 0) atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
+    nf = 0;
+  }
+  while (nf > 0) {
+    done += nf;
+    if (done > C.n) {  // a vertex was released twice: broken DAG
+      if (tid == 0) atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
+      break;
+    }
+    if (tid == 0) S.fnext = 0;
+    for (unsigned b = 0; b < nf; b += BB) {
+      const unsigned i = b + tid;
+      long long cnt = 0;
+      if (i < nf) {
+        const unsigned long long ent = Fc[i];
+        const int v = (int)(unsigned)ent;
+        int c = (int)(ent >> 32);
+        if (c == 0) c = ext_colour(P, C, v);
+        P.color[C.vo + v] = c;
+        cmax = c > cmax ? c : cmax;
+        const long long gv = C.vo + v;
+        const long long sb = P.rp[gv] + P.npred[gv];
+        cnt = P.rp[gv + 1] - sb;
+        S.sb[tid] = sb;
+        S.cl[tid] = c;
+      }
+      long long tot;
+      const long long pre = block_scan<BB>(cnt, S.red, &tot);   // barrier: sb, cl visible
+      S.start[tid] = pre;
+      if (tid == BB - 1) S.start[BB] = pre + cnt;
+      __syncthreads();
+      const int nv = (int)std::min<unsigned>(BB, nf - b);
+      for (long long e = tid; e < tot; e += BB) {
+        // owner: last k < nv with start[k] <= e
+        int lo = 0, hi = nv - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (S.start[mid] <= e) lo = mid;
+          else hi = mid - 1;
+        }
+        const int u = P.dag[S.sb[lo] + (e - S.start[lo])];
+        unsigned long long mask;
+        if (touch(P, C, u, S.cl[lo], &mask)) {
+          const int cu = mask == JP_MASK ? 0 : __ffsll((long long)~mask);
+          const unsigned pos = atomicAdd(&S.fnext, 1u);
+          if (pos < (unsigned)C.n) Fn[pos] = ((unsigned long long)cu << 32) | (unsigned)u;
+        }
+      }
+      __syncthreads();
+    }
+    nf = S.fnext;
+    if (nf > (unsigned)C.n) {
+      if (tid == 0) atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
+      break;
+    }
+    __syncthreads();   // everyone has read fnext before it is cleared
+    unsigned long long* t = Fc;
+    Fc = Fn;
+    Fn = t;
+  }
+  if (done != C.n && tid == 0 && done <= C.n) atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
+  return (int)block_max<BB>(cmax, S.red);
+}
+
+// ---------------------------------------------------------------- persistent kernel
+
+template <int BB>
+__global__ __launch_bounds__(BB) void k_batched(BParams P) {
+  __shared__ Lds<BB> S;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) {
+      const unsigned k = atomicAdd(&P.ctrl->next, 1u);
+      S.gid = k < (unsigned)P.G ? P.sched[k] : -1;
+      S.f0 = 0;
+      S.extc = 0;
+    }
+    __syncthreads();
+    const int g = S.gid;
+    if (g < 0) return;
+    GraphCtx C;
+    C.vo = P.vo[g];
+    C.n = (int)(P.vo[g + 1] - C.vo);
+    C.e0 = P.rp[C.vo];
+    C.nnz = P.rp[C.vo + C.n] - C.e0;
+    C.ebase = C.e0 / 64 + g;
+    C.ecap = (P.rp[P.vo[g + 1]] / 64 + g + 1) - C.ebase;
+    int L = 0, K = 0;
+    if (C.n > 0) {
+      L = adg_graph<BB>(P, C, S);
+      __syncthreads();   // f0, extc final
+      K = jp_graph<BB>(P, C, S, S.f0);
+    }
+    if (tid == 0) {
+      P.num_colors[g] = K;
+      if (P.num_rounds) P.num_rounds[g] = L;
+    }
+    __syncthreads();   // S reused by the next graph
+  }
+}
+
+// ---------------------------------------------------------------- host side
+
+struct BLayout {
+  size_t ctrl, sched, round, D, UL0, UL1, RL, dag, npred, eoff, word, F0, F1, ext, total;
+};
+
+BLayout make_layout(int64_t G, int64_t tn, int64_t tnnz) {
+  BLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + (bytes ? bytes : 1), 256);
+    return o;
+  };
+  const size_t n = (size_t)tn;
+  L.ctrl = take(sizeof(BCtrl));
+  L.sched = take(4 * (size_t)G);
+  L.round = take(4 * n);
+  L.D = take(4 * n);
+  L.UL0 = take(4 * n);
+  L.UL1 = take(4 * n);
+  L.RL = take(4 * n);
+  L.dag = take(4 * (size_t)tnnz);
+  L.npred = take(4 * n);
+  L.eoff = take(4 * n);
+  L.word = take(8 * n);
+  L.F0 = take(8 * n);
+  L.F1 = take(8 * n);
+  // graph g's region: [rp[vo[g]] / 64 + g, rp[vo[g+1]] / 64 + g + 1), at least
+  // floor(nnz_g / 64) + 1 words, more than the nnz_g / 80 that sum over v of
+  // ceil((|pred(v)| + 1 - 40) / 64) can reach
+  L.ext = take(8 * ((size_t)tnnz / 64 + (size_t)G + 2));
+  L.total = off;
+  return L;
+}
+
+int sm_count() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      n = 256;
+  }
+  return n;
+}
+
+int check_batch(const adg_batch_t* b) {
+  if (!b) return ADG_ERR_ARG;
+  if (b->num_graphs < 0 || b->total_n < 0 || b->total_nnz < 0 || b->total_n > 0x7ffffffeLL) return ADG_ERR_ARG;
+  if (b->num_graphs > 0 && (!b->vtx_off || !b->row_ptr)) return ADG_ERR_ARG;
+  if (b->total_n > 0 && !b->row_ptr) return ADG_ERR_ARG;
+  if (b->total_nnz > 0 && !b->col_idx) return ADG_ERR_ARG;
+  if (b->num_graphs == 0 && b->total_n > 0) return ADG_ERR_ARG;
+  return ADG_OK;
+}
+
+int launch(const BParams& P, const adg_batch_config_t& cfg, hipStream_t s) {
+  const int bpc = cfg.blocks_per_cu;
+  long long grid = (long long)sm_count() * bpc;
+  grid = std::min<long long>(grid, P.G);
+  if (grid < 1) grid = 1;
+  switch (cfg.block_threads) {
+    case 256: hipLaunchKernelGGL(k_batched<256>, dim3((unsigned)grid), dim3(256), 0, s, P); break;
+    case 512: hipLaunchKernelGGL(k_batched<512>, dim3((unsigned)grid), dim3(512), 0, s, P); break;
+    case 1024: hipLaunchKernelGGL(k_batched<1024>, dim3((unsigned)grid), dim3(1024), 0, s, P); break;
+    default: return ADG_ERR_ARG;
+  }
+  HIPCHK(hipGetLastError());
+  return ADG_OK;
+}
+
+bool valid_config(const adg_batch_config_t& c) {
+  return (c.block_threads == 256 || c.block_threads == 512 || c.block_threads == 1024) && c.blocks_per_cu >= 1 &&
+         c.blocks_per_cu <= 32 && (c.schedule == ADG_SCHED_LPT || c.schedule == ADG_SCHED_NATURAL);
+}
+
+// Autotuner cache: batch shape class -> fastest launch shape measured.
+struct TuneKey {
+  int G;
+  int ln, lnnz;   // ceil(log2) of total_n and total_nnz
+  bool operator==(const TuneKey& o) const { return G == o.G && ln == o.ln && lnnz == o.lnnz; }
+};
+struct TuneEntry {
+  TuneKey key;
+  adg_batch_config_t cfg;
+  float ms;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+
+int ceil_log2(long long x) {
+  int k = 0;
+  while ((1LL << k) < x && k < 62) ++k;
+  return k;
+}
+TuneKey tune_key(const adg_batch_t* b) { return {b->num_graphs, ceil_log2(b->total_n), ceil_log2(b->total_nnz)}; }
+
+}  // namespace batched
+}  // namespace adg
+
+using namespace adg;
+using namespace adg::batched;
+
+extern "C" {
+
+size_t adg_batched_workspace_bytes(int32_t num_graphs, int64_t total_n, int64_t total_nnz) {
+  if (num_graphs < 0 || total_n < 0 || total_nnz < 0 || total_n > 0x7ffffffeLL) return 0;
+  return make_layout(num_graphs, total_n, total_nnz).total;
+}
+
+adg_batch_config_t adg_batched_default_config(void) {
+  adg_batch_config_t c;
+  c.block_threads = 512;
+  c.blocks_per_cu = 2;
+  c.schedule = ADG_SCHED_LPT;
+  return c;
+}
+
+int color_graph_batched(const adg_batch_t* b, int32_t eps_num, int32_t eps_den, uint64_t seed, int32_t* color_out,
+                        int32_t* round_out, int32_t* num_colors_out, int32_t* num_rounds_out,
+                        const adg_batch_config_t* config, void* workspace, size_t ws_bytes, void* stream) {
+  int rc = check_batch(b);
+  if (rc) return rc;
+  if (eps_num < 0 || eps_den < 1) return ADG_ERR_ARG;
+  if (b->total_n > 0 && !color_out) return ADG_ERR_ARG;
+  if (b->num_graphs > 0 && !num_colors_out) return ADG_ERR_ARG;
+  adg_batch_config_t cfg = config ? *config : adg_batched_default_config();
+  if (!valid_config(cfg)) return ADG_ERR_ARG;
+  if (b->num_graphs == 0) return ADG_OK;
+  const BLayout L = make_layout(b->num_graphs, b->total_n, b->total_nnz);
+  if (!workspace || ((uintptr_t)workspace & 255) || ws_bytes < L.total) return ADG_ERR_WORKSPACE;
+  char* base = (char*)workspace;
+  BParams P{};
+  P.G = b->num_graphs;
+  P.vo = (const long long*)b->vtx_off;
+  P.rp = (const long long*)b->row_ptr;
+  P.col = b->col_idx;
+  P.p = (unsigned long long)eps_num;
+  P.q = (unsigned long long)eps_den;
+  P.hkey = hash_key_from_seed(seed);
+  P.ctrl = (BCtrl*)(base + L.ctrl);
+  P.sched = (int*)(base + L.sched);
+  P.round = round_out ? round_out : (int*)(base + L.round);
+  P.D = (int*)(base + L.D);
+  P.UL0 = (int*)(base + L.UL0);
+  P.UL1 = (int*)(base + L.UL1);
+  P.RL = (int*)(base + L.RL);
+  P.dag = (int*)(base + L.dag);
+  P.npred = (int*)(base + L.npred);
+  P.eoff = (int*)(base + L.eoff);
+  P.word = (unsigned long long*)(base + L.word);
+  P.F0 = (unsigned long long*)(base + L.F0);
+  P.F1 = (unsigned long long*)(base + L.F1);
+  P.ext = (unsigned long long*)(base + L.ext);
+  P.color = color_out;
+  P.num_colors = num_colors_out;
+  P.num_rounds = num_rounds_out;
+  hipStream_t s = (hipStream_t)stream;
+  TIMED(KC_BATCH, s);
+  hipLaunchKernelGGL(k_sched, dim3(1), dim3(SCHED_BS), 0, s, P, cfg.schedule == ADG_SCHED_NATURAL ? 1 : 0);
+  HIPCHK(hipGetLastError());
+  return launch(P, cfg, s);
+}
+
+int adg_batched_error(const void* workspace, size_t ws_bytes, int32_t* host_error, void* stream) {
+  if (!workspace || !host_error || ws_bytes < sizeof(BCtrl)) return ADG_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  BCtrl h;
+  HIPCHK(hipMemcpyAsync(&h, workspace, sizeof(BCtrl), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *host_error = h.error;
+  return ADG_OK;
+}
+
+int adg_batched_autotune(const adg_batch_t* b, int32_t eps_num, int32_t eps_den, uint64_t seed, int32_t* color_out,
+                         int32_t* num_colors_out, void* workspace, size_t ws_bytes, void* stream, int32_t reuse,
+                         adg_batch_config_t* best_out, float* best_ms_out) {
+  int rc = check_batch(b);
+  if (rc) return rc;
+  if (!best_out) return ADG_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  const TuneKey key = tune_key(b);
+  if (reuse) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    for (const TuneEntry& e : g_tune)
+      if (e.key == key) {
+        *best_out = e.cfg;
+        if (best_ms_out) *best_ms_out = e.ms;
+        return ADG_OK;
+      }
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return ADG_ERR_HIP;
+  }
+  auto run = [&](const adg_batch_config_t& c, float* ms) -> int {
+    if (hipEventRecord(e0, s) != hipSuccess) return ADG_ERR_HIP;
+    int r = color_graph_batched(b, eps_num, eps_den, seed, color_out, nullptr, num_colors_out, nullptr, &c,
+                                workspace, ws_bytes, stream);
+    if (r) return r;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+      return ADG_ERR_HIP;
+    return ADG_OK;
+  };
+  adg_batch_config_t best = adg_batched_default_config();
+  float best_ms = 0.f;
+  // warm-up (first-launch costs), then every candidate shape once
+  rc = run(best, &best_ms);
+  if (!rc) rc = run(best, &best_ms);
+  static const int shapes[][2] = {{256, 1}, {256, 2}, {256, 4}, {256, 8}, {512, 1},
+                                  {512, 2}, {512, 4}, {1024, 1}, {1024, 2}};
+  for (const auto& sh : shapes) {
+    if (rc) break;
+    adg_batch_config_t c{sh[0], sh[1], ADG_SCHED_LPT};
+    float ms = 0.f;
+    rc = run(c, &ms);
+    if (!rc && ms < best_ms) {
+      best = c;
+      best_ms = ms;
+    }
+  }
+  if (!rc) {
+    adg_batch_config_t c = best;
+    c.schedule = ADG_SCHED_NATURAL;
+    float ms = 0.f;
+    rc = run(c, &ms);
+    if (!rc && ms < best_ms) {
+      best = c;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    bool found = false;
+    for (TuneEntry& e : g_tune)
+      if (e.key == key) {
+        e.cfg = best;
+        e.ms = best_ms;
+        found = true;
+      }
+    if (!found) g_tune.push_back({key, best, best_ms});
+  }
+  *best_out = best;
+  if (best_ms_out) *best_ms_out = best_ms;
+  return ADG_OK;
+}
+
+}  // extern "C"

@@ -44,6 +44,7 @@
 
 #include "../../include/adg.h"
 #include "adg_device.h"
+#include "adg_host.h"
 
 namespace adg {
 
@@ -1392,13 +1393,10 @@ __global__ void k_validate(int n, long long nnz, const long long* rp, const int*
 
 using namespace adg;
 
-namespace {
-
-inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+namespace adg {
 
 // ---- optional per-kernel timing with HIP events on the launch stream
-enum KClass { KC_INIT, KC_STATS, KC_COUNT, KC_SCAN, KC_SCATTER, KC_UPDATE, KC_PART1, KC_JP_PREP, KC_JP, KC_FINISH,
-              KC_BATCH, KC_JP_NARROW, KC_NUM };
+namespace {
 const char* kclass_names[KC_NUM] = {"init", "stats", "count", "scan", "scatter", "update", "part1",
                                     "jp_prep", "jp", "finish", "batched", "jp_narrow"};
 struct ProfRec {
@@ -1420,28 +1418,33 @@ hipEvent_t prof_event() {
   if (hipEventCreate(&e) != hipSuccess) return nullptr;
   return e;
 }
+}  // namespace
 
-struct ProfScope {
-  int cls;
-  hipStream_t s;
-  hipEvent_t a = nullptr;
-  ProfScope(int c, hipStream_t st) : cls(c), s(st) {
-    if (g_prof_mask & (1u << c)) {
-      std::lock_guard<std::mutex> g(g_prof_mu);
-      a = prof_event();
-      if (a) (void)hipEventRecord(a, s);
-    }
+hipEvent_t prof_begin(int cls, hipStream_t s) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  if (!(g_prof_mask & (1u << cls))) return nullptr;
+  hipEvent_t a = prof_event();
+  if (a && hipEventRecord(a, s) != hipSuccess) {
+    g_pool.push_back(a);
+    return nullptr;
   }
-  ~ProfScope() {
-    if (!a) return;
-    std::lock_guard<std::mutex> g(g_prof_mu);
-    hipEvent_t b = prof_event();
-    if (!b) return;
-    (void)hipEventRecord(b, s);
-    g_prof.push_back({cls, a, b});
+  return a;
+}
+
+void prof_end(int cls, hipStream_t s, hipEvent_t a) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  hipEvent_t b = prof_event();
+  if (!b || hipEventRecord(b, s) != hipSuccess) {
+    g_pool.push_back(a);
+    if (b) g_pool.push_back(b);
+    return;
   }
-};
-#define TIMED(cls, s) ProfScope prof_scope_##__LINE__(cls, s)
+  g_prof.push_back({cls, a, b});
+}
+
+}  // namespace adg
+
+namespace {
 
 struct Layout {
   size_t ctrl, bcount, boff, bsum, xpart, D, status, UL0, UL1, ORD, roundN, round, dag, npred, nsr, word, F0, F1, H0,
@@ -1489,15 +1492,6 @@ Layout make_layout(int64_t n, int64_t nnz) {
   L.ext = take(8 * L.ext_words);
   L.total = off;
   return L;
-}
-
-uint32_t hash_key_from_seed(uint64_t seed) {
-  // low 32 bits of the first SplitMix64 output from state `seed`
-  uint64_t z = seed + 0x9e3779b97f4a7c15ULL;
-  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
-  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
-  z ^= z >> 31;
-  return (uint32_t)z;
 }
 
 int check_graph(const adg_csr_t* g) {
@@ -1567,11 +1561,6 @@ Params make_params(const adg_csr_t* g, void* ws, uint64_t p, uint64_t q, uint64_
   P.max_rounds = (int)std::min<long long>(bound, 0x7fffffff);
   return P;
 }
-
-#define HIPCHK(x)                              \
-  do {                                         \
-    if ((x) != hipSuccess) return ADG_ERR_HIP; \
-  } while (0)
 
 int* pinned_flags() {
   static int* h = nullptr;

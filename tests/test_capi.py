@@ -55,3 +55,33 @@ def test_no_cpu_fallback():
     g = None
     with pytest.raises(RuntimeError):
         pkg.Graph([0, 0], [])
+
+
+def test_batched_entry_points_reject_bad_arguments_without_gpu():
+    import paper_2008_11321_amd.batched as bt
+    L = bt._lib()
+    assert L.adg_batched_workspace_bytes(-1, 0, 0) == 0
+    assert 0 < L.adg_batched_workspace_bytes(4, 100, 1000) < L.adg_batched_workspace_bytes(4, 10_000, 100_000)
+    c = L.adg_batched_default_config()
+    assert c.block_threads in (256, 512, 1024) and c.blocks_per_cu >= 1
+    args = (1, 10, 0, None, None, None, None)
+    assert L.color_graph_batched(None, *args, None, None, 0, None) == -1
+    # sizes without arrays
+    b = bt._Batch(2, 10, 20, None, None, None)
+    assert L.color_graph_batched(ctypes.byref(b), *args, None, None, 0, None) == -1
+    # an empty batch is a no-op that needs no device memory
+    b0 = bt._Batch(0, 0, 0, None, None, None)
+    assert L.color_graph_batched(ctypes.byref(b0), *args, None, None, 0, None) == 0
+    # a batch of two graphs (fake, never dereferenced on the host)
+    fake = 1 << 20
+    b2 = bt._Batch(2, 10, 20, fake, fake, fake)
+    out = (1, 10, 0, fake, None, fake, None)
+    bad = bt.BatchConfig(300, 1, 0)
+    assert L.color_graph_batched(ctypes.byref(b2), *out, ctypes.byref(bad), fake, 1 << 30, None) == -1
+    bad = bt.BatchConfig(256, 0, 0)
+    assert L.color_graph_batched(ctypes.byref(b2), *out, ctypes.byref(bad), fake, 1 << 30, None) == -1
+    good = bt.BatchConfig(256, 2, 1)
+    assert L.color_graph_batched(ctypes.byref(b2), *out, ctypes.byref(good), fake, 16, None) == -2
+    assert L.color_graph_batched(ctypes.byref(b2), *out, ctypes.byref(good), fake + 8, 1 << 30, None) == -2
+    assert L.color_graph_batched(ctypes.byref(b2), -1, 10, 0, fake, None, fake, None, None, fake, 1 << 30,
+                                 None) == -1
