@@ -6,11 +6,20 @@ Default workload: R-MAT scale 22, edge factor 16, (a, b, c) = (0.57, 0.19,
 configuration the headline metric is quoted on.  One step = one color_graph
 call (all of ADG and JP) on the graph already resident in HBM.
 
+Other workloads (--workload): R-MAT scale 26 at eps 1/100, 1/10, 1/2 (seed 3),
+the Erdos-Renyi parity graph, and the batched workload (4096 Chung-Lu graphs
+in one color_graph_batched launch, compared with 4096 plain color_graph
+calls on the same GPU).
+
 Prints one JSON line.  Extra fields:
   roofline      the dominant kernel's algorithmic bytes per launch over its
                 average launch time, measured with HIP events on the launch
                 stream during the timed steps, against the 8 TB/s HBM peak;
-  cpu_baseline  the CPU oracle (serial C) on the same graph, one run.
+                `traffic` is the HBM bytes per launch from the committed
+                profiler counters when they were taken on the current kernel
+                sources, else null;
+  cpu_baseline  the CPU oracle (serial C) on the same workload, or on the
+                bounded sample named in `sample`.
 """
 import argparse
 import hashlib
@@ -27,11 +36,25 @@ METRIC = "edges colored/sec (ADG+JP) + HBM GB/s; batched/served vs plain per-gra
 
 WORKLOADS = {
     "rmat22": dict(kind="rmat", scale=22, edge_factor=16, eps=(1, 10), seed=2),
-    "rmat26": dict(kind="rmat", scale=26, edge_factor=16, eps=(1, 10), seed=3),
-    "rmat26_e001": dict(kind="rmat", scale=26, edge_factor=16, eps=(1, 100), seed=3),
-    "rmat26_e05": dict(kind="rmat", scale=26, edge_factor=16, eps=(1, 2), seed=3),
+    "rmat26": dict(kind="rmat", scale=26, edge_factor=16, eps=(1, 10), seed=3, cpu_sample_scale=24),
+    "rmat26_e001": dict(kind="rmat", scale=26, edge_factor=16, eps=(1, 100), seed=3, cpu_sample_scale=24),
+    "rmat26_e05": dict(kind="rmat", scale=26, edge_factor=16, eps=(1, 2), seed=3, cpu_sample_scale=24),
     "er": dict(kind="er", n=10_000, mean_deg=10.0, eps=(1, 100), seed=1),
+    "batched": dict(kind="batched", num_graphs=4096, eps=(1, 10), seed=4),
+    "serving": dict(kind="serving", requests=240, eps=(1, 10), seed=5, load=0.7),
 }
+
+# kernel sources each timed kernel class is built from (for matching
+# committed counter records to the current code)
+KERNEL_SOURCES = {
+    "k_jp_narrow+k_jp_grid": ["adg_single.hip", "adg_device.h"],
+    "k_update": ["adg_single.hip", "adg_device.h"],
+    "k_batched": ["adg_batched.hip", "adg_device.h"],
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
 
 
 def make_graph(w):
@@ -49,19 +72,29 @@ def algorithmic_bytes(cls, n, nnz, st):
       read-modify-write (8).
     jp: per vertex the row_ptr pair (16), |pred| (4), the colour write (4) and
       a queue entry (4); per successor edge (m of them) the partitioned
-      neighbour id (4) and the 8-byte word read-modify-write (16)."""
+      neighbour id (4) and the 8-byte word read-modify-write (16).
+    batched (ADG and JP of every graph in one kernel): per vertex-round of ADG
+      the active-list entry, D, the output-list entry and the round (16);
+      per vertex the round-1 degree (8), the row_ptr pair, |pred|, JP word and
+      extension offset in UPDATE (32) and the level-list entry written and
+      read, row_ptr pair, |pred| and colour in JP (40); per adjacency entry the
+      neighbour id, its round and the partitioned copy (12); per cut edge the
+      D read-modify-write (8); per successor edge the id and the word
+      read-modify-write (20)."""
     m = nnz // 2
     if cls == "update":
         return 32 * n + 9 * nnz + 8 * st["cut_edges"]
     if cls == "jp":
         return 28 * n + 20 * m
+    if cls == "batched":
+        return 16 * st["sum_active"] + 80 * n + 12 * nnz + 8 * st["cut_edges"] + 20 * m
     return None
 
 
-def source_digest():
+def source_digest(kernel):
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2008_11321_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in sorted(KERNEL_SOURCES[kernel]):
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode())
             h.update(fh.read())
@@ -77,18 +110,292 @@ def measured_traffic(kernel, workload):
             rec = json.load(fh).get("%s/%s" % (kernel, workload))
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("source_digest") != source_digest():
+    if not rec or rec.get("source_digest") != source_digest(kernel):
         return None
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(rp, col, eps, seed, m):
+def cpu_baseline_graph(w, rp, col, m):
+    """The oracle on the workload's graph; for RMAT-26 on the same generator
+    at a smaller scale (a bounded sample of about 10-30 s of CPU work)."""
     import oracle
+    sample = "whole graph"
+    if "cpu_sample_scale" in w:
+        import graphgen
+        rp, col = graphgen.rmat_config(w["cpu_sample_scale"], seed=w["seed"], edge_factor=w["edge_factor"])
+        m = col.size // 2
+        sample = "R-MAT scale %d, same generator parameters and seed (m = %d)" % (w["cpu_sample_scale"], m)
     t0 = time.perf_counter()
-    oracle.color_graph(rp, col, eps[0], eps[1], seed)
+    oracle.color_graph(rp, col, w["eps"][0], w["eps"][1], w["seed"])
     dt = time.perf_counter() - t0
     return {"value": m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": "whole graph, one serial run of the C oracle (ADG then greedy JP), %.2f s" % dt}
+            "sample": "%s: one serial run of the C oracle (ADG then greedy JP), %.2f s" % (sample, dt)}
+
+
+def calibration_copy(mib):
+    """A plain device copy of known size, issued before the run so that
+    profiler byte counters can be scaled against it."""
+    import torch
+    if mib <= 0:
+        return
+    ca = torch.ones(mib << 20, dtype=torch.uint8, device="cuda:0")
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    torch.cuda.synchronize()
+    del ca, cb
+
+
+def roofline_record(dom, tot_ms, launches, steps, step_bytes, kname, workload, extra=None):
+    per_launch_ms = tot_ms / launches
+    launches_per_step = launches / steps
+    bytes_per_launch = step_bytes / launches_per_step
+    achieved = bytes_per_launch / (per_launch_ms * 1e-3) / 1e9
+    r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname, workload), "kernel": kname,
+         "avg_launch_ms": round(per_launch_ms, 4), "launches_per_step": launches_per_step,
+         "algorithmic_bytes_per_launch": int(bytes_per_launch)}
+    if extra:
+        r.update(extra)
+    return r
+
+
+def run_single(args, w):
+    import torch
+
+    import paper_2008_11321_amd as adg
+
+    t0 = time.time()
+    rp, col = make_graph(w)
+    n, nnz = rp.size - 1, col.size
+    m = nnz // 2
+    log("workload %s: n=%d nnz=%d (generated in %.1f s)" % (args.workload, n, nnz, time.time() - t0))
+    g = adg.Graph(rp, col, device="cuda:0")
+    ws = torch.empty(adg.workspace_bytes(n, nnz), dtype=torch.uint8, device="cuda:0")
+    out = (torch.empty(n, dtype=torch.int32, device="cuda:0"), torch.empty(n, dtype=torch.int32, device="cuda:0"),
+           torch.zeros(1, dtype=torch.int32, device="cuda:0"), torch.zeros(1, dtype=torch.int32, device="cuda:0"))
+    p, q = w["eps"]
+    seed = w["seed"]
+
+    def step():
+        adg.color_graph(g, p, q, seed, workspace=ws, out=out)
+
+    calibration_copy(args.calib_mib)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warm-up done")
+    adg.profile_read()  # drop anything recorded so far
+    adg.profile_enable(["update", "jp", "jp_narrow"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    adg.profile_enable([])
+    prof = adg.profile_read()
+    st = adg.get_stats(ws)
+    log("timed steps done: %.3f ms/step" % (dt * 1000 / args.steps))
+
+    # dominant kernel class: largest share of the timed region.  JP runs as
+    # single-block steps (jp_narrow) and grid-wide steps (jp); its algorithmic
+    # bytes are charged to the two together.
+    jp_ms = prof.get("jp", (0, 0))[0] + prof.get("jp_narrow", (0, 0))[0]
+    jp_launches = prof.get("jp", (0, 0))[1] + prof.get("jp_narrow", (0, 0))[1]
+    upd_ms, upd_launches = prof.get("update", (0.0, 0))
+    if jp_ms >= upd_ms:
+        dom, tot_ms, launches, kname = "jp", jp_ms, jp_launches, "k_jp_narrow+k_jp_grid"
+    else:
+        dom, tot_ms, launches, kname = "update", upd_ms, upd_launches, "k_update"
+    roofline = roofline_record(dom, tot_ms, launches, args.steps, algorithmic_bytes(dom, n, nnz, st), kname,
+                               args.workload,
+                               {"phase_ms_per_step": {"update": round(upd_ms / args.steps, 3),
+                                                      "jp": round(jp_ms / args.steps, 3)}})
+    if args.breakdown:
+        adg.profile_enable(adg.KERNEL_CLASSES)
+        step()
+        torch.cuda.synchronize()
+        adg.profile_enable([])
+        for k, (ms, cnt) in sorted(adg.profile_read().items(), key=lambda kv: -kv[1][0]):
+            log("  %-8s %8.3f ms  %4d launches" % (k, ms, cnt))
+        log("  stats", st)
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline_graph(w, rp, col, m)
+    cfg = {"workload": args.workload, "graph": w["kind"], "n": n, "nnz": nnz, "m": m, "eps": "%d/%d" % (p, q),
+           "seed": seed, "rounds": st["num_rounds"], "colors": st["num_colors"]}
+    if w["kind"] == "rmat":
+        cfg.update(scale=w["scale"], edge_factor=w["edge_factor"], abcd=[0.57, 0.19, 0.19, 0.05])
+    return m / (dt / args.steps), dt * 1000 / args.steps, cfg, roofline, cpu, {}
+
+
+def run_batched(args, w):
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2008_11321_amd as adg
+    import paper_2008_11321_amd.batched as bt
+
+    t0 = time.time()
+    graphs = graphgen.batched_graphs(w["num_graphs"], seed=w["seed"])
+    batch = bt.Batch(graphs, device="cuda:0")
+    m = batch.total_nnz // 2
+    log("workload batched: %d graphs, total n=%d nnz=%d (generated in %.1f s)" %
+        (batch.num_graphs, batch.total_n, batch.total_nnz, time.time() - t0))
+    p, q = w["eps"]
+    seed = w["seed"]
+    ws = torch.empty(bt.batched_workspace_bytes(batch.num_graphs, batch.total_n, batch.total_nnz),
+                     dtype=torch.uint8, device="cuda:0")
+    out = (torch.empty(batch.total_n, dtype=torch.int32, device="cuda:0"), None,
+           torch.zeros(batch.num_graphs, dtype=torch.int32, device="cuda:0"),
+           torch.zeros(batch.num_graphs, dtype=torch.int32, device="cuda:0"))
+    calibration_copy(args.calib_mib)
+    cfg_b, tune_ms = bt.autotune(batch, p, q, seed, workspace=ws, out=(out[0], out[2]))
+    log("autotuned launch shape %s (%.3f ms)" % (cfg_b, tune_ms))
+
+    def step():
+        bt.color_graph_batched(batch, p, q, seed, workspace=ws, config=cfg_b, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    adg.profile_read()
+    adg.profile_enable(["batched"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    adg.profile_enable([])
+    prof = adg.profile_read()
+    st = bt.batched_stats(ws)
+    assert st["error"] == 0, st
+    log("timed steps done: %.3f ms/step" % (dt * 1000 / args.steps))
+    b_ms, b_launches = prof["batched"]
+    roofline = roofline_record("batched", b_ms, b_launches, args.steps,
+                               algorithmic_bytes("batched", batch.total_n, batch.total_nnz, st), "k_batched",
+                               args.workload)
+
+    # the same graphs as plain per-graph color_graph calls on one stream
+    # (graphs resident in HBM, one workspace sized for the largest graph)
+    gl = [adg.Graph(rp, col, device="cuda:0") for rp, col in graphs]
+    big = max(range(len(gl)), key=lambda i: (gl[i].n, gl[i].nnz))
+    wsp = torch.empty(max(adg.workspace_bytes(x.n, x.nnz) for x in gl), dtype=torch.uint8, device="cuda:0")
+    nmax = max(x.n for x in gl)
+    po = (torch.empty(max(nmax, 1), dtype=torch.int32, device="cuda:0"), None,
+          torch.zeros(1, dtype=torch.int32, device="cuda:0"), torch.zeros(1, dtype=torch.int32, device="cuda:0"))
+    adg.color_graph(gl[big], p, q, seed, workspace=wsp, out=po)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for x in gl:
+        adg.color_graph(x, p, q, seed, workspace=wsp, out=po)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    log("plain per-graph pass: %.1f ms" % (plain_s * 1000))
+    # spot check: the last plain call equals its graph's slice of the batched output
+    assert np.array_equal(po[0][:gl[-1].n].cpu().numpy(), batch.split(out[0])[-1])
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        for rp, col in graphs:
+            oracle.color_graph(rp, col, p, q, seed)
+        cdt = time.perf_counter() - t0
+        cpu = {"value": m / cdt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+               "sample": "all %d graphs, one serial run of the C oracle each, %.2f s" % (len(graphs), cdt)}
+    cfg = {"workload": "batched", "graph": "chung-lu x %d" % batch.num_graphs, "num_graphs": batch.num_graphs,
+           "n": batch.total_n, "nnz": batch.total_nnz, "m": m, "eps": "%d/%d" % (p, q), "seed": seed,
+           "n_range": [100, 50000], "mean_degree_range": [8, 32], "gamma": 2.3, "max_rounds": st["num_rounds"],
+           "max_colors": st["num_colors"], "launch_shape": cfg_b.as_dict()}
+    extra = {"plain_per_graph": {"value": m / plain_s, "unit": "edges/s", "ms_per_pass": plain_s * 1000,
+                                 "calls": len(gl)},
+             "speedup_vs_plain": (m / (dt / args.steps)) / (m / plain_s)}
+    return m / (dt / args.steps), dt * 1000 / args.steps, cfg, roofline, cpu, extra
+
+
+def run_serving(args, w):
+    """Poisson stream of colouring requests (70% ER, 25% Chung-Lu, 5% R-MAT)
+    through the serving loop.  The saturation rate is measured first (every
+    request submitted at once); the timed stream then arrives at `load` times
+    that rate.  The plain comparison colours the same requests one at a time
+    (one worker, no grouping)."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2008_11321_amd.serving as sv
+
+    t0 = time.time()
+    specs = graphgen.serving_specs(w["requests"], seed=w["seed"])
+    graphs = []
+    for k, sp in enumerate(specs):
+        graphs.append(graphgen.serving_graph(sp))
+        if k % 40 == 39:
+            log("generated %d/%d requests" % (k + 1, len(specs)))
+    n_tot = sum(rp.size - 1 for rp, _ in graphs)
+    nnz_tot = sum(col.size for _, col in graphs)
+    m = nnz_tot // 2
+    kinds = {k: sum(1 for s in specs if s[0] == k) for k in ("er", "chung_lu", "rmat")}
+    log("workload serving: %d requests %s, total n=%d nnz=%d (generated in %.1f s)" %
+        (len(graphs), kinds, n_tot, nnz_tot, time.time() - t0))
+    p, q = w["eps"]
+    seed = w["seed"]
+    arena = 24 << 30
+    opts = dict(eps=(p, q), seed=seed, workers=4, small_nnz=1 << 20, max_group=64, max_bypass=16)
+    with sv.Server(arena, **opts) as srv:
+        sv.replay(srv, graphs[:min(16, len(graphs))])   # warm-up
+        sat = sv.latency_summary(sv.replay(srv, graphs))
+        log("saturation: %.1f req/s, %.3g edges/s" % (sat["requests_per_s"], sat["edges_per_s"]))
+        qps = w["load"] * sat["requests_per_s"]
+        arrivals = graphgen.poisson_arrivals(len(graphs), qps, seed=seed)
+        c0 = srv.counters()
+        res = sv.replay(srv, graphs, arrivals)
+        c1 = srv.counters()
+        served = sv.latency_summary(res)
+        log("poisson at %.1f req/s: p50 %.2f ms p99 %.2f ms, %.3g edges/s" %
+            (qps, served["p50_ms"], served["p99_ms"], served["edges_per_s"]))
+    assert all(r["status"] == 0 for r in res)
+    with sv.Server(arena, eps=(p, q), seed=seed, workers=1, small_nnz=-1, max_group=1, max_bypass=0) as srv:
+        sv.replay(srv, graphs[:min(16, len(graphs))])
+        plain_res = sv.replay(srv, graphs)
+    plain = sv.latency_summary(plain_res)
+    log("plain one-at-a-time: %.3g edges/s" % plain["edges_per_s"])
+    for a, b in zip(res, plain_res):
+        assert np.array_equal(a["color"], b["color"])
+    d = {k: c1[k] - c0[k] for k in c1}
+    alg = 16 * d["sum_active"] + 80 * d["vertices"] + 12 * d["entries"] + 8 * d["cut_edges"] + 10 * d["entries"]
+    achieved = alg / served["span_s"] / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "all kernels of the stream (overlapping on %d streams)" % opts["workers"],
+                "algorithmic_bytes": int(alg), "over": "wall time of the stream"}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        k = 0
+        me = 0
+        while k < len(graphs) and time.perf_counter() - t0 < 15.0:
+            oracle.color_graph(graphs[k][0], graphs[k][1], p, q, seed)
+            me += graphs[k][1].size // 2
+            k += 1
+        cdt = time.perf_counter() - t0
+        cpu = {"value": me / cdt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+               "sample": "the first %d requests in arrival order, one serial oracle run each, %.2f s" % (k, cdt)}
+    cfg = {"workload": "serving", "requests": len(graphs), "mix": kinds, "n": n_tot, "nnz": nnz_tot, "m": m,
+           "eps": "%d/%d" % (p, q), "seed": seed, "offered_qps": qps, "load_vs_saturation": w["load"],
+           "server": dict(opts, arena_bytes=arena, eps="%d/%d" % (p, q))}
+    extra = {"latency_ms": {"p50": served["p50_ms"], "p99": served["p99_ms"], "mean": served["mean_ms"],
+                            "queue_p50": served["queue_p50_ms"]},
+             "saturation": {"requests_per_s": sat["requests_per_s"], "edges_per_s": sat["edges_per_s"],
+                            "p50_ms": sat["p50_ms"], "p99_ms": sat["p99_ms"]},
+             "grouped_requests": d["grouped_requests"], "grouped_launches": d["grouped_jobs"],
+             "plain_per_graph": {"value": plain["edges_per_s"], "unit": "edges/s", "p50_ms": plain["p50_ms"],
+                                 "p99_ms": plain["p99_ms"]},
+             "speedup_vs_plain_saturated": sat["edges_per_s"] / plain["edges_per_s"]}
+    return served["edges_per_s"], served["span_s"] * 1000, cfg, roofline, cpu, extra
 
 
 def main():
@@ -107,99 +414,19 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(use --gpus 1)", file=sys.stderr)
         sys.exit(2)
-
-    import numpy as np
-    import torch
-
-    import paper_2008_11321_amd as adg
-
     w = WORKLOADS[args.workload]
-    t0 = time.time()
-    rp, col = make_graph(w)
-    gen_s = time.time() - t0
-    n, nnz = rp.size - 1, col.size
-    m = nnz // 2
-    print("workload %s: n=%d nnz=%d (generated in %.1f s)" % (args.workload, n, nnz, gen_s), file=sys.stderr,
-          flush=True)
-    g = adg.Graph(rp, col, device="cuda:0")
-    ws = torch.empty(adg.workspace_bytes(n, nnz), dtype=torch.uint8, device="cuda:0")
-    out = (torch.empty(n, dtype=torch.int32, device="cuda:0"), torch.empty(n, dtype=torch.int32, device="cuda:0"),
-           torch.zeros(1, dtype=torch.int32, device="cuda:0"), torch.zeros(1, dtype=torch.int32, device="cuda:0"))
-    p, q = w["eps"]
-    seed = w["seed"]
-
-    def step():
-        adg.color_graph(g, p, q, seed, workspace=ws, out=out)
-
-    if args.calib_mib > 0:
-        # reference for counter scaling: reads and writes calib_mib MiB once
-        ca = torch.ones(args.calib_mib << 20, dtype=torch.uint8, device="cuda:0")
-        cb = torch.empty_like(ca)
-        cb.copy_(ca)
-        torch.cuda.synchronize()
-        del ca, cb
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    st = adg.get_stats(ws)
-    adg.profile_read()  # drop anything recorded so far
-    adg.profile_enable(["update", "jp", "jp_narrow"])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    adg.profile_enable([])
-    prof = adg.profile_read()
-    st = adg.get_stats(ws)
-    ms_per_step = dt * 1000 / args.steps
-    value = m / (dt / args.steps)
-
-    # dominant kernel class: largest share of the timed region.  JP runs as
-    # single-block steps (jp_narrow) and grid-wide steps (jp); its algorithmic
-    # bytes are charged to the two together.
-    jp_ms = prof.get("jp", (0, 0))[0] + prof.get("jp_narrow", (0, 0))[0]
-    jp_launches = prof.get("jp", (0, 0))[1] + prof.get("jp_narrow", (0, 0))[1]
-    upd_ms, upd_launches = prof.get("update", (0.0, 0))
-    if jp_ms >= upd_ms:
-        dom, tot_ms, launches = "jp", jp_ms, jp_launches
+    if w["kind"] == "batched":
+        value, ms_per_step, cfg, roofline, cpu, extra = run_batched(args, w)
+    elif w["kind"] == "serving":
+        value, ms_per_step, cfg, roofline, cpu, extra = run_serving(args, w)
+        args.steps, args.warmup = 1, 1   # one timed stream after one warm-up pass
     else:
-        dom, tot_ms, launches = "update", upd_ms, upd_launches
-    per_launch_ms = tot_ms / launches
-    launches_per_step = launches / args.steps
-    step_bytes = algorithmic_bytes(dom, n, nnz, st)
-    bytes_per_launch = step_bytes / launches_per_step
-    achieved = bytes_per_launch / (per_launch_ms * 1e-3) / 1e9
-    kname = "k_jp_narrow+k_jp_grid" if dom == "jp" else "k_update"
-    traffic = measured_traffic(kname, args.workload)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
-                "avg_launch_ms": round(per_launch_ms, 4), "launches_per_step": launches_per_step,
-                "algorithmic_bytes_per_launch": int(bytes_per_launch),
-                "phase_ms_per_step": {"update": round(upd_ms / args.steps, 3), "jp": round(jp_ms / args.steps, 3)}}
-    if args.breakdown:
-        adg.profile_enable(adg.KERNEL_CLASSES)
-        step()
-        torch.cuda.synchronize()
-        adg.profile_enable([])
-        for k, (ms, cnt) in sorted(adg.profile_read().items(), key=lambda kv: -kv[1][0]):
-            print("  %-8s %8.3f ms  %4d launches" % (k, ms, cnt), file=sys.stderr)
-        print("  stats", st, file=sys.stderr)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(rp, col, w["eps"], seed, m)
-
-    cfg = {"workload": args.workload, "graph": w["kind"], "n": n, "nnz": nnz, "m": m, "eps": "%d/%d" % (p, q),
-           "seed": seed, "rounds": st["num_rounds"], "colors": st["num_colors"]}
-    if w["kind"] == "rmat":
-        cfg.update(scale=w["scale"], edge_factor=w["edge_factor"], abcd=[0.57, 0.19, 0.19, 0.05])
+        value, ms_per_step, cfg, roofline, cpu, extra = run_single(args, w)
     rec = {"metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "int32", "data": "synthetic", "config": cfg, "roofline": roofline,
            "cpu_baseline": cpu}
+    rec.update(extra)
     print(json.dumps(rec), flush=True)
 
 

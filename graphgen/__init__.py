@@ -120,6 +120,45 @@ def batched_graphs(num_graphs=4096, seed=4, size_scale=1.0):
     return chung_lu_many([(n, min(k, n - 1.0), s) for n, k, s in specs], 2.3)
 
 
+def serving_specs(count, seed=5):
+    """Request mix of the serving workload: 70% Erdos-Renyi (n log-uniform
+    in [1e3, 1e5], mean degree 10), 25% Chung-Lu (n log-uniform in [1e4, 1e6],
+    mean degree 16, exponent 2.3), 5% R-MAT (scale uniform in 20..23, edge
+    factor 16).  Returns [(kind, size, gen_seed)], size = n or the R-MAT scale."""
+    key = stream_seed(seed, 0x5E7E)
+    out = []
+    for i in range(count):
+        u = uniform01(key, 4 * i)
+        gs = stream_seed(seed, 0x6E, i)
+        if u < 0.70:
+            out.append(("er", log_uniform_int(uniform01(key, 4 * i + 1), 1_000, 100_000), gs))
+        elif u < 0.95:
+            out.append(("chung_lu", log_uniform_int(uniform01(key, 4 * i + 1), 10_000, 1_000_000), gs))
+        else:
+            out.append(("rmat", 20 + min(3, int(4 * uniform01(key, 4 * i + 1))), gs))
+    return out
+
+
+def serving_graph(spec):
+    kind, size, gs = spec
+    if kind == "er":
+        return erdos_renyi(size, min(1.0, 10.0 / max(size - 1, 1)), gs)
+    if kind == "chung_lu":
+        return chung_lu(size, 16.0, 2.3, gs)
+    return rmat(size, 16, 0.57, 0.19, 0.19, gs)
+
+
+def poisson_arrivals(count, qps, seed=5):
+    """Arrival times (seconds from 0) of a Poisson stream at rate qps."""
+    key = stream_seed(seed, 0xA771)
+    t = 0.0
+    out = []
+    for i in range(count):
+        t += -math.log1p(-uniform01(key, i)) / qps
+        out.append(t)
+    return out
+
+
 def chung_lu_weights(n, mean_deg, gamma=2.3):
     w = np.empty(int(n), dtype=np.float64)
     if _load().gg_chung_lu_weights(int(n), float(mean_deg), float(gamma), w.ctypes.data) != 0:

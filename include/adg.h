@@ -15,6 +15,8 @@
  *                  "Optimizations and Implementation".
  *   - color_graph_batched: JP-ADG on many independent graphs in one
  *                  persistent launch, each graph coloured exactly as alone.
+ *   - adg_server_*: a serving loop with continuous batching over a device
+ *                  arena.
  *
  * Conventions shared by every entry point:
  *   - Graphs are simple and undirected (symmetric adjacency, no self-loops,
@@ -61,7 +63,8 @@ enum {
   ADG_ERR_WORKSPACE = -2,   /* workspace missing, misaligned or too small */
   ADG_ERR_HIP = -3,         /* a HIP runtime call failed */
   ADG_ERR_INTERNAL = -4,    /* round-count watchdog tripped or device-side check failed */
-  ADG_ERR_UNSUPPORTED = -5  /* input outside the supported range (see entry point) */
+  ADG_ERR_UNSUPPORTED = -5  /* input outside the supported range: nnz / 64 + 2 n >= 2^32 for the
+                               single-graph calls; a serving request larger than the arena */
 };
 
 /* CSR view of one graph; all pointers are device pointers. */
@@ -101,8 +104,7 @@ int adg_order(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, int32_t* rou
  * color_out[v] >= 1 and num_colors_out[0] (device int32).  The colouring
  * equals sequential greedy colouring in decreasing priority order: each v
  * gets the smallest colour not used by its higher-priority neighbours.
- * Errors: ADG_ERR_ARG, ADG_ERR_WORKSPACE, ADG_ERR_HIP, ADG_ERR_UNSUPPORTED
- * (a vertex with 2^24 or more higher-priority neighbours). */
+ * Errors: ADG_ERR_ARG, ADG_ERR_WORKSPACE, ADG_ERR_HIP. */
 int jp_color(const adg_csr_t* g, const int32_t* round, uint64_t seed, int32_t* color_out,
              int32_t* num_colors_out, void* workspace, size_t ws_bytes, void* stream);
 
@@ -159,16 +161,19 @@ adg_batch_config_t adg_batched_default_config(void);
  * int32.  config may be NULL.  Fully asynchronous: no host synchronisation,
  * no memset, so the call can be recorded by stream capture.  Device-side
  * errors (a broken DAG, a round-count overrun) are reported by
- * adg_batched_error.  Errors returned: ADG_ERR_ARG, ADG_ERR_WORKSPACE,
+ * adg_batched_get_stats.  Errors returned: ADG_ERR_ARG, ADG_ERR_WORKSPACE,
  * ADG_ERR_HIP. */
 int color_graph_batched(const adg_batch_t* b, int32_t eps_num, int32_t eps_den, uint64_t seed,
                         int32_t* color_out, int32_t* round_out, int32_t* num_colors_out,
                         int32_t* num_rounds_out, const adg_batch_config_t* config, void* workspace,
                         size_t ws_bytes, void* stream);
 
-/* Device-side error flag of the last color_graph_batched call on this
- * workspace (0 = none, else an ADG_ERR_* code).  Synchronises `stream`. */
-int adg_batched_error(const void* workspace, size_t ws_bytes, int32_t* host_error, void* stream);
+/* Counters of the last color_graph_batched call on this workspace, summed
+ * over the batch (num_rounds and num_colors: the largest of any graph;
+ * frontier: vertices of JP's first level; error: the device-side error flag,
+ * 0 = none, else an ADG_ERR_* code -- a broken DAG or a round-count
+ * overrun).  Synchronises `stream`. */
+int adg_batched_get_stats(const void* workspace, size_t ws_bytes, adg_stats_t* host_out, void* stream);
 
 /* Launch-shape autotuner: runs color_graph_batched on this batch once per
  * candidate shape (block_threads x blocks_per_cu, then the schedule order for
@@ -180,6 +185,71 @@ int adg_batched_error(const void* workspace, size_t ws_bytes, int32_t* host_erro
 int adg_batched_autotune(const adg_batch_t* b, int32_t eps_num, int32_t eps_den, uint64_t seed,
                          int32_t* color_out, int32_t* num_colors_out, void* workspace, size_t ws_bytes,
                          void* stream, int32_t reuse, adg_batch_config_t* best_out, float* best_ms_out);
+
+/* ---- Serving: a request loop with continuous batching.
+ *
+ * The server colours independent graphs submitted from the host (CSR in host
+ * memory) with JP-ADG, each exactly as a standalone color_graph call would.
+ * Requests wait in arrival order; an idle worker admits the next job that
+ * fits into the device arena: a large request (nnz > small_nnz) alone, or a
+ * group of up to max_group consecutive small requests packed into one
+ * color_graph_batched launch.  Each worker has its own stream (default
+ * priority), so jobs admitted while others run overlap on the device; arena
+ * space and workers come free as jobs complete.  The oldest waiting request
+ * may be overtaken by later, smaller ones at most max_bypass times.  The
+ * arena is one caller-owned device buffer (256-byte aligned); the server
+ * never allocates device memory. */
+typedef struct adg_server adg_server_t;
+typedef struct adg_server_config {
+  int32_t eps_num, eps_den;  /* eps = eps_num / eps_den for every request */
+  uint64_t seed;             /* tie-break seed for every request */
+  int32_t workers;           /* concurrent jobs (host threads, one stream each), 1..16 */
+  int64_t small_nnz;         /* requests with nnz <= small_nnz are grouped */
+  int32_t max_group;         /* requests per grouped launch, >= 1 */
+  int32_t max_bypass;        /* overtakes of the oldest waiting request, >= 0 */
+} adg_server_config_t;
+typedef struct adg_request_result {
+  uint64_t tag;              /* as submitted */
+  int32_t status;            /* ADG_OK or an ADG_ERR_* code */
+  int32_t num_colors, num_rounds;
+  int32_t group_size;        /* requests in the launch that coloured it */
+  int64_t n, nnz;
+  double t_submit, t_admit, t_start, t_done;  /* adg_server_clock() seconds */
+} adg_request_result_t;
+
+adg_server_config_t adg_server_default_config(void);
+/* Arena bytes a request of this size needs on its own (0 for bad sizes). */
+size_t adg_server_footprint(const adg_server_config_t* cfg, int64_t n, int64_t nnz);
+/* Start a server on the current device.  Errors: ADG_ERR_ARG, ADG_ERR_HIP. */
+int adg_server_create(const adg_server_config_t* cfg, void* arena, size_t arena_bytes, adg_server_t** out);
+/* Queue one graph.  row_ptr[n+1], col_idx[nnz] and color_out[n] are HOST
+ * arrays that must stay valid until the request's result has been polled;
+ * color_out receives the colours.  Errors: ADG_ERR_ARG (bad sizes, row_ptr
+ * not spanning [0, nnz], server stopping), ADG_ERR_UNSUPPORTED (footprint
+ * larger than the whole arena). */
+int adg_server_submit(adg_server_t* s, int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                      int32_t* color_out, uint64_t tag);
+/* Move up to max_results finished requests to out (waiting up to wait_ms
+ * for the first); *count_out = number moved. */
+int adg_server_poll(adg_server_t* s, adg_request_result_t* out, int32_t max_results, int32_t wait_ms,
+                    int32_t* count_out);
+/* Requests submitted and not yet polled (-1 for a null server). */
+int64_t adg_server_in_flight(adg_server_t* s);
+/* The steady clock the result times use, in seconds. */
+double adg_server_clock(void);
+/* Totals over the server's successfully finished jobs. */
+typedef struct adg_server_counters {
+  int64_t single_jobs;       /* requests coloured by color_graph alone */
+  int64_t grouped_jobs;      /* color_graph_batched launches */
+  int64_t grouped_requests;  /* requests coloured in them */
+  int64_t vertices, entries; /* sum of n and of nnz */
+  int64_t sum_active;        /* sum over requests and ADG rounds of |U_l| */
+  int64_t cut_edges;         /* sum of ADG's degree decrements */
+} adg_server_counters_t;
+int adg_server_get_counters(adg_server_t* s, adg_server_counters_t* out);
+/* Finish every queued request, stop the workers and free the server (results
+ * not polled are dropped). */
+int adg_server_destroy(adg_server_t* s);
 
 /* Copy the counters of the last adg_order / jp_color / color_graph call on
  * this workspace to host memory.  Synchronises `stream`. */

@@ -11,10 +11,10 @@ import ctypes
 
 import numpy as np
 
-from . import _check, _ptr, _stream, _torch, lib
+from . import _Stats, _check, _ptr, _stream, _torch, lib
 
 __all__ = ["Batch", "BatchConfig", "batched_workspace_bytes", "color_graph_batched", "autotune", "batched_error",
-           "default_config"]
+           "batched_stats", "default_config"]
 
 ADG_SCHED_LPT = 0
 ADG_SCHED_NATURAL = 1
@@ -48,8 +48,8 @@ def _setup(L):
     L.adg_batched_default_config.argtypes = []
     L.color_graph_batched.restype = ctypes.c_int
     L.color_graph_batched.argtypes = [P(_Batch), i32, i32, u64, vp, vp, vp, vp, P(BatchConfig), vp, sz, vp]
-    L.adg_batched_error.restype = ctypes.c_int
-    L.adg_batched_error.argtypes = [vp, sz, P(ctypes.c_int32), vp]
+    L.adg_batched_get_stats.restype = ctypes.c_int
+    L.adg_batched_get_stats.argtypes = [vp, sz, P(_Stats), vp]
     L.adg_batched_autotune.restype = ctypes.c_int
     L.adg_batched_autotune.argtypes = [P(_Batch), i32, i32, u64, vp, vp, vp, sz, vp, i32, P(BatchConfig),
                                        P(ctypes.c_float)]
@@ -148,12 +148,18 @@ def color_graph_batched(batch, eps_num, eps_den, seed, workspace=None, stream=No
             nr[:batch.num_graphs])
 
 
+def batched_stats(workspace, stream=None):
+    """Counters of the last batched call on ``workspace``, summed over the
+    batch (num_rounds / num_colors: the largest of any graph)."""
+    st = _Stats()
+    _check(_lib().adg_batched_get_stats(_ptr(workspace), workspace.numel(), ctypes.byref(st), _stream(stream)),
+           "adg_batched_get_stats")
+    return {k: int(getattr(st, k)) for k, _ in _Stats._fields_}
+
+
 def batched_error(workspace, stream=None):
     """Device-side error code of the last batched call on ``workspace`` (0 = none)."""
-    e = ctypes.c_int32(0)
-    _check(_lib().adg_batched_error(_ptr(workspace), workspace.numel(), ctypes.byref(e), _stream(stream)),
-           "adg_batched_error")
-    return int(e.value)
+    return batched_stats(workspace, stream)["error"]
 
 
 def autotune(batch, eps_num, eps_den, seed, workspace=None, stream=None, reuse=True, out=None):

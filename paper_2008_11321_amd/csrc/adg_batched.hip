@@ -54,9 +54,15 @@ constexpr int SCHED_BUCKETS = 64;     // work classes (floor(log2(work)))
 constexpr int WG = __HIP_MEMORY_SCOPE_WORKGROUP;
 
 struct BCtrl {
-  unsigned int next;   // queue head: graphs claimed so far
-  int error;           // ADG_ERR_* raised on the device
-  unsigned int pad[62];
+  unsigned int next;              // queue head: graphs claimed so far
+  int error;                      // ADG_ERR_* raised on the device
+  unsigned long long sum_active;  // sum over graphs and rounds of |U_l|
+  unsigned long long cut_edges;   // decrements of D
+  unsigned long long frontier;    // vertices of JP's first level
+  unsigned long long levels;      // JP levels
+  int max_rounds;                 // largest L of the batch
+  int max_colors;                 // largest colour count of the batch
+  unsigned int pad[52];
 };
 
 struct BParams {
@@ -166,6 +172,12 @@ __global__ __launch_bounds__(SCHED_BS) void k_sched(BParams P, int natural) {
   if (threadIdx.x == 0) {
     P.ctrl->next = 0;
     P.ctrl->error = 0;
+    P.ctrl->sum_active = 0;
+    P.ctrl->cut_edges = 0;
+    P.ctrl->frontier = 0;
+    P.ctrl->levels = 0;
+    P.ctrl->max_rounds = 0;
+    P.ctrl->max_colors = 0;
   }
   __syncthreads();
   if (natural) {
@@ -253,9 +265,10 @@ __device__ __forceinline__ void finish_row(const BParams& P, const GraphCtx& C, 
   }
 }
 
-// ADG on graph C; returns the number of rounds.
+// ADG on graph C; returns the number of rounds and adds sum |U_l| and the
+// number of decrements to *act and *cut.
 template <int BB>
-__device__ int adg_graph(const BParams& P, const GraphCtx& C, Lds<BB>& S) {
+__device__ int adg_graph(const BParams& P, const GraphCtx& C, Lds<BB>& S, long long* act, long long* cut) {
   const int tid = threadIdx.x;
   const int wid = tid / WAVE;
   const unsigned lane = lane_id();
@@ -272,6 +285,7 @@ __device__ int adg_graph(const BParams& P, const GraphCtx& C, Lds<BB>& S) {
       return l - 1;
     }
     const unsigned long long T = ((P.q + P.p) * Ssum) / (P.q * N);
+    *act += (long long)N;
     // ---- selection: U_l -> R_l | U_{l+1}, stable
     long long nr = 0, nu = 0, sstay = 0;
     for (long long b = 0; b < (long long)N; b += BB) {
@@ -361,6 +375,7 @@ __device__ int adg_graph(const BParams& P, const GraphCtx& C, Lds<BB>& S) {
       __syncthreads();   // big[] and nbig are rewritten by the next chunk
     }
     x = block_sum<BB>(x, S.red);   // barrier: D decrements done
+    *cut += x;
     rpos += nr;
     if (nu == 0) return l;
     N = (unsigned long long)nu;
@@ -408,8 +423,10 @@ __device__ __forceinline__ bool touch(const BParams& P, const GraphCtx& C, int u
   return (old >> JP_MASK_BITS) == 1;
 }
 
+// JP on graph C from its first level (nf vertices); returns the number of
+// colours and adds the number of levels to *levels.
 template <int BB>
-__device__ int jp_graph(const BParams& P, const GraphCtx& C, Lds<BB>& S, unsigned nf) {
+__device__ int jp_graph(const BParams& P, const GraphCtx& C, Lds<BB>& S, unsigned nf, long long* levels) {
   const int tid = threadIdx.x;
   unsigned long long* Fc = P.F0 + C.vo;
   unsigned long long* Fn = P.F1 + C.vo;
@@ -420,6 +437,7 @@ __device__ int jp_graph(const BParams& P, const GraphCtx& C, Lds<BB>& S, unsigne
     nf = 0;
   }
   while (nf > 0) {
+    ++*levels;
     done += nf;
     if (done > C.n) {  // a vertex was released twice: broken DAG
       if (tid == 0) atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
@@ -504,14 +522,23 @@ __global__ __launch_bounds__(BB) void k_batched(BParams P) {
     C.ebase = C.e0 / 64 + g;
     C.ecap = (P.rp[P.vo[g + 1]] / 64 + g + 1) - C.ebase;
     int L = 0, K = 0;
+    long long act = 0, cut = 0, lev = 0;
+    unsigned f0 = 0;
     if (C.n > 0) {
-      L = adg_graph<BB>(P, C, S);
+      L = adg_graph<BB>(P, C, S, &act, &cut);
       __syncthreads();   // f0, extc final
-      K = jp_graph<BB>(P, C, S, S.f0);
+      f0 = S.f0;
+      K = jp_graph<BB>(P, C, S, f0, &lev);
     }
     if (tid == 0) {
       P.num_colors[g] = K;
       if (P.num_rounds) P.num_rounds[g] = L;
+      atomicAdd(&P.ctrl->sum_active, (unsigned long long)act);
+      atomicAdd(&P.ctrl->cut_edges, (unsigned long long)cut);
+      atomicAdd(&P.ctrl->frontier, (unsigned long long)f0);
+      atomicAdd(&P.ctrl->levels, (unsigned long long)lev);
+      atomicMax(&P.ctrl->max_rounds, L);
+      atomicMax(&P.ctrl->max_colors, K);
     }
     __syncthreads();   // S reused by the next graph
   }
@@ -682,13 +709,19 @@ int color_graph_batched(const adg_batch_t* b, int32_t eps_num, int32_t eps_den, 
   return launch(P, cfg, s);
 }
 
-int adg_batched_error(const void* workspace, size_t ws_bytes, int32_t* host_error, void* stream) {
-  if (!workspace || !host_error || ws_bytes < sizeof(BCtrl)) return ADG_ERR_ARG;
+int adg_batched_get_stats(const void* workspace, size_t ws_bytes, adg_stats_t* out, void* stream) {
+  if (!workspace || !out || ws_bytes < sizeof(BCtrl)) return ADG_ERR_ARG;
   hipStream_t s = (hipStream_t)stream;
   BCtrl h;
   HIPCHK(hipMemcpyAsync(&h, workspace, sizeof(BCtrl), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  *host_error = h.error;
+  out->num_rounds = h.max_rounds;
+  out->num_colors = h.max_colors;
+  out->sum_active = (int64_t)h.sum_active;
+  out->cut_edges = (int64_t)h.cut_edges;
+  out->frontier = (int64_t)h.frontier;
+  out->jp_levels = (int64_t)h.levels;
+  out->error = h.error;
   return ADG_OK;
 }
 

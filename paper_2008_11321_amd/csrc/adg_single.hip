@@ -56,31 +56,32 @@ constexpr int FB_CAP = 2048;            // per-block staging of level lists (LDS
 constexpr int JP_SMALL = 32;            // lane-per-vertex successor loops
 constexpr int JP_UNROLL = 4;
 constexpr int JP_CHUNK = WAVE * JP_UNROLL;   // successors per wavefront step / fan-out chunk
-constexpr int FAN_LDS = 2048;                // fan-out list entries a grid block stages in LDS
+constexpr int FAN_LDS = 1024;                // fan-out list entries a grid block stages in LDS
 constexpr int NARROW_BS = 1024;              // threads of the single-block JP kernel
-constexpr int JP_NARROW_MAX = 2048;          // level size the single block takes
-constexpr int JP_NARROW_EDGES = 1 << 14;     // level edges the single block takes
-constexpr int NARROW_SCAN = 1 << 16;         // round size whose level-0 scan the block takes
-constexpr int NARROW_PUSH_WORK = 1 << 16;    // push work (edges) the block takes
+constexpr int NARROW_MAX = 1024;             // level size the single block takes
+constexpr int NARROW_WORDS = 8192;           // colour bitmap words of a level it takes
+constexpr int NARROW_SUCC = 8192;            // same-round successor entries of a level it takes
+constexpr int NARROW_XPULL = 512;            // round size whose later-round colours it pulls in
+constexpr int NARROW_UNROLL = 4;             // edges per thread in flight in a narrow level
 
-enum { JP_MODE_NARROW = 0, JP_MODE_WIDE = 1 };
-enum { PH_FRONTIER = 0, PH_LEVEL = 1, PH_PUSH = 2 };
-enum { OP_NONE = 0, OP_FRONTIER = 1, OP_LEVEL = 2, OP_PUSH = 3 };
+enum { OP_NONE = 0, OP_SPLIT = 1, OP_LEVEL = 2, OP_XPULL = 3 };
 
 // JP progress.  Lives in the control block between kernels; the single-block
 // kernel keeps its own copy in LDS while it runs.
 struct JpState {
   int round;                   // round being coloured (L .. 1)
-  int phase;                   // PH_* of that round
   int level;                   // level inside the round
-  int mode;                    // JP_MODE_* of that level
+  int split;                   // the round's first level is still only in L0
+  int xpull;                   // the round's later-round colours are still to be pulled in
+  int top;                     // L (the first round coloured)
   int done;                    // JP finished
   int levels;                  // levels processed (all rounds)
-  unsigned int F;              // vertices that started a level 0
+  unsigned long long F;        // vertices that formed a round's first level
   unsigned int fcnt[3];        // plain vertices per level (by level mod 3)
+  unsigned int pad3;
   unsigned long long hctr[3];  // fan-out vertices (low 32 bits) and chunks (high 32 bits)
-  unsigned long long ecnt[3];  // same-round successor edges of each level's vertices
-  unsigned long long phctr;    // push fan-out vertices and chunks of the current round
+  unsigned long long psum[3];  // bitmap words summed over each level's vertices
+  unsigned long long ssum[3];  // same-round successors summed over each level's vertices
 };
 
 // Device-resident control block (one per workspace).
@@ -100,6 +101,7 @@ struct Ctrl {
   int error;                   // ADG_ERR_* raised on the device
   int stats_round;             // last round k_stats has computed
   // JP state
+  unsigned long long bm_next;  // colour bitmap words handed out
   int grid_op;                 // OP_* the grid kernel has to run next
   int grid_ran;                // the grid kernel has run grid_op
   int num_colors;
@@ -132,14 +134,15 @@ struct Params {
   int* dag;                    // [nnz] rows as [pred | same-round succ | earlier succ]
   int* npred;                  // |pred(v)|
   int* nsr;                    // same-round successors of v (JP levels walk these)
-  unsigned long long* word;    // JP word (adg_device.h)
+  int* cnt;                    // same-round predecessors of v not yet coloured
+  unsigned long long* rec;     // (colour bitmap offset << 32) | |pred(v)|
+  unsigned* B;                 // colour bitmaps (bm_words(|pred|) words per vertex)
+  unsigned long long bm_cap;   // words of B
+  unsigned* L0;                // first JP level of each round, in the round's ORD slot range
+  unsigned* l0n;               // its size, per round
   unsigned* F[2];              // level lists, plain vertices (by level parity)
   unsigned long long* H[2];    // level lists, fan-out vertices: (first chunk << 32) | vertex
-  unsigned long long* PH;      // push fan-out list of the current round
   unsigned hub_cap;
-  int* eoff;                   // [n+1] extension-word offsets
-  unsigned long long* ext;     // extension words (colours above 40)
-  unsigned long long ext_cap;
   int* color;
 };
 
@@ -203,20 +206,23 @@ __global__ void k_init(Params P) {
   c->grid_op = OP_NONE;
   c->grid_ran = 0;
   c->num_colors = 0;
+  c->bm_next = 0;
   JpState& j = c->js;
   j.round = 0;
-  j.phase = PH_FRONTIER;
   j.level = 0;
-  j.mode = JP_MODE_NARROW;
+  j.split = 0;
+  j.xpull = 0;
+  j.top = 0;
   j.done = 0;
   j.levels = 0;
   j.F = 0;
   for (int k = 0; k < 3; ++k) {
     j.fcnt[k] = 0;
     j.hctr[k] = 0;
-    j.ecnt[k] = 0;
+    j.psum[k] = 0;
+    j.ssum[k] = 0;
   }
-  j.phctr = 0;
+  for (int k = 0; k < 3; ++k) P.l0n[k] = 0;
 }
 
 // One block.  Computes N_l, S_l and T_l for round l, or ends the loop.
@@ -245,7 +251,10 @@ __global__ void k_stats(Params P, int l) {
     S = c->SUnext - red[0];
     c->cut_edges += red[0];
   }
-  if (l <= P.max_rounds + 1) P.roundN[l] = (unsigned)N;
+  if (l <= P.max_rounds + 1) {
+    P.roundN[l] = (unsigned)N;
+    P.l0n[l] = 0;
+  }
   if (N == 0) {
     c->done = 1;
     c->num_rounds = l - 1;
@@ -446,9 +455,11 @@ __global__ __launch_bounds__(BS) void k_scatter(Params P, int l) {
   }
 }
 
-// Neighbour classes of v in round l: 0 = JP predecessor (w still in U, or
-// removed in round l with a larger hash), 1 = same-round successor,
-// 2 = successor from an earlier round.  Decrements D[w] for w still in U.
+// Neighbour classes of v in round l: 0 = JP predecessor still in U (a later
+// round), 3 = predecessor removed in round l (larger hash), 1 = same-round
+// successor, 2 = successor from an earlier round.  Decrements D[w] for w
+// still in U.
+enum { NB_PRED = 0, NB_SUCC_SAME = 1, NB_SUCC_EARLIER = 2, NB_PRED_SAME = 3, NB_NONE = 5 };
 template <bool FUSED>
 __device__ __forceinline__ int visit3(const Params& P, int w, int l, unsigned char code, uint32_t hv, unsigned& x,
                                       bool decrement) {
@@ -458,21 +469,74 @@ __device__ __forceinline__ int visit3(const Params& P, int w, int l, unsigned ch
       atomicSub(&P.D[w], 1);
       x += 1;
     }
-    return 0;
+    return NB_PRED;
   }
-  if (FUSED && st == code && P.round[w] == l) return tiebreak(P.hkey, (uint32_t)w) > hv ? 0 : 1;
-  return 2;
+  if (FUSED && st == code && P.round[w] == l)
+    return tiebreak(P.hkey, (uint32_t)w) > hv ? NB_PRED_SAME : NB_SUCC_SAME;
+  return NB_SUCC_EARLIER;
 }
 
-__device__ __forceinline__ void store_row_meta(const Params& P, int v, long long np, long long ns) {
+__device__ __forceinline__ bool is_pred(int cl) { return cl == NB_PRED || cl == NB_PRED_SAME; }
+
+// Colour bitmap words of a vertex with np predecessors: bits for colours
+// 1 .. np+2 (GetColor's answer is at most np + 1).
+__device__ __forceinline__ unsigned bm_words(int np) { return (unsigned)(np + 2 + 31) / 32; }
+
+template <typename T>
+__device__ __forceinline__ T wave_excl_scan(T x, T* total) {
+  const unsigned lane = lane_id();
+  T incl = x;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const T t = __shfl_up(incl, o, WAVE);
+    if ((int)lane >= o) incl += t;
+  }
+  *total = __shfl(incl, WAVE - 1, WAVE);
+  return incl - x;
+}
+
+// Whole wavefront: JP bookkeeping of the lanes' vertices with `has` set --
+// |pred(v)| (np), same-round successors (ns), same-round predecessors still
+// to be coloured (cnt = nps), and a cleared colour bitmap from the bump
+// allocator; rec[v] = (bitmap offset << 32) | np.
+__device__ __forceinline__ void jp_row(const Params& P, bool has, int v, long long np, long long ns, long long nps) {
+  const unsigned w = has ? bm_words((int)np) : 0;
+  unsigned tot;
+  const unsigned pre = wave_excl_scan<unsigned>(w, &tot);
+  unsigned long long base = 0;
+  if (lane_id() == 0 && tot) base = atomicAdd(&P.ctrl->bm_next, (unsigned long long)tot);
+  base = readlane_u64(base, 0);
+  if (!has) return;
+  unsigned long long off = base + pre;
+  if (off + w > P.bm_cap) {  // cannot happen (see the capacity); keep accesses in bounds
+    atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
+    off = 0;
+    np = 0;
+  } else {
+    for (unsigned k = 0; k < w; ++k) P.B[off + k] = 0;
+  }
   P.npred[v] = (int)np;
   P.nsr[v] = (int)ns;
-  P.word[v] = (unsigned long long)np << JP_MASK_BITS;
-  if (np > JP_MAX_PRED) atomicExch(&P.ctrl->error, ADG_ERR_UNSUPPORTED);
+  P.cnt[v] = (int)nps;
+  P.rec[v] = (off << 32) | (unsigned)np;
+}
+
+// Wavefront: append the lanes' vertices with z set to the first JP level of
+// their round (list L0 at `base`, counter l0n[l]).
+__device__ __forceinline__ void l0_append(const Params& P, int l, long long base, bool z, int v) {
+  const uint64_t m = ballot(z);
+  if (!m) return;
+  const int leader = __ffsll((long long)m) - 1;
+  unsigned at = 0;
+  if (lane_id() == (unsigned)leader) at = atomicAdd(&P.l0n[l], (unsigned)__popcll(m));
+  at = readlane_u(at, leader);
+  if (z) P.L0[base + at + lanes_below(m)] = (unsigned)v;
 }
 
 // Lane-per-vertex UPDATE for rows of at most SMALL_DEG entries: one pass to
-// count (and decrement), one pass to place the partitioned row.
+// count (and decrement), one pass to place the row as [predecessors from
+// later rounds | same-round predecessors | same-round successors |
+// successors from earlier rounds].
 template <bool FUSED>
 __device__ void update_small(const Params& P, int v, bool valid, int l, unsigned char code, unsigned& x) {
   long long b = 0, e = 0;
@@ -481,22 +545,28 @@ __device__ void update_small(const Params& P, int v, bool valid, int l, unsigned
     e = P.rp[v + 1];
   }
   const uint32_t hv = tiebreak(P.hkey, (uint32_t)v);
-  long long np = 0, ns = 0;
+  long long nl = 0, nps = 0, ns = 0;
   for (long long j = b; j < e; ++j) {
     int cl = visit3<FUSED>(P, P.col[j], l, code, hv, x, true);
-    np += cl == 0;
-    ns += cl == 1;
+    nl += cl == NB_PRED;
+    nps += cl == NB_PRED_SAME;
+    ns += cl == NB_SUCC_SAME;
   }
-  if (!FUSED || !valid) return;
-  long long f = b, s = b + np, r = e;
-  for (long long j = b; j < e; ++j) {
-    int w = P.col[j];
-    int cl = visit3<FUSED>(P, w, l, code, hv, x, false);
-    if (cl == 0) P.dag[f++] = w;
-    else if (cl == 1) P.dag[s++] = w;
-    else P.dag[--r] = w;
+  if (!FUSED) return;
+  const long long np = nl + nps;
+  if (valid) {
+    long long f = b, g = b + nl, s = b + np, r = e;
+    for (long long j = b; j < e; ++j) {
+      int w = P.col[j];
+      int cl = visit3<FUSED>(P, w, l, code, hv, x, false);
+      if (cl == NB_PRED) P.dag[f++] = w;
+      else if (cl == NB_PRED_SAME) P.dag[g++] = w;
+      else if (cl == NB_SUCC_SAME) P.dag[s++] = w;
+      else P.dag[--r] = w;
+    }
   }
-  store_row_meta(P, v, np, ns);
+  jp_row(P, valid, v, np, ns, nps);
+  l0_append(P, l, (long long)P.n - P.roundN[l], valid && nps == 0, v);
 }
 
 // Wave-per-vertex UPDATE for longer rows: count pass (with the decrements),
@@ -506,33 +576,39 @@ __device__ void update_big(const Params& P, int v, int l, unsigned char code, un
   const long long b = P.rp[v], e = P.rp[v + 1];
   const uint32_t hv = tiebreak(P.hkey, (uint32_t)v);
   const unsigned lane = lane_id();
-  long long np = 0, ns = 0;
+  long long nl = 0, nps = 0, ns = 0;
   for (long long base = b; base < e; base += WAVE) {
     long long j = base + lane;
     bool valid = j < e;
     int w = valid ? P.col[j] : 0;
-    int cl = valid ? visit3<FUSED>(P, w, l, code, hv, x, true) : 3;
+    int cl = valid ? visit3<FUSED>(P, w, l, code, hv, x, true) : NB_NONE;
     if (FUSED) {
-      np += __popcll(ballot(cl == 0));
-      ns += __popcll(ballot(cl == 1));
+      nl += __popcll(ballot(cl == NB_PRED));
+      nps += __popcll(ballot(cl == NB_PRED_SAME));
+      ns += __popcll(ballot(cl == NB_SUCC_SAME));
     }
   }
   if (!FUSED) return;
-  long long fc = 0, sc = 0, lc = 0;
+  const long long np = nl + nps;
+  long long fc = 0, gc = 0, sc = 0, lc = 0;
   for (long long base = b; base < e; base += WAVE) {
     long long j = base + lane;
     bool valid = j < e;
     int w = valid ? P.col[j] : 0;
-    int cl = valid ? visit3<FUSED>(P, w, l, code, hv, x, false) : 3;
-    uint64_t pm = ballot(cl == 0), sm = ballot(cl == 1), lm = ballot(cl == 2);
-    if (cl == 0) P.dag[b + fc + lanes_below(pm)] = w;
-    else if (cl == 1) P.dag[b + np + sc + lanes_below(sm)] = w;
-    else if (cl == 2) P.dag[e - 1 - lc - lanes_below(lm)] = w;
-    fc += __popcll(pm);
+    int cl = valid ? visit3<FUSED>(P, w, l, code, hv, x, false) : NB_NONE;
+    uint64_t fm = ballot(cl == NB_PRED), gm = ballot(cl == NB_PRED_SAME), sm = ballot(cl == NB_SUCC_SAME),
+             lm = ballot(cl == NB_SUCC_EARLIER);
+    if (cl == NB_PRED) P.dag[b + fc + lanes_below(fm)] = w;
+    else if (cl == NB_PRED_SAME) P.dag[b + nl + gc + lanes_below(gm)] = w;
+    else if (cl == NB_SUCC_SAME) P.dag[b + np + sc + lanes_below(sm)] = w;
+    else if (cl == NB_SUCC_EARLIER) P.dag[e - 1 - lc - lanes_below(lm)] = w;
+    fc += __popcll(fm);
+    gc += __popcll(gm);
     sc += __popcll(sm);
     lc += __popcll(lm);
   }
-  if (lane == 0) store_row_meta(P, v, np, ns);
+  jp_row(P, lane == 0, v, np, ns, nps);
+  l0_append(P, l, (long long)P.n - P.roundN[l], lane == 0 && nps == 0, v);
 }
 
 template <bool FUSED>
@@ -576,8 +652,8 @@ __device__ __forceinline__ uint64_t prio(const Params& P, int w) {
 
 // For jp_color on a given ranking: classify every neighbour by the priority
 // <round, hash> and write rows [pred | succ].  All vertices form one
-// pseudo-round (ORD is the identity), so every successor is walked by the
-// levels: nsr(v) = |succ(v)|.
+// pseudo-round (its L0 at offset 0), so every predecessor is counted by cnt
+// and every successor is walked by the levels: nsr(v) = |succ(v)|.
 __global__ __launch_bounds__(BS) void k_part1(Params P) {
   const long long gw = (long long)blockIdx.x * WPB + threadIdx.x / WAVE;
   const long long gstride = (long long)gridDim.x * WPB;
@@ -590,6 +666,7 @@ __global__ __launch_bounds__(BS) void k_part1(Params P) {
     long long b = valid ? P.rp[v] : 0, e = valid ? P.rp[v + 1] : 0;
     const uint64_t kv = prio(P, v);
     const bool small = valid && (e - b) <= SMALL_DEG;
+    long long np = 0;
     if (small) {
       long long f = b, s = e;
       for (long long j = b; j < e; ++j) {
@@ -597,8 +674,10 @@ __global__ __launch_bounds__(BS) void k_part1(Params P) {
         if (prio(P, w) > kv) P.dag[f++] = w;
         else P.dag[--s] = w;
       }
-      store_row_meta(P, v, f - b, e - f);
+      np = f - b;
     }
+    jp_row(P, small, v, np, (e - b) - np, np);
+    l0_append(P, 1, 0, small && np == 0, v);
     uint64_t big = ballot(valid && !small);
     while (big) {
       int L = __ffsll((long long)big) - 1;
@@ -618,193 +697,58 @@ __global__ __launch_bounds__(BS) void k_part1(Params P) {
         fc += __popcll(pm);
         sc += __popcll(sm);
       }
-      if (lane == 0) store_row_meta(P, u, fc, sc);
+      jp_row(P, lane == 0, u, fc, sc, fc);
+      l0_append(P, 1, 0, lane == 0 && fc == 0, u);
     }
   }
 }
 
 // ================================================================ JP Part 2
-
-// Colours above 40 do not fit the JP word.  A vertex that may need them
-// (|pred| + 1 > 40) owns E(v) = ceil((|pred| + 1 - 40) / 64) extension words
-// ext[eoff[v] .. eoff[v+1]) with bits for colours 41, 42, ...; the smallest
-// free colour never exceeds |pred| + 1, so they always suffice.  eoff is an
-// exclusive scan of E over vertices.
-__device__ __forceinline__ int ext_words(int np) {
-  int over = np + 1 - JP_MASK_BITS;
-  return over > 0 ? (over + 63) / 64 : 0;
-}
-
-__global__ __launch_bounds__(BS) void k_ext_count(Params P) {
-  Chunk ch = sel_chunk((unsigned long long)P.n);
-  unsigned long long s = 0;
-  for (long long v = ch.beg + threadIdx.x; v < ch.end; v += BS) s += (unsigned long long)ext_words(P.npred[v]);
-  s = wave_sum(s);
-  __shared__ unsigned long long red[WPB];
-  if (lane_id() == 0) red[threadIdx.x / WAVE] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long t = 0;
-    for (int k = 0; k < WPB; ++k) t += red[k];
-    P.bsum[blockIdx.x] = t;
-  }
-}
-
-__global__ __launch_bounds__(BS) void k_ext_scan(Params P) {
-  constexpr int PER = SEL_BLOCKS / BS;
-  __shared__ unsigned long long part[BS];
-  unsigned long long loc = 0;
-  const int b0 = threadIdx.x * PER;
-  for (int k = 0; k < PER; ++k) loc += P.bsum[b0 + k];
-  part[threadIdx.x] = loc;
-  __syncthreads();
-  for (int off = 1; off < BS; off <<= 1) {
-    unsigned long long v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
-  }
-  unsigned long long run = part[threadIdx.x] - loc;
-  for (int k = 0; k < PER; ++k) {
-    P.boff[(b0 + k) * 3] = run;
-    run += P.bsum[b0 + k];
-  }
-  if (threadIdx.x == BS - 1) {
-    P.eoff[P.n] = (int)part[BS - 1];
-    if (part[BS - 1] > P.ext_cap) atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
-  }
-}
-
-// Writes eoff for the block's slice of vertices and clears their extension words.
-__global__ __launch_bounds__(BS) void k_ext_fill(Params P) {
-  Chunk ch = sel_chunk((unsigned long long)P.n);
-  unsigned long long base = P.boff[blockIdx.x * 3];
-  __shared__ unsigned wsum[WPB];
-  const int w = threadIdx.x / WAVE;
-  for (long long t = ch.beg; t < ch.end; t += BS) {
-    long long v = t + threadIdx.x;
-    int E = v < ch.end ? ext_words(P.npred[v]) : 0;
-    int incl = E;
-#pragma unroll
-    for (int off = 1; off < WAVE; off <<= 1) {
-      int o = __shfl_up(incl, off, WAVE);
-      if ((int)lane_id() >= off) incl += o;
-    }
-    if (lane_id() == WAVE - 1) wsum[w] = incl;
-    __syncthreads();
-    unsigned pre = 0, tot = 0;
-    for (int k = 0; k < WPB; ++k) {
-      if (k < w) pre += wsum[k];
-      tot += wsum[k];
-    }
-    unsigned long long off = base + pre + (incl - E);
-    if (v < ch.end) {
-      P.eoff[v] = (int)off;
-      for (int k = 0; k < E && off + k < P.ext_cap; ++k) P.ext[off + k] = 0;
-    }
-    base += tot;
-    __syncthreads();
-  }
-}
-
-// Colour of v when colours 1..40 are all taken by its predecessors: the first
-// clear bit of its extension words.  Whole wavefront.  Only called once every
-// predecessor has finished (earlier level, round or push), so all bits are final.
-template <int S>
-__device__ int jp_ext_color(const Params& P, int v) {
-  const unsigned lane = lane_id();
-  const int e0 = P.eoff[v], e1 = P.eoff[v + 1];
-  for (int base = e0; base < e1; base += WAVE) {
-    int k = base + (int)lane;
-    int found = 0x7fffffff;
-    if (k < e1) {
-      unsigned long long wd = ld64<S>(&P.ext[k]);
-      if (~wd) found = (k - e0) * 64 + __ffsll((long long)~wd) - 1;
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      int o = __shfl_xor(found, off, WAVE);
-      found = o < found ? o : found;
-    }
-    if (found != 0x7fffffff) return JP_MASK_BITS + 1 + found;
-  }
-  // unreachable for a consistent DAG: E(v) words cover colours up to |pred|+1
-  if (lane == 0) atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
-  return JP_MASK_BITS + 1 + (e1 - e0) * 64;
-}
-
-// Record colour c (> 40) of a predecessor in successor u's extension words, if
-// u has a word for it (colours beyond |pred(u)| + 1 cannot matter to u).
-template <int S>
-__device__ __forceinline__ void jp_ext_mark(const Params& P, int u, int c) {
-  const int e0 = P.eoff[u], e1 = P.eoff[u + 1];
-  const int k = (c - JP_MASK_BITS - 1) >> 6;
-  if (k < e1 - e0) or64<S>(&P.ext[e0 + k], 1ull << ((c - JP_MASK_BITS - 1) & 63));
-}
-
-// Same-round successor update: record colour c, take one count unit off u's
-// word; true if that was u's last uncoloured predecessor.
-template <int S>
-__device__ __forceinline__ bool jp_touch(const Params& P, int u, int c) {
-  if (c > JP_MASK_BITS) jp_ext_mark<S>(P, u, c);
-  else or64<S>(&P.word[u], 1ull << (c - 1));
-  unsigned long long old = add64<S>(&P.word[u], (unsigned long long)(-(long long)JP_ONE));
-  return (old >> JP_MASK_BITS) == 1;
-}
-
-// Earlier-round successor update (bulk push): the same, without a result --
-// u becomes ready in its own round's level-0 scan.
-template <int S>
-__device__ __forceinline__ void jp_push_one(const Params& P, int u, int c) {
-  if (c > JP_MASK_BITS) jp_ext_mark<S>(P, u, c);
-  else or64<S>(&P.word[u], 1ull << (c - 1));
-  add64<S>(&P.word[u], (unsigned long long)(-(long long)JP_ONE));
-}
-
-// GetColor for a ready vertex: the first clear bit of its word, or of its
-// extension words when colours 1..40 are all taken.  Whole wavefront.
-template <int S>
-__device__ __forceinline__ int jp_colour(const Params& P, bool act, int v) {
-  int col = 0;
-  unsigned long long M = 0;
-  if (act) M = ld64<S>(&P.word[v]) & JP_MASK;
-  const bool full = act && M == JP_MASK;
-  if (act && !full) col = __ffsll((long long)~M);  // first clear bit i -> colour i + 1
-  uint64_t wide = ballot(full);
-  while (wide) {
-    int L = __ffsll((long long)wide) - 1;
-    wide &= wide - 1;
-    int cc = jp_ext_color<S>(P, readlane_i(v, L));
-    if (lane_id() == (unsigned)L) col = cc;
-  }
-  return col;
-}
-
-// ---- level lists
-// Level l's vertices with at most JP_SMALL same-round successors are in
-// F[l & 1] (count fcnt[l % 3]); the others ("fan-out" vertices) are in
-// H[l & 1] as (first chunk, vertex), their same-round successors cut into
-// chunks of JP_CHUNK that different wavefronts process (hctr[l % 3]: entries
-// in the low 32 bits, chunks in the high 32 bits, so one atomic gives both and
-// the entries come out sorted by first chunk).
+//
+// Rounds are coloured from L down to 1.  Every edge of G_rho between two
+// rounds points from the higher round to the lower, so once rounds above r
+// are coloured, a vertex of round r waits only for its same-round
+// predecessors: cnt[v] counts those not yet coloured (set by UPDATE), and the
+// round's vertices with none form its first level (the list L0 of the round,
+// also built by UPDATE).  Each vertex owns a bitmap of the colours its
+// predecessors took (colours 1 .. |pred|+2).  When round r starts, one bulk
+// step ORs in the colours of every predecessor from a later round (final by
+// then).  Inside the round, a coloured vertex ORs its colour into the bitmap
+// of each same-round successor and takes one unit off its cnt; whoever takes
+// the last unit appends the successor to the next level.  A level's vertex
+// is coloured with the first clear bit of its bitmap (GetColor), complete
+// once all its predecessors have been coloured at earlier levels.
+//
+// Levels of at most NARROW_MAX vertices (and bounded work) run inside one
+// 1024-thread block with the level lists in LDS; wider ones over the grid,
+// with lists in global memory: F (vertices with at most JP_SMALL same-round
+// successors, a lane each) and H (the others, whose successors are cut into
+// JP_CHUNK-sized chunks that different wavefronts take).
 
 struct JpStage {
-  unsigned* buf;                // LDS staging of plain vertices
+  unsigned* buf;                // LDS staging of plain vertices (grid kernel), or null
   unsigned* cnt;                // its fill level (LDS)
-  unsigned* fcnt;               // level counters (control block, or LDS in the single block)
+  unsigned* fcnt;               // level counters (control block, or LDS)
   unsigned long long* hctr;
-  unsigned long long* ecnt;
-  unsigned long long* phctr;
+  unsigned long long* psum;     // bitmap words of the level's vertices
+  unsigned long long* ssum;     // their same-round successors
 };
 
-// Append u (ready) to level l + 1.
+// Append u (ready) to the global lists of level l + 1.
 template <int S>
 __device__ __forceinline__ void jp_append(const Params& P, JpStage& st, int l, bool rdy, int u) {
-  long long ns = 0;
-  if (rdy) ns = P.nsr[u];
+  long long ns = 0, wd = 0;
+  if (rdy) {
+    ns = P.nsr[u];
+    wd = bm_words(P.npred[u]);
+  }
   if (ballot(rdy)) {
-    unsigned long long es = wave_sum((unsigned long long)ns);
-    if (lane_id() == 0 && es) add64<S>(&st.ecnt[(l + 1) % 3], es);
+    const unsigned long long es = wave_sum((unsigned long long)ns);
+    const unsigned long long ps = wave_sum((unsigned long long)wd);
+    if (lane_id() == 0) {
+      if (es) add64<S>(&st.ssum[(l + 1) % 3], es);
+      if (ps) add64<S>(&st.psum[(l + 1) % 3], ps);
+    }
   }
   const bool fan = rdy && ns > JP_SMALL;
   if (fan) {
@@ -818,6 +762,13 @@ __device__ __forceinline__ void jp_append(const Params& P, JpStage& st, int l, b
   uint64_t m = ballot(plain);
   if (!m) return;
   unsigned k = __popcll(m);
+  if (!st.buf) {
+    unsigned g = 0;
+    if (lane_id() == 0) g = add32<S>(&st.fcnt[(l + 1) % 3], k);
+    g = readlane_u(g, 0);
+    if (plain) sti<S>((int*)&P.F[(l + 1) & 1][g + lanes_below(m)], u);
+    return;
+  }
   unsigned base = 0;
   if (lane_id() == 0) base = atomicAdd(st.cnt, k);
   base = readlane_u(base, 0);
@@ -848,27 +799,102 @@ __device__ __forceinline__ void jp_stage_flush(const Params& P, JpStage& st, int
   __syncthreads();
 }
 
-// Whole wavefront: same-round successors dag[s0 .. s1) of a vertex of colour cc.
+// Mark colour c in the bitmap described by rec (if it can matter there).
 template <int S>
-__device__ __forceinline__ void jp_succ_range(const Params& P, JpStage& st, int l, int cc, long long s0,
-                                              long long s1) {
-  const unsigned lane = lane_id();
-  for (long long base = s0; base < s1; base += JP_CHUNK) {
-    int u[JP_UNROLL];
-    bool ok[JP_UNROLL];
-#pragma unroll
-    for (int t = 0; t < JP_UNROLL; ++t) {
-      long long j = base + t * WAVE + lane;
-      ok[t] = j < s1;
-      u[t] = ok[t] ? P.dag[j] : 0;
-    }
-    bool rdy[JP_UNROLL];
-#pragma unroll
-    for (int t = 0; t < JP_UNROLL; ++t) rdy[t] = ok[t] && jp_touch<S>(P, u[t], cc);
-#pragma unroll
-    for (int t = 0; t < JP_UNROLL; ++t) jp_append<S>(P, st, l, rdy[t], u[t]);
+__device__ __forceinline__ void bm_mark(const Params& P, unsigned long long rec, int c) {
+  if (c >= 1 && c <= (int)(unsigned)rec + 2) {
+    const unsigned b = (unsigned)(c - 1);
+    __hip_atomic_fetch_or(&P.B[(rec >> 32) + (b >> 5)], 1u << (b & 31), __ATOMIC_RELAXED, S);
   }
 }
+
+// Same-round successor u (bitmap rec) of a vertex of colour c: record c, take
+// one unit off cnt[u]; true if that was u's last uncoloured same-round
+// predecessor.
+template <int S>
+__device__ __forceinline__ bool jp_push(const Params& P, int u, unsigned long long rec, int c) {
+  bm_mark<S>(P, rec, c);
+  return __hip_atomic_fetch_add(&P.cnt[u], -1, __ATOMIC_RELAXED, S) == 1;
+}
+
+// A bitmap word, read at the device's coherence point (atomics update it).
+__device__ __forceinline__ unsigned bm_load(const Params& P, unsigned long long at) {
+  return agent_load_u32(&P.B[at]);
+}
+
+// Colour of a finished vertex (also read at the coherence point).
+__device__ __forceinline__ int done_colour(const Params& P, int u) { return agent_load_i32(&P.color[u]); }
+
+struct WaveLds {
+  int off[WAVE + 1];           // exclusive scan of the lanes' item counts
+  unsigned long long rec[WAVE];
+  long long pb[WAVE];
+  int ffree[WAVE];             // first clear bit found in the lanes' bitmaps
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int wave_owner(const WaveLds& W, int e) {
+  int lo = 0, hi = WAVE;  // last k with off[k] <= e
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (W.off[mid] <= e) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// GetColor for every active lane (bitmap rec): the wavefront reads all the
+// lanes' bitmap words, spread evenly over its lanes, and each lane takes the
+// first clear bit of its own.
+__device__ int wave_colour(const Params& P, WaveLds& W, bool act, unsigned long long rec) {
+  const unsigned lane = lane_id();
+  int tot;
+  const int pre = wave_excl_scan<int>(act ? (int)bm_words((int)(unsigned)rec) : 0, &tot);
+  W.off[lane] = pre;
+  W.rec[lane] = rec;
+  W.ffree[lane] = 0x7fffffff;
+  if (lane == 0) W.off[WAVE] = tot;
+  wave_sync();
+  for (int e0 = 0; e0 < tot; e0 += WAVE * JP_UNROLL) {
+    int own[JP_UNROLL];
+    unsigned wd[JP_UNROLL];
+#pragma unroll
+    for (int t = 0; t < JP_UNROLL; ++t) {
+      const int e = e0 + t * WAVE + (int)lane;
+      own[t] = -1;
+      wd[t] = ~0u;
+      if (e < tot) {
+        own[t] = wave_owner(W, e);
+        wd[t] = bm_load(P, (W.rec[own[t]] >> 32) + (unsigned)(e - W.off[own[t]]));
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < JP_UNROLL; ++t)
+      if (own[t] >= 0 && ~wd[t]) {
+        const int e = e0 + t * WAVE + (int)lane;
+        atomicMin(&W.ffree[own[t]], (e - W.off[own[t]]) * 32 + __ffs((int)~wd[t]) - 1);
+      }
+  }
+  wave_sync();
+  int col = 0;
+  if (act) {
+    const int f = W.ffree[lane];
+    if (f == 0x7fffffff) {  // unreachable: at most |pred| of the |pred|+2 bits are set
+      atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
+      col = (int)(unsigned)rec + 1;
+    } else {
+      col = f + 1;
+    }
+  }
+  wave_sync();
+  return col;
+}
+
+// ---- grid-wide steps
 
 // Fan-out chunk k of a list sorted by first chunk: its entry (binary search,
 // in the block's LDS copy `lds` when the list was staged there).
@@ -902,14 +928,95 @@ __device__ __forceinline__ const unsigned long long* fan_stage(const unsigned lo
   return lds;
 }
 
-__device__ __forceinline__ long long succ_begin(const Params& P, int v) { return P.rp[v] + P.npred[v]; }
+__device__ __forceinline__ long long seg_begin(const Params& P, int r) { return (long long)P.n - P.roundN[r]; }
+__device__ __forceinline__ long long seg_size(const Params& P, int r) {
+  return (long long)P.roundN[r] - (long long)P.roundN[r + 1];
+}
 
-// The work items of level l for wavefronts gw, gw + gstride, ...: items
-// [0, groups) are groups of 64 plain vertices (a lane each; the whole wave for
-// more than JP_SMALL successors), then the fan-out chunks.
+// Bulk step at the start of round r: the colours of every predecessor from a
+// later round into the round's bitmaps.  Wavefronts take groups of 64 of the
+// round's vertices and spread each group's entries evenly over their lanes.
 template <int S>
-__device__ void jp_level_items(const Params& P, JpStage& st, int l, unsigned nf, unsigned long long hc, long long gw,
-                               long long gstride, const unsigned long long* hlds) {
+__device__ void jp_xpull_items(const Params& P, WaveLds& W, int r, long long gw, long long gstride) {
+  const long long b = seg_begin(P, r), sz = seg_size(P, r);
+  const unsigned lane = lane_id();
+  for (long long g = gw; g * WAVE < sz; g += gstride) {
+    const long long i = g * WAVE + lane;
+    const bool ok = i < sz;
+    int x = 0;
+    if (ok) {
+      const int v = P.ORD[b + i];
+      x = P.npred[v] - P.cnt[v];   // predecessors from later rounds (cnt is untouched until the round starts)
+      W.rec[lane] = P.rec[v];
+      W.pb[lane] = P.rp[v];
+    }
+    int tot;
+    W.off[lane] = wave_excl_scan<int>(x, &tot);
+    if (lane == 0) W.off[WAVE] = tot;
+    wave_sync();
+    for (int e0 = 0; e0 < tot; e0 += WAVE * JP_UNROLL) {
+      int own[JP_UNROLL], c[JP_UNROLL];
+#pragma unroll
+      for (int t = 0; t < JP_UNROLL; ++t) {
+        const int e = e0 + t * WAVE + (int)lane;
+        own[t] = -1;
+        c[t] = 0;
+        if (e < tot) {
+          own[t] = wave_owner(W, e);
+          c[t] = P.dag[W.pb[own[t]] + (e - W.off[own[t]])];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < JP_UNROLL; ++t) c[t] = own[t] >= 0 ? done_colour(P, c[t]) : 0;
+#pragma unroll
+      for (int t = 0; t < JP_UNROLL; ++t)
+        if (own[t] >= 0) bm_mark<S>(P, W.rec[own[t]], c[t]);
+    }
+    wave_sync();
+  }
+}
+
+// Level 0 of round r as global lists: its L0 vertices split into F and H.
+__device__ void jp_split_items(const Params& P, JpStage& st, int r, long long gw, long long gstride) {
+  const long long b = seg_begin(P, r), sz = P.l0n[r];
+  const unsigned lane = lane_id();
+  for (long long g = gw; g * WAVE < sz; g += gstride) {
+    const long long i = g * WAVE + lane;
+    const bool ok = i < sz;
+    const int v = ok ? (int)P.L0[b + i] : 0;
+    jp_append<SC_AGENT>(P, st, -1, ok, v);
+  }
+}
+
+// Whole wavefront: push colour cc to the same-round successors dag[s0 .. s1).
+__device__ __forceinline__ void jp_push_range(const Params& P, JpStage& st, int l, int cc, long long s0,
+                                              long long s1) {
+  const unsigned lane = lane_id();
+  for (long long base = s0; base < s1; base += WAVE * JP_UNROLL) {
+    int u[JP_UNROLL];
+    bool ok[JP_UNROLL];
+    unsigned long long rc[JP_UNROLL];
+#pragma unroll
+    for (int t = 0; t < JP_UNROLL; ++t) {
+      const long long j = base + t * WAVE + lane;
+      ok[t] = j < s1;
+      u[t] = ok[t] ? P.dag[j] : 0;
+    }
+#pragma unroll
+    for (int t = 0; t < JP_UNROLL; ++t) rc[t] = ok[t] ? P.rec[u[t]] : 0;
+    bool rdy[JP_UNROLL];
+#pragma unroll
+    for (int t = 0; t < JP_UNROLL; ++t) rdy[t] = ok[t] && jp_push<SC_AGENT>(P, u[t], rc[t], cc);
+#pragma unroll
+    for (int t = 0; t < JP_UNROLL; ++t) jp_append<SC_AGENT>(P, st, l, rdy[t], u[t]);
+  }
+}
+
+// The work items of wide level l: groups of 64 plain vertices (colour and
+// successors a lane each), then the fan-out chunks (each chunk reads its
+// vertex's bitmap; the one that starts the range stores the colour).
+__device__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, unsigned nf, unsigned long long hc,
+                               long long gw, long long gstride, const unsigned long long* hlds) {
   const unsigned lane = lane_id();
   const unsigned nh = (unsigned)hc;
   const unsigned nch = (unsigned)(hc >> 32);
@@ -918,353 +1025,499 @@ __device__ void jp_level_items(const Params& P, JpStage& st, int l, unsigned nf,
   const long long groups = ((long long)nf + WAVE - 1) / WAVE;
   for (long long it = gw; it < groups + (long long)nch; it += gstride) {
     if (it < groups) {
-      // plain vertices: at most JP_SMALL same-round successors, a lane each
       const long long idx = it * WAVE + lane;
       const bool act = idx < nf;
-      const int v = act ? (int)ld32<S>(&Fl[idx]) : 0;
-      const int col = jp_colour<S>(P, act, v);
-      if (act) sti<S>(&P.color[v], col);
-      long long b = 0, e = 0;
+      const int v = act ? (int)ld32<SC_AGENT>(&Fl[idx]) : 0;
+      unsigned long long rec = 0;
+      long long s0 = 0, s1 = 0;
       if (act) {
-        b = succ_begin(P, v);
-        e = b + P.nsr[v];
+        rec = P.rec[v];
+        s0 = P.rp[v] + (int)(unsigned)rec;
+        s1 = s0 + P.nsr[v];
       }
-      for (long long j = b; ballot(act && j < e); j += JP_UNROLL) {
+      const int col = wave_colour(P, W, act, rec);
+      if (act) sti<SC_AGENT>(&P.color[v], col);
+      for (long long j = s0; ballot(act && j < s1); j += JP_UNROLL) {
         int u[JP_UNROLL];
         bool ok[JP_UNROLL];
+        unsigned long long rc[JP_UNROLL];
 #pragma unroll
         for (int t = 0; t < JP_UNROLL; ++t) {
-          ok[t] = act && j + t < e;
+          ok[t] = act && j + t < s1;
           u[t] = ok[t] ? P.dag[j + t] : 0;
         }
+#pragma unroll
+        for (int t = 0; t < JP_UNROLL; ++t) rc[t] = ok[t] ? P.rec[u[t]] : 0;
         bool rdy[JP_UNROLL];
 #pragma unroll
-        for (int t = 0; t < JP_UNROLL; ++t) rdy[t] = ok[t] && jp_touch<S>(P, u[t], col);
+        for (int t = 0; t < JP_UNROLL; ++t) rdy[t] = ok[t] && jp_push<SC_AGENT>(P, u[t], rc[t], col);
 #pragma unroll
-        for (int t = 0; t < JP_UNROLL; ++t) jp_append<S>(P, st, l, rdy[t], u[t]);
+        for (int t = 0; t < JP_UNROLL; ++t) jp_append<SC_AGENT>(P, st, l, rdy[t], u[t]);
       }
     } else {
       const unsigned k = (unsigned)(it - groups);
-      const unsigned long long ent = fan_entry<S>(Hl, nh, k, hlds);
+      const unsigned long long ent = fan_entry<SC_AGENT>(Hl, nh, k, hlds);
       const int v = (int)(unsigned)ent;
       const unsigned first = (unsigned)(ent >> 32);
-      const int col = jp_colour<S>(P, true, v);
-      if (k == first && lane == 0) sti<S>(&P.color[v], col);
-      const long long b = succ_begin(P, v), e = b + P.nsr[v];
+      const unsigned long long rec = P.rec[v];
+      // the whole wavefront reads v's bitmap: first clear bit
+      const unsigned nw = bm_words((int)(unsigned)rec);
+      int col = 0;
+      for (unsigned w0 = 0; w0 < nw && !col; w0 += WAVE) {
+        const unsigned w = w0 + lane;
+        const unsigned wd = w < nw ? bm_load(P, (rec >> 32) + w) : ~0u;
+        int f = ~wd ? (int)(w * 32) + __ffs((int)~wd) - 1 : 0x7fffffff;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          const int g = __shfl_xor(f, o, WAVE);
+          f = g < f ? g : f;
+        }
+        if (f != 0x7fffffff) col = f + 1;
+      }
+      if (!col) {
+        if (lane == 0) atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
+        col = (int)(unsigned)rec + 1;
+      }
+      if (k == first && lane == 0) sti<SC_AGENT>(&P.color[v], col);
+      const long long b = P.rp[v] + (int)(unsigned)rec, e = b + P.nsr[v];
       const long long s0 = b + (long long)(k - first) * JP_CHUNK;
       const long long s1 = s0 + JP_CHUNK < e ? s0 + JP_CHUNK : e;
-      jp_succ_range<S>(P, st, l, col, s0, s1);
+      jp_push_range(P, st, l, col, s0, s1);
     }
-  }
-}
-
-// ---- per-round operations
-
-__device__ __forceinline__ long long seg_begin(const Params& P, int r) { return (long long)P.n - P.roundN[r]; }
-__device__ __forceinline__ long long seg_size(const Params& P, int r) {
-  return (long long)P.roundN[r] - (long long)P.roundN[r + 1];
-}
-__device__ __forceinline__ int seg_vertex(const Params& P, long long i) { return P.ord_identity ? (int)i : P.ORD[i]; }
-
-// Level 0 of round r: its vertices whose count is already zero.  Also lists
-// the round's vertices with more than JP_SMALL earlier-round successors for
-// the push (chunked across wavefronts), in PH with its counter phctr.
-template <int S>
-__device__ void jp_frontier_items(const Params& P, JpStage& st, int r, long long gw, long long gstride) {
-  const long long b = seg_begin(P, r), sz = seg_size(P, r);
-  const unsigned lane = lane_id();
-  for (long long g = gw; g * WAVE < sz; g += gstride) {
-    long long i = g * WAVE + lane;
-    bool ok = i < sz;
-    int v = ok ? seg_vertex(P, b + i) : 0;
-    bool rdy = ok && (ld64<S>(&P.word[v]) >> JP_MASK_BITS) == 0;
-    jp_append<S>(P, st, -1, rdy, v);
-    if (ok && !P.ord_identity) {
-      long long sb = succ_begin(P, v) + P.nsr[v], se = P.rp[v + 1];
-      if (se - sb > JP_SMALL) {
-        unsigned long long nch = (unsigned long long)((se - sb + JP_CHUNK - 1) / JP_CHUNK);
-        unsigned long long old = add64<S>(st.phctr, (nch << 32) | 1ull);
-        unsigned pos = (unsigned)old;
-        if (pos < P.hub_cap) st64<S>(&P.PH[pos], (old & 0xffffffff00000000ull) | (unsigned)v);
-        else atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
-      }
-    }
-  }
-}
-
-// Bulk push of round r's colours to earlier-round successors.  Items: groups
-// of 64 vertices of the round (a lane each, for at most JP_SMALL successors),
-// then the JP_CHUNK-sized chunks of the longer ranges listed in PH.
-template <int S>
-__device__ void jp_push_items(const Params& P, int r, unsigned long long phc, long long gw, long long gstride,
-                              const unsigned long long* plds) {
-  const long long b = seg_begin(P, r), sz = seg_size(P, r);
-  const unsigned lane = lane_id();
-  const long long groups = (sz + WAVE - 1) / WAVE;
-  const unsigned nh = (unsigned)phc, nch = (unsigned)(phc >> 32);
-  for (long long it = gw; it < groups + (long long)nch; it += gstride) {
-    if (it < groups) {
-      long long i = it * WAVE + lane;
-      bool act = i < sz;
-      int v = act ? seg_vertex(P, b + i) : 0;
-      long long s0 = 0, s1 = 0;
-      int col = 0;
-      if (act) {
-        s0 = succ_begin(P, v) + P.nsr[v];
-        s1 = P.rp[v + 1];
-        act = s1 - s0 <= JP_SMALL;  // longer ranges are chunks
-        if (act) col = ldi<S>(&P.color[v]);
-      }
-      for (long long j = s0; ballot(act && j < s1); j += JP_UNROLL) {
-#pragma unroll
-        for (int t = 0; t < JP_UNROLL; ++t)
-          if (act && j + t < s1) jp_push_one<S>(P, P.dag[j + t], col);
-      }
-    } else {
-      const unsigned k = (unsigned)(it - groups);
-      const unsigned long long ent = fan_entry<S>(P.PH, nh, k, plds);
-      const int v = (int)(unsigned)ent;
-      const unsigned first = (unsigned)(ent >> 32);
-      const long long sb = succ_begin(P, v) + P.nsr[v], se = P.rp[v + 1];
-      const long long s0 = sb + (long long)(k - first) * JP_CHUNK;
-      const long long s1 = s0 + JP_CHUNK < se ? s0 + JP_CHUNK : se;
-      const int cc = ldi<S>(&P.color[v]);
-#pragma unroll
-      for (int t = 0; t < JP_UNROLL; ++t) {
-        long long j = s0 + t * WAVE + lane;
-        if (j < s1) jp_push_one<S>(P, P.dag[j], cc);
-      }
-    }
-  }
-}
-
-// ---- a narrow level in one block, balanced over edges
-
-struct NarrowLds {
-  int v[JP_NARROW_MAX];            // the level's vertices
-  int col[JP_NARROW_MAX];          // their colours
-  long long b[JP_NARROW_MAX];      // first same-round successor in dag
-  unsigned off[JP_NARROW_MAX + 1]; // exclusive scan of same-round successor counts
-  unsigned wsum[NARROW_BS / WAVE];
-};
-
-// Colour of v computed by one thread (its word is final: v is ready).
-template <int S>
-__device__ __forceinline__ int jp_colour_thread(const Params& P, int v) {
-  unsigned long long M = ld64<S>(&P.word[v]) & JP_MASK;
-  if (M != JP_MASK) return __ffsll((long long)~M);
-  const int e0 = P.eoff[v], e1 = P.eoff[v + 1];
-  for (int k = e0; k < e1; ++k) {
-    unsigned long long wd = ld64<S>(&P.ext[k]);
-    if (~wd) return JP_MASK_BITS + 1 + (k - e0) * 64 + __ffsll((long long)~wd) - 1;
-  }
-  atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
-  return JP_MASK_BITS + 1 + (e1 - e0) * 64;
-}
-
-// Level l with nf plain and nh fan-out vertices (nf + nh <= JP_NARROW_MAX):
-// colour every vertex (a thread each), scan the same-round successor counts,
-// then let every thread update single successors.
-template <int S>
-__device__ void jp_level_narrow(const Params& P, JpStage& st, NarrowLds& Z, int l, unsigned nf, unsigned nh) {
-  const unsigned nv = nf + nh;
-  const unsigned* Fl = P.F[l & 1];
-  const unsigned long long* Hl = P.H[l & 1];
-  const int tid = threadIdx.x;
-  // 1. colours
-  for (unsigned i = tid; i < nv; i += NARROW_BS) {
-    int v = i < nf ? (int)ld32<S>(&Fl[i]) : (int)(unsigned)ld64<S>(&Hl[i - nf]);
-    int c = jp_colour_thread<S>(P, v);
-    sti<S>(&P.color[v], c);
-    Z.v[i] = v;
-    Z.col[i] = c;
-    Z.b[i] = succ_begin(P, v);
-    Z.off[i] = (unsigned)P.nsr[v];
-  }
-  __syncthreads();
-  // 2. exclusive scan of Z.off[0 .. nv) (two entries per thread)
-  const unsigned lane = lane_id();
-  const int w = tid / WAVE;
-  const unsigned a0 = 2u * tid < nv ? Z.off[2 * tid] : 0;
-  const unsigned a1 = 2u * tid + 1 < nv ? Z.off[2 * tid + 1] : 0;
-  unsigned incl = a0 + a1;
-#pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) {
-    unsigned t = __shfl_up(incl, o, WAVE);
-    if ((int)lane >= o) incl += t;
-  }
-  if (lane == WAVE - 1) Z.wsum[w] = incl;
-  __syncthreads();
-  unsigned pre = 0, total = 0;
-  for (int k = 0; k < NARROW_BS / WAVE; ++k) {
-    if (k < w) pre += Z.wsum[k];
-    total += Z.wsum[k];
-  }
-  __syncthreads();
-  const unsigned ex = pre + incl - (a0 + a1);
-  if (2u * tid < nv) Z.off[2 * tid] = ex;
-  if (2u * tid + 1 < nv) Z.off[2 * tid + 1] = ex + a0;
-  if (tid == 0) Z.off[nv] = total;
-  __syncthreads();
-  // 3. one successor per thread and step
-  for (unsigned e0 = 0; e0 < total; e0 += NARROW_BS * JP_UNROLL) {
-    int u[JP_UNROLL], cc[JP_UNROLL];
-    bool ok[JP_UNROLL];
-#pragma unroll
-    for (int t = 0; t < JP_UNROLL; ++t) {
-      const unsigned e = e0 + t * NARROW_BS + tid;
-      ok[t] = e < total;
-      u[t] = 0;
-      cc[t] = 0;
-      if (ok[t]) {
-        unsigned lo = 0, hi = nv;  // last i with off[i] <= e
-        while (hi - lo > 1) {
-          unsigned mid = (lo + hi) >> 1;
-          if (Z.off[mid] <= e) lo = mid;
-          else hi = mid;
-        }
-        u[t] = P.dag[Z.b[lo] + (e - Z.off[lo])];
-        cc[t] = Z.col[lo];
-      }
-    }
-    bool rdy[JP_UNROLL];
-#pragma unroll
-    for (int t = 0; t < JP_UNROLL; ++t) rdy[t] = ok[t] && jp_touch<S>(P, u[t], cc[t]);
-#pragma unroll
-    for (int t = 0; t < JP_UNROLL; ++t) jp_append<S>(P, st, l, rdy[t], u[t]);
   }
 }
 
 // ---- JP state machine (plain accesses: the state is in LDS while the
 // single-block kernel runs, in the control block between kernels)
 
-__device__ __forceinline__ void jp_decide_level(JpState& j, int l) {
-  const unsigned nf = j.fcnt[l % 3];
-  const unsigned nh = (unsigned)j.hctr[l % 3];
-  if (nf == 0 && nh == 0) {
-    j.phase = PH_PUSH;
-    return;
-  }
-  j.mode = (nf + nh > (unsigned)JP_NARROW_MAX || j.ecnt[l % 3] > (unsigned long long)JP_NARROW_EDGES)
-               ? JP_MODE_WIDE
-               : JP_MODE_NARROW;
+__device__ __forceinline__ void jp_clear_level(JpState& j, int idx) {
+  j.fcnt[idx] = 0;
+  j.hctr[idx] = 0;
+  j.psum[idx] = 0;
+  j.ssum[idx] = 0;
 }
 
-// Start round r: level lists empty, level 0 to be scanned.
+// Start round r: its later-round colours still to be pulled in (except in
+// the top round), its first level still only in L0.
 __device__ __forceinline__ void jp_begin_round(JpState& j, int r) {
   j.round = r;
-  if (r <= 0) {
-    j.done = 1;
-    return;
-  }
-  j.phase = PH_FRONTIER;
-  j.level = -1;
-  for (int k = 0; k < 3; ++k) {
-    j.fcnt[k] = 0;
-    j.hctr[k] = 0;
-    j.ecnt[k] = 0;
-  }
-  j.phctr = 0;
+  j.level = 0;
+  j.split = 1;
+  j.xpull = r < j.top ? 1 : 0;
+  for (int k = 0; k < 3; ++k) jp_clear_level(j, k);
+  if (r <= 0) j.done = 1;
 }
 
-// After level l's items have been processed (or level 0 was scanned, l = -1).
-__device__ __forceinline__ void jp_next_level(JpState& j, int l) {
-  const int nl = l + 1;
-  j.level = nl;
-  j.fcnt[(nl + 1) % 3] = 0;
-  j.hctr[(nl + 1) % 3] = 0;
-  j.ecnt[(nl + 1) % 3] = 0;
-  if (nl == 0) j.F += j.fcnt[0] + (unsigned)j.hctr[0];
-  else j.levels += 1;
-  j.phase = PH_LEVEL;
-  jp_decide_level(j, nl);
+// Level l has been processed: level l + 1 becomes current.
+__device__ __forceinline__ void jp_next_level(JpState& j) {
+  j.levels += 1;
+  j.level += 1;
+  jp_clear_level(j, (j.level + 1) % 3);
 }
 
-// Work of round r's push, in successor entries, capped at limit + 1.
-__device__ long long jp_push_work(const Params& P, int r, long long limit) {
-  __shared__ unsigned long long acc;
-  if (threadIdx.x == 0) acc = 0;
-  __syncthreads();
-  const long long b = seg_begin(P, r), sz = seg_size(P, r);
-  unsigned long long mine = 0;
-  for (long long i = threadIdx.x; i < sz; i += blockDim.x) {
-    int v = seg_vertex(P, b + i);
-    mine += (unsigned long long)(P.rp[v + 1] - succ_begin(P, v) - P.nsr[v]);
+// Work of a level, as the single block sees it: bitmap words + successors.
+__device__ __forceinline__ bool jp_fits_narrow(unsigned nv, unsigned long long words, unsigned long long succs) {
+  return nv <= (unsigned)NARROW_MAX && words <= (unsigned long long)NARROW_WORDS &&
+         succs <= (unsigned long long)NARROW_SUCC;
+}
+
+// ---- narrow levels: one block, level lists in LDS
+
+struct NarrowLds {
+  int v[2][NARROW_MAX];                  // level lists (current / next)
+  long long pb[2][NARROW_MAX];           // first entry of the row in dag
+  unsigned long long rec[2][NARROW_MAX]; // bitmap offset and |pred|
+  int ns[2][NARROW_MAX];                 // same-round successors
+  unsigned woff[NARROW_MAX + 1];         // exclusive scans of bitmap words and successors
+  unsigned soff[NARROW_MAX + 1];
+  int ffree[NARROW_MAX];                 // first clear bit of each vertex's bitmap
+  int col[NARROW_MAX];
+  unsigned wsum[2][NARROW_BS / WAVE];
+  unsigned cnt[2];                       // list sizes
+  unsigned long long wds[2], sus[2];     // their bitmap words and successors
+  WaveLds wl[NARROW_BS / WAVE];
+};
+
+// Append u (bitmap urec) to the next LDS list (slot `nx`), or -- past its
+// capacity -- to the global lists of level l + 1.  Loads u's row metadata
+// for the next level.
+__device__ __forceinline__ void narrow_append(const Params& P, NarrowLds& Z, JpStage& st, int nx, int l, bool rdy,
+                                              int u, unsigned long long urec) {
+  long long pb = 0;
+  int ns = 0;
+  if (rdy) {
+    pb = P.rp[u];
+    ns = P.nsr[u];
   }
-  mine = wave_sum(mine);
-  if (lane_id() == 0) atomicAdd(&acc, mine);
-  __syncthreads();
-  long long w = (long long)acc;
-  __syncthreads();
-  return w > limit ? limit + 1 : w;
+  const uint64_t m = ballot(rdy);
+  if (!m) return;
+  const unsigned long long ws = wave_sum((unsigned long long)(rdy ? bm_words((int)(unsigned)urec) : 0));
+  const unsigned long long ss = wave_sum((unsigned long long)ns);
+  unsigned base = 0;
+  if (lane_id() == 0) {
+    base = atomicAdd(&Z.cnt[nx], (unsigned)__popcll(m));
+    atomicAdd(&Z.wds[nx], ws);
+    atomicAdd(&Z.sus[nx], ss);
+  }
+  base = readlane_u(base, 0);
+  const unsigned pos = base + lanes_below(m);
+  const bool lds = rdy && pos < (unsigned)NARROW_MAX;
+  if (lds) {
+    Z.v[nx][pos] = u;
+    Z.pb[nx][pos] = pb;
+    Z.rec[nx][pos] = urec;
+    Z.ns[nx][pos] = ns;
+  }
+  if (base + __popcll(m) > (unsigned)NARROW_MAX) jp_append<SC_WG>(P, st, l, rdy && !lds, u);
 }
 
-// One block.  Finishes what the grid kernel has just done, then runs every
-// step one block can take (scans of small rounds, narrow levels, small
-// pushes) with its state in LDS, until JP ends or a step needs the grid.
+// Block-wide: the LDS entries of list `cur` (level l) to the global lists of
+// level l (the level's sums are set by the caller).
+__device__ void narrow_flush(const Params& P, NarrowLds& Z, JpStage& st, int cur, int l) {
+  const unsigned n = Z.cnt[cur] < (unsigned)NARROW_MAX ? Z.cnt[cur] : (unsigned)NARROW_MAX;
+  for (unsigned b = 0; b < n; b += NARROW_BS) {
+    const unsigned i = b + threadIdx.x;
+    const bool ok = i < n;
+    const int v = ok ? Z.v[cur][i] : 0;
+    const int ns = ok ? Z.ns[cur][i] : 0;
+    const bool fan = ok && ns > JP_SMALL;
+    if (fan) {
+      unsigned long long nch = (unsigned long long)((ns + JP_CHUNK - 1) / JP_CHUNK);
+      unsigned long long old = add64<SC_WG>(&st.hctr[l % 3], (nch << 32) | 1ull);
+      unsigned pos = (unsigned)old;
+      if (pos < P.hub_cap) st64<SC_WG>(&P.H[l & 1][pos], (old & 0xffffffff00000000ull) | (unsigned)v);
+      else atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
+    }
+    const uint64_t m = ballot(ok && !fan);
+    if (m) {
+      unsigned g = 0;
+      if (lane_id() == 0) g = add32<SC_WG>(&st.fcnt[l % 3], (unsigned)__popcll(m));
+      g = readlane_u(g, 0);
+      if (ok && !fan) sti<SC_WG>((int*)&P.F[l & 1][g + lanes_below(m)], v);
+    }
+  }
+}
+
+// Block-wide: n vertices from a global list into LDS list `cur` at `at`.
+__device__ void narrow_load(const Params& P, NarrowLds& Z, int cur, const unsigned* src, unsigned n) {
+  for (unsigned i = threadIdx.x; i < n; i += NARROW_BS) {
+    const int v = (int)ld32<SC_AGENT>(&src[i]);
+    Z.v[cur][i] = v;
+    Z.pb[cur][i] = P.rp[v];
+    Z.rec[cur][i] = P.rec[v];
+    Z.ns[cur][i] = P.nsr[v];
+  }
+}
+__device__ void narrow_load_fan(const Params& P, NarrowLds& Z, int cur, const unsigned long long* src, unsigned n,
+                                unsigned at) {
+  for (unsigned i = threadIdx.x; i < n; i += NARROW_BS) {
+    const int v = (int)(unsigned)ld64<SC_AGENT>(&src[i]);
+    Z.v[cur][at + i] = v;
+    Z.pb[cur][at + i] = P.rp[v];
+    Z.rec[cur][at + i] = P.rec[v];
+    Z.ns[cur][at + i] = P.nsr[v];
+  }
+}
+
+// Block-wide exclusive scans of two per-thread values (thread t: entry t).
+__device__ void narrow_scan2(NarrowLds& Z, unsigned a0, unsigned a1, unsigned nv) {
+  const unsigned lane = lane_id();
+  const int w = threadIdx.x / WAVE;
+  unsigned i0 = a0, i1 = a1;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const unsigned t0 = __shfl_up(i0, o, WAVE), t1 = __shfl_up(i1, o, WAVE);
+    if ((int)lane >= o) {
+      i0 += t0;
+      i1 += t1;
+    }
+  }
+  if (lane == WAVE - 1) {
+    Z.wsum[0][w] = i0;
+    Z.wsum[1][w] = i1;
+  }
+  __syncthreads();
+  unsigned p0 = 0, p1 = 0, s0 = 0, s1 = 0;
+  for (int k = 0; k < NARROW_BS / WAVE; ++k) {
+    const unsigned x0 = Z.wsum[0][k], x1 = Z.wsum[1][k];
+    if (k < w) {
+      p0 += x0;
+      p1 += x1;
+    }
+    s0 += x0;
+    s1 += x1;
+  }
+  const unsigned t = threadIdx.x;
+  if (t < nv) {
+    Z.woff[t] = p0 + i0 - a0;
+    Z.soff[t] = p1 + i1 - a1;
+    Z.ffree[t] = 0x7fffffff;
+  }
+  if (t == 0) {
+    Z.woff[nv] = s0;
+    Z.soff[nv] = s1;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ unsigned owner(const unsigned* off, unsigned nv, unsigned e) {
+  unsigned lo = 0, hi = nv;  // last k < nv with off[k] <= e
+  while (hi - lo > 1) {
+    const unsigned mid = (lo + hi) >> 1;
+    if (off[mid] <= e) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// One narrow level (list `cur`, level l): read the bitmaps and colour every
+// vertex; then push the colours to the same-round successors and append the
+// ready ones to list `nx`.
+__device__ void narrow_level(const Params& P, NarrowLds& Z, JpStage& st, int cur, int nx, int l) {
+  const unsigned nv = Z.cnt[cur];
+  const unsigned t = threadIdx.x;
+  {
+    const bool ok = t < nv;
+    narrow_scan2(Z, ok ? bm_words((int)(unsigned)Z.rec[cur][t]) : 0, ok ? (unsigned)Z.ns[cur][t] : 0, nv);
+  }
+  const unsigned wtot = Z.woff[nv], stot = Z.soff[nv];
+  // bitmap words -> first clear bit per vertex; successors of the first
+  // pass fetched meanwhile
+  int su[NARROW_UNROLL];
+  unsigned sk[NARROW_UNROLL];
+  unsigned long long sr[NARROW_UNROLL];
+#pragma unroll
+  for (int q = 0; q < NARROW_UNROLL; ++q) {
+    const unsigned e = q * NARROW_BS + t;
+    su[q] = -1;
+    sk[q] = 0;
+    if (e < stot) {
+      sk[q] = owner(Z.soff, nv, e);
+      su[q] = P.dag[Z.pb[cur][sk[q]] + (int)(unsigned)Z.rec[cur][sk[q]] + (e - Z.soff[sk[q]])];
+    }
+  }
+  for (unsigned e0 = 0; e0 < wtot; e0 += NARROW_BS * NARROW_UNROLL) {
+    unsigned k[NARROW_UNROLL], wd[NARROW_UNROLL];
+#pragma unroll
+    for (int q = 0; q < NARROW_UNROLL; ++q) {
+      const unsigned e = e0 + q * NARROW_BS + t;
+      wd[q] = ~0u;
+      k[q] = 0;
+      if (e < wtot) {
+        k[q] = owner(Z.woff, nv, e);
+        wd[q] = bm_load(P, (Z.rec[cur][k[q]] >> 32) + (e - Z.woff[k[q]]));
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NARROW_UNROLL; ++q)
+      if (~wd[q]) {
+        const unsigned e = e0 + q * NARROW_BS + t;
+        atomicMin(&Z.ffree[k[q]], (int)((e - Z.woff[k[q]]) * 32) + __ffs((int)~wd[q]) - 1);
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < NARROW_UNROLL; ++q) sr[q] = su[q] >= 0 ? P.rec[su[q]] : 0;
+  __syncthreads();
+  // GetColor
+  if (t < nv) {
+    const int f = Z.ffree[t];
+    int c;
+    if (f == 0x7fffffff) {  // unreachable: at most |pred| of the |pred|+2 bits are set
+      atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
+      c = (int)(unsigned)Z.rec[cur][t] + 1;
+    } else {
+      c = f + 1;
+    }
+    Z.col[t] = c;
+    sti<SC_WG>(&P.color[Z.v[cur][t]], c);
+  }
+  __syncthreads();
+  // push the colours to the same-round successors
+  for (unsigned e0 = 0; e0 < stot; e0 += NARROW_BS * NARROW_UNROLL) {
+    if (e0 > 0) {
+#pragma unroll
+      for (int q = 0; q < NARROW_UNROLL; ++q) {
+        const unsigned e = e0 + q * NARROW_BS + t;
+        su[q] = -1;
+        sk[q] = 0;
+        if (e < stot) {
+          sk[q] = owner(Z.soff, nv, e);
+          su[q] = P.dag[Z.pb[cur][sk[q]] + (int)(unsigned)Z.rec[cur][sk[q]] + (e - Z.soff[sk[q]])];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < NARROW_UNROLL; ++q) sr[q] = su[q] >= 0 ? P.rec[su[q]] : 0;
+    }
+    bool rdy[NARROW_UNROLL];
+#pragma unroll
+    for (int q = 0; q < NARROW_UNROLL; ++q) rdy[q] = su[q] >= 0 && jp_push<SC_WG>(P, su[q], sr[q], Z.col[sk[q]]);
+#pragma unroll
+    for (int q = 0; q < NARROW_UNROLL; ++q) narrow_append(P, Z, st, nx, l, rdy[q], su[q], sr[q]);
+  }
+  order_point();
+  __syncthreads();
+}
+
+// One block.  Finishes the state change of what the grid kernel has just
+// done, then runs every step one block can take (the later-round colours of
+// a small round, levels that fit) with the level lists in LDS, until JP ends
+// or a step needs the grid.
 __global__ __launch_bounds__(NARROW_BS) void k_jp_narrow(Params P, int max_steps) {
   Ctrl* c = P.ctrl;
-  __shared__ unsigned fbuf[FB_CAP];
-  __shared__ unsigned fcnt;
   __shared__ JpState S;
   __shared__ NarrowLds Z;
+  __shared__ int have;   // the current level is in LDS list `cur`
   if (threadIdx.x == 0) {
-    fcnt = 0;
     S = c->js;
+    have = 0;
     if (!S.done && c->grid_ran) {
       const int op = c->grid_op;
       c->grid_ran = 0;
       c->grid_op = OP_NONE;
-      if (op == OP_FRONTIER) jp_next_level(S, -1);
-      else if (op == OP_LEVEL) jp_next_level(S, S.level);
-      else if (op == OP_PUSH) jp_begin_round(S, S.round - 1);
+      if (op == OP_XPULL) S.xpull = 0;
+      else if (op == OP_SPLIT) S.split = 0;
+      else if (op == OP_LEVEL) jp_next_level(S);
     }
   }
   __syncthreads();
-  JpStage st{fbuf, &fcnt, S.fcnt, S.hctr, S.ecnt, &S.phctr};
-  const long long gw = threadIdx.x / WAVE;
-  const long long gstride = NARROW_BS / WAVE;
+  JpStage st{nullptr, nullptr, S.fcnt, S.hctr, S.psum, S.ssum};
+  WaveLds& W = Z.wl[threadIdx.x / WAVE];
+  int cur = 0;
   int handed = OP_NONE;
-  for (int step = 0; step < max_steps && !S.done; ++step) {
+  for (int step = 0; step < max_steps; ++step) {
+    if (S.done) break;
     const int r = S.round;
-    if (S.phase == PH_FRONTIER) {
-      if (seg_size(P, r) > NARROW_SCAN) {
-        handed = OP_FRONTIER;
-      } else {
-        jp_frontier_items<SC_WG>(P, st, r, gw, gstride);
-        order_point();
-        jp_stage_flush<SC_WG>(P, st, -1);
-        order_point();
-        __syncthreads();
-        if (threadIdx.x == 0) jp_next_level(S, -1);
+    const int l = S.level;
+    if (S.xpull) {
+      if (seg_size(P, r) > (long long)NARROW_XPULL) {
+        handed = OP_XPULL;
+        break;
       }
-    } else if (S.phase == PH_LEVEL) {
-      if (S.mode == JP_MODE_WIDE) {
+      jp_xpull_items<SC_WG>(P, W, r, threadIdx.x / WAVE, NARROW_BS / WAVE);
+      order_point();
+      __syncthreads();
+      if (threadIdx.x == 0) S.xpull = 0;
+      __syncthreads();
+      continue;
+    }
+    if (!have) {
+      if (S.split) {
+        // the round's first level, from L0
+        const unsigned n0 = P.l0n[r];
+        if (n0 > (unsigned)NARROW_MAX) {
+          handed = OP_SPLIT;
+          break;
+        }
+        narrow_load(P, Z, cur, P.L0 + seg_begin(P, r), n0);
+        if (threadIdx.x == 0) {
+          Z.cnt[cur] = n0;
+          S.split = 0;
+          S.F += n0;
+        }
+      } else {
+        const unsigned nf = S.fcnt[l % 3], nh = (unsigned)S.hctr[l % 3];
+        if (nf + nh == 0) {  // round finished
+          __syncthreads();
+          if (threadIdx.x == 0) jp_begin_round(S, r - 1);
+          __syncthreads();
+          continue;
+        }
+        if (!jp_fits_narrow(nf + nh, S.psum[l % 3], S.ssum[l % 3])) {
+          handed = OP_LEVEL;
+          break;
+        }
+        narrow_load(P, Z, cur, P.F[l & 1], nf);
+        narrow_load_fan(P, Z, cur, P.H[l & 1], nh, nf);
+        if (threadIdx.x == 0) Z.cnt[cur] = nf + nh;
+      }
+      __syncthreads();
+      // sums of the loaded level (level 0 of a round is not counted yet)
+      unsigned long long ws = 0, ss = 0;
+      for (unsigned i = threadIdx.x; i < Z.cnt[cur]; i += NARROW_BS) {
+        ws += (unsigned long long)bm_words((int)(unsigned)Z.rec[cur][i]);
+        ss += (unsigned long long)Z.ns[cur][i];
+      }
+      ws = wave_sum(ws);
+      ss = wave_sum(ss);
+      if (threadIdx.x == 0) {
+        Z.wds[cur] = 0;
+        Z.sus[cur] = 0;
+      }
+      __syncthreads();
+      if (lane_id() == 0) {
+        atomicAdd(&Z.wds[cur], ws);
+        atomicAdd(&Z.sus[cur], ss);
+      }
+      __syncthreads();
+      if (!jp_fits_narrow(Z.cnt[cur], Z.wds[cur], Z.sus[cur])) {
+        // too much work for one block: to the global lists, for the grid
+        if (threadIdx.x == 0) {
+          jp_clear_level(S, l % 3);
+          S.psum[l % 3] = Z.wds[cur];
+          S.ssum[l % 3] = Z.sus[cur];
+        }
+        __syncthreads();
+        narrow_flush(P, Z, st, cur, l);
+        order_point();
         handed = OP_LEVEL;
-      } else {
-        const int l = S.level;
-        jp_level_narrow<SC_WG>(P, st, Z, l, S.fcnt[l % 3], (unsigned)S.hctr[l % 3]);
-        order_point();
-        jp_stage_flush<SC_WG>(P, st, l);
-        order_point();
-        __syncthreads();
-        if (threadIdx.x == 0) jp_next_level(S, l);
+        break;
       }
-    } else {  // PH_PUSH
-      const long long work = P.ord_identity ? 0 : jp_push_work(P, r, NARROW_PUSH_WORK);
-      if (work > NARROW_PUSH_WORK) {
-        handed = OP_PUSH;
-      } else {
-        if (work > 0) jp_push_items<SC_WG>(P, r, S.phctr, gw, gstride, nullptr);
-        order_point();
-        __syncthreads();
-        if (threadIdx.x == 0) jp_begin_round(S, r - 1);
+      if (threadIdx.x == 0) have = 1;
+      __syncthreads();
+    }
+    // process level l from LDS list `cur`
+    const int nx = cur ^ 1;
+    if (threadIdx.x == 0) {
+      Z.cnt[nx] = 0;
+      Z.wds[nx] = 0;
+      Z.sus[nx] = 0;
+    }
+    __syncthreads();
+    if (Z.cnt[cur] == 0) {  // nothing ready: the round is finished
+      if (threadIdx.x == 0) {
+        jp_begin_round(S, r - 1);
+        have = 0;
+      }
+      __syncthreads();
+      continue;
+    }
+    narrow_level(P, Z, st, cur, nx, l);
+    const unsigned nn = Z.cnt[nx];
+    const bool fits = jp_fits_narrow(nn, Z.wds[nx], Z.sus[nx]);
+    if (nn > 0 && !fits) {
+      // the next level goes to the grid: its overflow entries are already in
+      // the global lists; add the LDS ones
+      if (threadIdx.x == 0) {
+        S.psum[(l + 1) % 3] = Z.wds[nx];
+        S.ssum[(l + 1) % 3] = Z.sus[nx];
+      }
+      __syncthreads();
+      narrow_flush(P, Z, st, nx, l + 1);
+      order_point();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      jp_next_level(S);
+      if (nn == 0) {
+        jp_begin_round(S, r - 1);
+        have = 0;
+      } else if (!fits) {
+        have = 0;
       }
     }
     __syncthreads();
-    if (handed != OP_NONE) break;
+    cur = nx;
+    if (nn > 0 && !fits) {
+      handed = OP_LEVEL;
+      break;
+    }
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
+    if (have) {  // step bound reached with a level still in LDS: a broken state
+      atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
+      S.done = 1;
+    }
     c->js = S;
     c->grid_op = handed;
     order_point();
@@ -1279,25 +1532,26 @@ __global__ __launch_bounds__(BS) void k_jp_grid(Params P) {
   __shared__ unsigned fbuf[FB_CAP];
   __shared__ unsigned fcnt;
   __shared__ unsigned long long flds[FAN_LDS];
+  __shared__ WaveLds wl[WPB];
   if (threadIdx.x == 0) fcnt = 0;
   __syncthreads();
-  JpStage st{fbuf, &fcnt, c->js.fcnt, c->js.hctr, c->js.ecnt, &c->js.phctr};
+  JpStage st{fbuf, &fcnt, c->js.fcnt, c->js.hctr, c->js.psum, c->js.ssum};
   const int r = c->js.round;
   const long long gw = (long long)blockIdx.x * WPB + threadIdx.x / WAVE;
   const long long gstride = (long long)gridDim.x * WPB;
-  if (op == OP_FRONTIER) {
-    jp_frontier_items<SC_AGENT>(P, st, r, gw, gstride);
+  WaveLds& W = wl[threadIdx.x / WAVE];
+  if (op == OP_XPULL) {
+    jp_xpull_items<SC_AGENT>(P, W, r, gw, gstride);
+  } else if (op == OP_SPLIT) {
+    jp_split_items(P, st, r, gw, gstride);
     jp_stage_flush<SC_AGENT>(P, st, -1);
-  } else if (op == OP_LEVEL) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&c->js.F, (unsigned long long)P.l0n[r]);
+  } else {
     const int l = c->js.level;
     const unsigned long long hc = c->js.hctr[l % 3];
     const unsigned long long* hl = fan_stage<SC_AGENT>(P.H[l & 1], (unsigned)hc, flds);
-    jp_level_items<SC_AGENT>(P, st, l, c->js.fcnt[l % 3], hc, gw, gstride, hl);
+    jp_level_items(P, st, W, l, c->js.fcnt[l % 3], hc, gw, gstride, hl);
     jp_stage_flush<SC_AGENT>(P, st, l);
-  } else {
-    const unsigned long long phc = c->js.phctr;
-    const unsigned long long* pl = fan_stage<SC_AGENT>(P.PH, (unsigned)phc, flds);
-    jp_push_items<SC_AGENT>(P, r, phc, gw, gstride, pl);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) c->grid_ran = 1;
 }
@@ -1311,6 +1565,7 @@ __global__ void k_jp_start(Params P, int rounds) {
   j.done = 0;
   j.levels = 0;
   j.F = 0;
+  j.top = rounds;
   if (P.ord_identity) {
     P.roundN[1] = (unsigned)P.n;
     P.roundN[2] = 0;
@@ -1447,8 +1702,8 @@ void prof_end(int cls, hipStream_t s, hipEvent_t a) {
 namespace {
 
 struct Layout {
-  size_t ctrl, bcount, boff, bsum, xpart, D, status, UL0, UL1, ORD, roundN, round, dag, npred, nsr, word, F0, F1, H0,
-      H1, PH, hub_cap, eoff, ext, ext_words, total;
+  size_t ctrl, bcount, boff, bsum, xpart, D, status, UL0, UL1, ORD, roundN, round, dag, npred, nsr, cnt, rec, B,
+      bm_cap, L0, l0n, F0, F1, H0, H1, hub_cap, total;
 };
 
 constexpr int UPD_BLOCKS = 2048;
@@ -1477,19 +1732,20 @@ Layout make_layout(int64_t n, int64_t nnz) {
   L.dag = take(4 * (size_t)nnz);
   L.npred = take(4 * nn);
   L.nsr = take(4 * nn);
-  L.word = take(8 * nn);
+  L.cnt = take(4 * nn);
+  L.rec = take(8 * nn);
+  // colour bitmaps: sum over v of ceil((|pred|+2)/32) <= m/32 + 33n/32 words
+  L.bm_cap = (size_t)nnz / 64 + 2 * nn + 64;
+  L.B = take(4 * L.bm_cap);
+  L.L0 = take(4 * nn);
+  L.l0n = take(4 * (nn + 4));
   L.F0 = take(4 * nn);
   L.F1 = take(4 * nn);
-  // fan-out entries: vertices with more than JP_SMALL successors in the
-  // range concerned (level lists, push list), at most m / JP_SMALL of them
+  // fan-out entries: vertices with more than JP_SMALL same-round successors
+  // in a level, at most m / JP_SMALL of them
   L.hub_cap = (size_t)nnz / (2 * JP_SMALL) + 64;
   L.H0 = take(8 * L.hub_cap);
   L.H1 = take(8 * L.hub_cap);
-  L.PH = take(8 * L.hub_cap);
-  L.eoff = take(4 * (nn + 1));
-  // sum over v of ceil((|pred|+1-40)/64) <= m/64 + m/40 < nnz/48, plus slack
-  L.ext_words = (size_t)nnz / 48 + 64;
-  L.ext = take(8 * L.ext_words);
   L.total = off;
   return L;
 }
@@ -1499,6 +1755,8 @@ int check_graph(const adg_csr_t* g) {
   if (g->n < 0 || g->n > 0x7ffffffeLL || g->nnz < 0) return ADG_ERR_ARG;
   if (g->n > 0 && (!g->row_ptr)) return ADG_ERR_ARG;
   if (g->nnz > 0 && !g->col_idx) return ADG_ERR_ARG;
+  // JP's colour bitmaps are addressed with 32-bit word offsets
+  if ((unsigned long long)g->nnz / 64 + 2ull * (unsigned long long)g->n + 64 >= (1ull << 32)) return ADG_ERR_UNSUPPORTED;
   return ADG_OK;
 }
 
@@ -1539,16 +1797,17 @@ Params make_params(const adg_csr_t* g, void* ws, uint64_t p, uint64_t q, uint64_
   P.dag = (int*)(base + L.dag);
   P.npred = (int*)(base + L.npred);
   P.nsr = (int*)(base + L.nsr);
-  P.word = (unsigned long long*)(base + L.word);
+  P.cnt = (int*)(base + L.cnt);
+  P.rec = (unsigned long long*)(base + L.rec);
+  P.B = (unsigned*)(base + L.B);
+  P.bm_cap = L.bm_cap;
+  P.L0 = (unsigned*)(base + L.L0);
+  P.l0n = (unsigned*)(base + L.l0n);
   P.F[0] = (unsigned*)(base + L.F0);
   P.F[1] = (unsigned*)(base + L.F1);
   P.H[0] = (unsigned long long*)(base + L.H0);
   P.H[1] = (unsigned long long*)(base + L.H1);
-  P.PH = (unsigned long long*)(base + L.PH);
   P.hub_cap = (unsigned)L.hub_cap;
-  P.eoff = (int*)(base + L.eoff);
-  P.ext = (unsigned long long*)(base + L.ext);
-  P.ext_cap = L.ext_words;
   P.color = color;
   // Round-count bound from the ADG depth lemma: |U| shrinks by a factor
   // 1/(1+eps) per round, so L <= ceil(log n / log(1+eps)) + 1; +1 margin.
@@ -1562,11 +1821,34 @@ Params make_params(const adg_csr_t* g, void* ws, uint64_t p, uint64_t q, uint64_
   return P;
 }
 
-int* pinned_flags() {
-  static int* h = nullptr;
-  if (!h && hipHostMalloc((void**)&h, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) h = nullptr;
-  return h;
-}
+// Pinned host words through which the host reads the device's loop flags.
+// Every entry-point call takes its own from a pool (calls may run
+// concurrently from several host threads on different streams) and returns
+// it on exit; buffers live until the process ends.
+std::mutex g_flag_mu;
+std::vector<int*> g_flag_pool;
+
+struct PinnedFlags {
+  int* h = nullptr;
+  PinnedFlags() {
+    {
+      std::lock_guard<std::mutex> g(g_flag_mu);
+      if (!g_flag_pool.empty()) {
+        h = g_flag_pool.back();
+        g_flag_pool.pop_back();
+        return;
+      }
+    }
+    if (hipHostMalloc((void**)&h, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) h = nullptr;
+  }
+  ~PinnedFlags() {
+    if (!h) return;
+    std::lock_guard<std::mutex> g(g_flag_mu);
+    g_flag_pool.push_back(h);
+  }
+  PinnedFlags(const PinnedFlags&) = delete;
+  PinnedFlags& operator=(const PinnedFlags&) = delete;
+};
 
 // ADG's round loop.  Synchronises the stream between chunks of rounds.
 int run_adg(Params& P, hipStream_t s, bool fused, int* num_rounds_host) {
@@ -1577,7 +1859,8 @@ int run_adg(Params& P, hipStream_t s, bool fused, int* num_rounds_host) {
   HIPCHK(hipGetLastError());
   *num_rounds_host = 0;
   if (P.n == 0) return ADG_OK;
-  int* h = pinned_flags();
+  PinnedFlags pf;
+  int* h = pf.h;
   if (!h) return ADG_ERR_HIP;
   int l = 1;
   int chunk = 8;
@@ -1634,22 +1917,23 @@ int run_jp(Params& P, hipStream_t s, int rounds) {
   if (P.n == 0) return ADG_OK;
   {
     TIMED(KC_JP_PREP, s);
-    hipLaunchKernelGGL(k_ext_count, dim3(SEL_BLOCKS), dim3(BS), 0, s, P);
-    hipLaunchKernelGGL(k_ext_scan, dim3(1), dim3(BS), 0, s, P);
-    hipLaunchKernelGGL(k_ext_fill, dim3(SEL_BLOCKS), dim3(BS), 0, s, P);
     hipLaunchKernelGGL(k_jp_start, dim3(1), dim3(64), 0, s, P, rounds);
   }
   HIPCHK(hipGetLastError());
-  int* h = pinned_flags();
+  PinnedFlags pf;
+  int* h = pf.h;
   if (!h) return ADG_ERR_HIP;
   int chunk = 2;
   long long pairs = 0;
   const long long max_pairs = 4LL * ((long long)P.n + rounds + 4);
+  // steps of one single-block launch: every step processes a level, loads
+  // one or starts a round
+  const int max_steps = (int)std::min<long long>(0x7fffffff, 3LL * ((long long)P.n + rounds) + 16);
   while (true) {
     for (int k = 0; k < chunk; ++k) {
       {
         TIMED(KC_JP_NARROW, s);
-        hipLaunchKernelGGL(k_jp_narrow, dim3(1), dim3(NARROW_BS), 0, s, P, 1 << 30);
+        hipLaunchKernelGGL(k_jp_narrow, dim3(1), dim3(NARROW_BS), 0, s, P, max_steps);
       }
       {
         TIMED(KC_JP, s);
@@ -1717,7 +2001,8 @@ int jp_color(const adg_csr_t* g, const int32_t* round, uint64_t seed, int32_t* c
       TIMED(KC_PART1, s);
       hipLaunchKernelGGL(k_part1, dim3(P.upd_blocks), dim3(BS), 0, s, P);
     }
-    int* h = pinned_flags();
+    PinnedFlags pf;
+    int* h = pf.h;
     if (!h) return ADG_ERR_HIP;
     HIPCHK(hipMemcpyAsync(h, &P.ctrl->error, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1763,7 +2048,7 @@ int adg_get_stats(const void* workspace, size_t ws_bytes, adg_stats_t* out, void
   out->num_colors = h.num_colors;
   out->sum_active = (int64_t)h.sum_active;
   out->cut_edges = (int64_t)h.cut_edges;
-  out->frontier = h.js.F;
+  out->frontier = (int64_t)h.js.F;
   out->jp_levels = h.js.levels;
   out->error = h.error;
   return ADG_OK;

@@ -120,7 +120,13 @@ def test_batched_config_scaled_down(bt):
     ws = torch.empty(bt.batched_workspace_bytes(batch.num_graphs, batch.total_n, batch.total_nnz),
                      dtype=torch.uint8, device="cuda")
     bt.color_graph_batched(batch, 1, 10, 4, workspace=ws)
-    assert bt.batched_error(ws) == 0
+    st = bt.batched_stats(ws)
+    assert st["error"] == 0
+    # batch-wide counters against the oracle's per-graph counters
+    ost = [oracle.color_graph(rp, col, 1, 10, 4) for rp, col in graphs]
+    assert st["sum_active"] == sum(o[4]["sum_active"] for o in ost)
+    assert st["cut_edges"] == sum(o[4]["cut_edges"] for o in ost)
+    assert st["num_rounds"] == max(o[3] for o in ost) and st["num_colors"] == max(o[1] for o in ost)
 
 
 def test_graph_capture_replays(bt):
