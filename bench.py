@@ -185,7 +185,7 @@ def run_single(args, w):
     torch.cuda.synchronize()
     log("warm-up done")
     adg.profile_read()  # drop anything recorded so far
-    adg.profile_enable(["update", "jp", "jp_narrow"])
+    adg.profile_enable(["update", "update_huge", "jp", "jp_narrow"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -202,7 +202,8 @@ def run_single(args, w):
     # bytes are charged to the two together.
     jp_ms = prof.get("jp", (0, 0))[0] + prof.get("jp_narrow", (0, 0))[0]
     jp_launches = prof.get("jp", (0, 0))[1] + prof.get("jp_narrow", (0, 0))[1]
-    upd_ms, upd_launches = prof.get("update", (0.0, 0))
+    upd_ms = prof.get("update", (0.0, 0))[0] + prof.get("update_huge", (0.0, 0))[0]
+    upd_launches = prof.get("update", (0.0, 0))[1]
     if jp_ms >= upd_ms:
         dom, tot_ms, launches, kname = "jp", jp_ms, jp_launches, "k_jp_narrow+k_jp_grid"
     else:

@@ -266,7 +266,8 @@ int adg_validate_csr(const adg_csr_t* g, void* workspace, size_t ws_bytes, void*
  * adg_profile_enable(mask) makes every later launch of a kernel class whose
  * bit is set in `mask` (classes: 0 init, 1 stats, 2 count, 3 scan,
  * 4 scatter, 5 update, 6 part1, 7 jp_prep, 8 jp (grid-wide JP steps),
- * 9 finish, 10 batched, 11 jp_narrow (single-block JP steps))
+ * 9 finish, 10 batched, 11 jp_narrow (single-block JP steps), 12 update_huge
+ * (UPDATE of rows longer than 16384 entries, cut into chunks))
  * record a pair of HIP events on its launch stream; 0 disables it.
  * adg_profile_read waits for the recorded events, adds up the elapsed time
  * and launch count per class into *out and forgets the records.  Process-wide,

@@ -47,7 +47,7 @@ class _Profile(ctypes.Structure):
 
 
 KERNEL_CLASSES = ["init", "stats", "count", "scan", "scatter", "update", "part1", "jp_prep", "jp", "finish",
-                  "batched", "jp_narrow"]
+                  "batched", "jp_narrow", "update_huge"]
 
 _lib = None
 

@@ -52,15 +52,17 @@ constexpr int BS = 256;                 // threads per block
 constexpr int WPB = BS / WAVE;          // wavefronts per block
 constexpr int SEL_BLOCKS = 2048;        // fixed grid of the selection kernels
 constexpr int SMALL_DEG = 32;           // lane-per-vertex rows up to this length
+constexpr int HUGE_DEG = 16384;         // rows longer than this are cut into chunks in UPDATE
+constexpr int HUGE_CHUNK = 4096;        // entries of such a chunk
 constexpr int FB_CAP = 2048;            // per-block staging of level lists (LDS)
-constexpr int JP_SMALL = 32;            // lane-per-vertex successor loops
+constexpr int JP_SMALL = 4;             // lane-per-vertex successor loops
 constexpr int JP_UNROLL = 4;
 constexpr int JP_CHUNK = WAVE * JP_UNROLL;   // successors per wavefront step / fan-out chunk
 constexpr int FAN_LDS = 1024;                // fan-out list entries a grid block stages in LDS
 constexpr int NARROW_BS = 1024;              // threads of the single-block JP kernel
 constexpr int NARROW_MAX = 1024;             // level size the single block takes
-constexpr int NARROW_WORDS = 8192;           // colour bitmap words of a level it takes
-constexpr int NARROW_SUCC = 8192;            // same-round successor entries of a level it takes
+constexpr int NARROW_WORDS = 4096;           // colour bitmap words of a level it takes
+constexpr int NARROW_SUCC = 4096;            // same-round successor entries of a level it takes
 constexpr int NARROW_XPULL = 512;            // round size whose later-round colours it pulls in
 constexpr int NARROW_UNROLL = 4;             // edges per thread in flight in a narrow level
 
@@ -102,6 +104,8 @@ struct Ctrl {
   int stats_round;             // last round k_stats has computed
   // JP state
   unsigned long long bm_next;  // colour bitmap words handed out
+  unsigned long long huge_ctr; // rows of the round cut into chunks (low 32 bits) and their chunks (high)
+  unsigned long long xhuge;    // decrements done by the chunked rows
   int grid_op;                 // OP_* the grid kernel has to run next
   int grid_ran;                // the grid kernel has run grid_op
   int num_colors;
@@ -138,6 +142,9 @@ struct Params {
   unsigned long long* rec;     // (colour bitmap offset << 32) | |pred(v)|
   unsigned* B;                 // colour bitmaps (bm_words(|pred|) words per vertex)
   unsigned long long bm_cap;   // words of B
+  unsigned long long* HL;      // rows of the round cut into chunks: (first chunk << 32) | vertex
+  unsigned* HC;                // per such row: class counts [4] and placed counts [4]
+  unsigned huge_cap;
   unsigned* L0;                // first JP level of each round, in the round's ORD slot range
   unsigned* l0n;               // its size, per round
   unsigned* F[2];              // level lists, plain vertices (by level parity)
@@ -207,6 +214,8 @@ __global__ void k_init(Params P) {
   c->grid_ran = 0;
   c->num_colors = 0;
   c->bm_next = 0;
+  c->huge_ctr = 0;
+  c->xhuge = 0;
   JpState& j = c->js;
   j.round = 0;
   j.level = 0;
@@ -247,10 +256,13 @@ __global__ void k_stats(Params P, int l) {
     N = (unsigned long long)P.n;
     S = (unsigned long long)P.nnz;
   } else {
+    const unsigned long long X = red[0] + c->xhuge;
     N = c->Nnext;
-    S = c->SUnext - red[0];
-    c->cut_edges += red[0];
+    S = c->SUnext - X;
+    c->cut_edges += X;
   }
+  c->xhuge = 0;
+  c->huge_ctr = 0;
   if (l <= P.max_rounds + 1) {
     P.roundN[l] = (unsigned)N;
     P.l0n[l] = 0;
@@ -574,6 +586,20 @@ __device__ void update_small(const Params& P, int v, bool valid, int l, unsigned
 template <bool FUSED>
 __device__ void update_big(const Params& P, int v, int l, unsigned char code, unsigned& x) {
   const long long b = P.rp[v], e = P.rp[v + 1];
+  if (e - b > HUGE_DEG) {  // a hub: its chunks are spread over the grid by k_update_huge_*
+    if (lane_id() == 0) {
+      const unsigned long long nch = (unsigned long long)((e - b + HUGE_CHUNK - 1) / HUGE_CHUNK);
+      const unsigned long long old = atomicAdd(&P.ctrl->huge_ctr, (nch << 32) | 1ull);
+      const unsigned h = (unsigned)old;
+      if (h < P.huge_cap) {
+        P.HL[h] = (old & 0xffffffff00000000ull) | (unsigned)v;
+        for (int k = 0; k < 8; ++k) P.HC[8 * (size_t)h + k] = 0;
+      } else {
+        atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
+      }
+    }
+    return;
+  }
   const uint32_t hv = tiebreak(P.hkey, (uint32_t)v);
   const unsigned lane = lane_id();
   long long nl = 0, nps = 0, ns = 0;
@@ -641,6 +667,107 @@ __global__ __launch_bounds__(BS) void k_update(Params P, int l) {
     unsigned long long t = 0;
     for (int k = 0; k < WPB; ++k) t += xred[k];
     P.xpart[blockIdx.x] = t;
+  }
+}
+
+// ---- hubs: rows longer than HUGE_DEG, cut into HUGE_CHUNK-sized chunks
+
+// Hub entry of chunk k (entries are sorted by first chunk).
+__device__ __forceinline__ unsigned huge_entry(const Params& P, unsigned nh, unsigned k, unsigned* h) {
+  unsigned lo = 0, hi = nh;
+  while (hi - lo > 1) {
+    const unsigned mid = (lo + hi) >> 1;
+    if ((unsigned)(P.HL[mid] >> 32) <= k) lo = mid;
+    else hi = mid;
+  }
+  *h = lo;
+  return (unsigned)(P.HL[lo] >> 32);
+}
+
+// Count pass over the hubs' chunks: neighbour classes (summed per hub) and
+// the decrements of D.
+template <bool FUSED>
+__global__ __launch_bounds__(BS) void k_update_huge_count(Params P, int l) {
+  Ctrl* c = P.ctrl;
+  if (c->done) return;
+  const unsigned long long hc = c->huge_ctr;
+  const unsigned nh = (unsigned)hc < P.huge_cap ? (unsigned)hc : P.huge_cap, nch = (unsigned)(hc >> 32);
+  if (nh == 0) return;
+  const unsigned char code = round_code(l);
+  const unsigned lane = lane_id();
+  const long long gw = (long long)blockIdx.x * WPB + threadIdx.x / WAVE;
+  const long long gstride = (long long)gridDim.x * WPB;
+  unsigned x = 0;
+  for (long long k = gw; k < nch; k += gstride) {
+    unsigned h;
+    const unsigned first = huge_entry(P, nh, (unsigned)k, &h);
+    const int v = (int)(unsigned)P.HL[h];
+    const long long b = P.rp[v], e = P.rp[v + 1];
+    const long long c0 = b + ((long long)k - first) * HUGE_CHUNK;
+    const long long c1 = c0 + HUGE_CHUNK < e ? c0 + HUGE_CHUNK : e;
+    const uint32_t hv = tiebreak(P.hkey, (uint32_t)v);
+    unsigned cnt[4] = {0, 0, 0, 0};
+    for (long long base = c0; base < c1; base += WAVE) {
+      const long long j = base + lane;
+      const int cl = j < c1 ? visit3<FUSED>(P, P.col[j], l, code, hv, x, true) : NB_NONE;
+      cnt[NB_PRED] += __popcll(ballot(cl == NB_PRED));
+      cnt[NB_PRED_SAME] += __popcll(ballot(cl == NB_PRED_SAME));
+      cnt[NB_SUCC_SAME] += __popcll(ballot(cl == NB_SUCC_SAME));
+      cnt[NB_SUCC_EARLIER] += __popcll(ballot(cl == NB_SUCC_EARLIER));
+    }
+    if (FUSED && lane < 4) atomicAdd(&P.HC[8 * (size_t)h + lane], cnt[lane]);
+  }
+  const unsigned long long xs = wave_sum((unsigned long long)x);
+  if (lane == 0 && xs) atomicAdd(&c->xhuge, xs);
+}
+
+// Placing pass over the hubs' chunks: each chunk writes its entries at
+// offsets reserved in its hub's partitions; the chunk that starts a hub also
+// does the hub's JP bookkeeping.
+__global__ __launch_bounds__(BS) void k_update_huge_place(Params P, int l) {
+  Ctrl* c = P.ctrl;
+  if (c->done) return;
+  const unsigned long long hc = c->huge_ctr;
+  const unsigned nh = (unsigned)hc < P.huge_cap ? (unsigned)hc : P.huge_cap, nch = (unsigned)(hc >> 32);
+  if (nh == 0) return;
+  const unsigned char code = round_code(l);
+  const unsigned lane = lane_id();
+  const long long gw = (long long)blockIdx.x * WPB + threadIdx.x / WAVE;
+  const long long gstride = (long long)gridDim.x * WPB;
+  unsigned x = 0;
+  for (long long k = gw; k < nch; k += gstride) {
+    unsigned h;
+    const unsigned first = huge_entry(P, nh, (unsigned)k, &h);
+    const int v = (int)(unsigned)P.HL[h];
+    const long long b = P.rp[v], e = P.rp[v + 1];
+    const long long c0 = b + ((long long)k - first) * HUGE_CHUNK;
+    const long long c1 = c0 + HUGE_CHUNK < e ? c0 + HUGE_CHUNK : e;
+    const uint32_t hv = tiebreak(P.hkey, (uint32_t)v);
+    unsigned* C = P.HC + 8 * (size_t)h;
+    const long long nl = C[NB_PRED], nps = C[NB_PRED_SAME], ns = C[NB_SUCC_SAME];
+    const long long np = nl + nps;
+    const long long start[4] = {b, b + np, 0, b + nl};   // by class; earlier successors fill from the end
+    for (long long base = c0; base < c1; base += WAVE) {
+      const long long j = base + lane;
+      const int w = j < c1 ? P.col[j] : 0;
+      const int cl = j < c1 ? visit3<true>(P, w, l, code, hv, x, false) : NB_NONE;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint64_t m = ballot(cl == q);
+        if (!m) continue;
+        unsigned at = 0;
+        if (lane == 0) at = atomicAdd(&C[4 + q], (unsigned)__popcll(m));
+        at = readlane_u(at, 0);
+        if (cl == q) {
+          const long long o = at + lanes_below(m);
+          P.dag[q == NB_SUCC_EARLIER ? e - 1 - o : start[q] + o] = w;
+        }
+      }
+    }
+    if (k == first) {
+      jp_row(P, lane == 0, v, np, ns, nps);
+      l0_append(P, l, (long long)P.n - P.roundN[l], lane == 0 && nps == 0, v);
+    }
   }
 }
 
@@ -732,31 +859,38 @@ struct JpStage {
   unsigned long long* hctr;
   unsigned long long* psum;     // bitmap words of the level's vertices
   unsigned long long* ssum;     // their same-round successors
+  unsigned long long* acc;      // LDS [2]: this block's share of psum and ssum (null: sums not kept)
 };
 
 // Append u (ready) to the global lists of level l + 1.
 template <int S>
 __device__ __forceinline__ void jp_append(const Params& P, JpStage& st, int l, bool rdy, int u) {
-  long long ns = 0, wd = 0;
-  if (rdy) {
-    ns = P.nsr[u];
-    wd = bm_words(P.npred[u]);
-  }
-  if (ballot(rdy)) {
+  long long ns = 0;
+  if (rdy) ns = P.nsr[u];
+  if (st.acc && ballot(rdy)) {
     const unsigned long long es = wave_sum((unsigned long long)ns);
-    const unsigned long long ps = wave_sum((unsigned long long)wd);
+    const unsigned long long ps = wave_sum((unsigned long long)(rdy ? bm_words(P.npred[u]) : 0));
     if (lane_id() == 0) {
-      if (es) add64<S>(&st.ssum[(l + 1) % 3], es);
-      if (ps) add64<S>(&st.psum[(l + 1) % 3], ps);
+      atomicAdd(&st.acc[0], ps);
+      atomicAdd(&st.acc[1], es);
     }
   }
   const bool fan = rdy && ns > JP_SMALL;
-  if (fan) {
-    unsigned long long nch = (unsigned long long)((ns + JP_CHUNK - 1) / JP_CHUNK);
-    unsigned long long old = add64<S>(&st.hctr[(l + 1) % 3], (nch << 32) | 1ull);
-    unsigned pos = (unsigned)old;
-    if (pos < P.hub_cap) st64<S>(&P.H[(l + 1) & 1][pos], (old & 0xffffffff00000000ull) | (unsigned)u);
-    else atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
+  const uint64_t fm = ballot(fan);
+  if (fm) {
+    // one atomic per wavefront: (chunks << 32) | entries for all its fan-out vertices
+    const unsigned nch = fan ? (unsigned)((ns + JP_CHUNK - 1) / JP_CHUNK) : 0;
+    unsigned ctot;
+    const unsigned cpre = wave_excl_scan<unsigned>(nch, &ctot);
+    unsigned long long old = 0;
+    if (lane_id() == 0) old = add64<S>(&st.hctr[(l + 1) % 3], ((unsigned long long)ctot << 32) | __popcll(fm));
+    old = readlane_u64(old, 0);
+    if (fan) {
+      const unsigned pos = (unsigned)old + lanes_below(fm);
+      const unsigned first = (unsigned)(old >> 32) + cpre;
+      if (pos < P.hub_cap) st64<S>(&P.H[(l + 1) & 1][pos], ((unsigned long long)first << 32) | (unsigned)u);
+      else atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
+    }
   }
   const bool plain = rdy && !fan;
   uint64_t m = ballot(plain);
@@ -790,7 +924,14 @@ __device__ __forceinline__ void jp_stage_flush(const Params& P, JpStage& st, int
   __shared__ unsigned gbase;
   unsigned k = *st.cnt;
   if (k > (unsigned)FB_CAP) k = FB_CAP;
-  if (threadIdx.x == 0) gbase = k ? add32<S>(&st.fcnt[(l + 1) % 3], k) : 0;
+  if (threadIdx.x == 0) {
+    gbase = k ? add32<S>(&st.fcnt[(l + 1) % 3], k) : 0;
+    if (st.acc) {
+      if (st.acc[0]) add64<S>(&st.psum[(l + 1) % 3], st.acc[0]);
+      if (st.acc[1]) add64<S>(&st.ssum[(l + 1) % 3], st.acc[1]);
+      st.acc[0] = st.acc[1] = 0;
+    }
+  }
   __syncthreads();
   for (unsigned i = threadIdx.x; i < k; i += blockDim.x)
     sti<S>((int*)&P.F[(l + 1) & 1][gbase + i], (int)st.buf[i]);
@@ -1134,41 +1275,51 @@ struct NarrowLds {
   int col[NARROW_MAX];
   unsigned wsum[2][NARROW_BS / WAVE];
   unsigned cnt[2];                       // list sizes
-  unsigned long long wds[2], sus[2];     // their bitmap words and successors
   WaveLds wl[NARROW_BS / WAVE];
 };
 
-// Append u (bitmap urec) to the next LDS list (slot `nx`), or -- past its
-// capacity -- to the global lists of level l + 1.  Loads u's row metadata
-// for the next level.
-__device__ __forceinline__ void narrow_append(const Params& P, NarrowLds& Z, JpStage& st, int nx, int l, bool rdy,
-                                              int u, unsigned long long urec) {
-  long long pb = 0;
-  int ns = 0;
-  if (rdy) {
-    pb = P.rp[u];
-    ns = P.nsr[u];
+// Append the ready ones among a thread's NARROW_UNROLL items (vertex u[q],
+// bitmap urec[q]) to the next LDS list (slot `nx`), with their row metadata;
+// past its capacity, to the global lists of level l + 1.  One LDS atomic per
+// wavefront.
+__device__ __forceinline__ void narrow_append(const Params& P, NarrowLds& Z, JpStage& st, int nx, int l,
+                                              const bool* rdy, const int* u, const unsigned long long* urec) {
+  uint64_t m[NARROW_UNROLL];
+  unsigned tot = 0;
+#pragma unroll
+  for (int q = 0; q < NARROW_UNROLL; ++q) {
+    m[q] = ballot(rdy[q]);
+    tot += (unsigned)__popcll(m[q]);
   }
-  const uint64_t m = ballot(rdy);
-  if (!m) return;
-  const unsigned long long ws = wave_sum((unsigned long long)(rdy ? bm_words((int)(unsigned)urec) : 0));
-  const unsigned long long ss = wave_sum((unsigned long long)ns);
+  if (!tot) return;
+  long long pb[NARROW_UNROLL];
+  int ns[NARROW_UNROLL];
+#pragma unroll
+  for (int q = 0; q < NARROW_UNROLL; ++q) {
+    pb[q] = rdy[q] ? P.rp[u[q]] : 0;
+    ns[q] = rdy[q] ? P.nsr[u[q]] : 0;
+  }
   unsigned base = 0;
-  if (lane_id() == 0) {
-    base = atomicAdd(&Z.cnt[nx], (unsigned)__popcll(m));
-    atomicAdd(&Z.wds[nx], ws);
-    atomicAdd(&Z.sus[nx], ss);
-  }
+  if (lane_id() == 0) base = atomicAdd(&Z.cnt[nx], tot);
   base = readlane_u(base, 0);
-  const unsigned pos = base + lanes_below(m);
-  const bool lds = rdy && pos < (unsigned)NARROW_MAX;
-  if (lds) {
-    Z.v[nx][pos] = u;
-    Z.pb[nx][pos] = pb;
-    Z.rec[nx][pos] = urec;
-    Z.ns[nx][pos] = ns;
+  unsigned run = base;
+  bool over[NARROW_UNROLL];
+#pragma unroll
+  for (int q = 0; q < NARROW_UNROLL; ++q) {
+    const unsigned pos = run + lanes_below(m[q]);
+    run += (unsigned)__popcll(m[q]);
+    over[q] = rdy[q] && pos >= (unsigned)NARROW_MAX;
+    if (rdy[q] && !over[q]) {
+      Z.v[nx][pos] = u[q];
+      Z.pb[nx][pos] = pb[q];
+      Z.rec[nx][pos] = urec[q];
+      Z.ns[nx][pos] = ns[q];
+    }
   }
-  if (base + __popcll(m) > (unsigned)NARROW_MAX) jp_append<SC_WG>(P, st, l, rdy && !lds, u);
+  if (base + tot > (unsigned)NARROW_MAX) {
+#pragma unroll
+    for (int q = 0; q < NARROW_UNROLL; ++q) jp_append<SC_WG>(P, st, l, over[q], u[q]);
+  }
 }
 
 // Block-wide: the LDS entries of list `cur` (level l) to the global lists of
@@ -1272,8 +1423,9 @@ __device__ __forceinline__ unsigned owner(const unsigned* off, unsigned nv, unsi
 
 // One narrow level (list `cur`, level l): read the bitmaps and colour every
 // vertex; then push the colours to the same-round successors and append the
-// ready ones to list `nx`.
-__device__ void narrow_level(const Params& P, NarrowLds& Z, JpStage& st, int cur, int nx, int l) {
+// ready ones to list `nx`.  Returns false, having changed nothing outside
+// LDS, if the level's work exceeds what one block takes.
+__device__ bool narrow_level(const Params& P, NarrowLds& Z, JpStage& st, int cur, int nx, int l) {
   const unsigned nv = Z.cnt[cur];
   const unsigned t = threadIdx.x;
   {
@@ -1281,6 +1433,7 @@ __device__ void narrow_level(const Params& P, NarrowLds& Z, JpStage& st, int cur
     narrow_scan2(Z, ok ? bm_words((int)(unsigned)Z.rec[cur][t]) : 0, ok ? (unsigned)Z.ns[cur][t] : 0, nv);
   }
   const unsigned wtot = Z.woff[nv], stot = Z.soff[nv];
+  if (wtot > (unsigned)NARROW_WORDS || stot > (unsigned)NARROW_SUCC) return false;
   // bitmap words -> first clear bit per vertex; successors of the first
   // pass fetched meanwhile
   int su[NARROW_UNROLL];
@@ -1312,7 +1465,8 @@ __device__ void narrow_level(const Params& P, NarrowLds& Z, JpStage& st, int cur
     for (int q = 0; q < NARROW_UNROLL; ++q)
       if (~wd[q]) {
         const unsigned e = e0 + q * NARROW_BS + t;
-        atomicMin(&Z.ffree[k[q]], (int)((e - Z.woff[k[q]]) * 32) + __ffs((int)~wd[q]) - 1);
+        const int f = (int)((e - Z.woff[k[q]]) * 32) + __ffs((int)~wd[q]) - 1;
+        if (f < Z.ffree[k[q]]) atomicMin(&Z.ffree[k[q]], f);
       }
   }
 #pragma unroll
@@ -1351,11 +1505,11 @@ __device__ void narrow_level(const Params& P, NarrowLds& Z, JpStage& st, int cur
     bool rdy[NARROW_UNROLL];
 #pragma unroll
     for (int q = 0; q < NARROW_UNROLL; ++q) rdy[q] = su[q] >= 0 && jp_push<SC_WG>(P, su[q], sr[q], Z.col[sk[q]]);
-#pragma unroll
-    for (int q = 0; q < NARROW_UNROLL; ++q) narrow_append(P, Z, st, nx, l, rdy[q], su[q], sr[q]);
+    narrow_append(P, Z, st, nx, l, rdy, su, sr);
   }
   order_point();
   __syncthreads();
+  return true;
 }
 
 // One block.  Finishes the state change of what the grid kernel has just
@@ -1380,10 +1534,11 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_narrow(Params P, int max_steps
     }
   }
   __syncthreads();
-  JpStage st{nullptr, nullptr, S.fcnt, S.hctr, S.psum, S.ssum};
+  JpStage st{nullptr, nullptr, S.fcnt, S.hctr, S.psum, S.ssum, nullptr};
   WaveLds& W = Z.wl[threadIdx.x / WAVE];
   int cur = 0;
   int handed = OP_NONE;
+  bool in_global = false;   // the LDS level is also in the global lists
   for (int step = 0; step < max_steps; ++step) {
     if (S.done) break;
     const int r = S.round;
@@ -1409,6 +1564,7 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_narrow(Params P, int max_steps
           break;
         }
         narrow_load(P, Z, cur, P.L0 + seg_begin(P, r), n0);
+        in_global = false;
         if (threadIdx.x == 0) {
           Z.cnt[cur] = n0;
           S.split = 0;
@@ -1428,52 +1584,18 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_narrow(Params P, int max_steps
         }
         narrow_load(P, Z, cur, P.F[l & 1], nf);
         narrow_load_fan(P, Z, cur, P.H[l & 1], nh, nf);
+        in_global = true;
         if (threadIdx.x == 0) Z.cnt[cur] = nf + nh;
-      }
-      __syncthreads();
-      // sums of the loaded level (level 0 of a round is not counted yet)
-      unsigned long long ws = 0, ss = 0;
-      for (unsigned i = threadIdx.x; i < Z.cnt[cur]; i += NARROW_BS) {
-        ws += (unsigned long long)bm_words((int)(unsigned)Z.rec[cur][i]);
-        ss += (unsigned long long)Z.ns[cur][i];
-      }
-      ws = wave_sum(ws);
-      ss = wave_sum(ss);
-      if (threadIdx.x == 0) {
-        Z.wds[cur] = 0;
-        Z.sus[cur] = 0;
-      }
-      __syncthreads();
-      if (lane_id() == 0) {
-        atomicAdd(&Z.wds[cur], ws);
-        atomicAdd(&Z.sus[cur], ss);
-      }
-      __syncthreads();
-      if (!jp_fits_narrow(Z.cnt[cur], Z.wds[cur], Z.sus[cur])) {
-        // too much work for one block: to the global lists, for the grid
-        if (threadIdx.x == 0) {
-          jp_clear_level(S, l % 3);
-          S.psum[l % 3] = Z.wds[cur];
-          S.ssum[l % 3] = Z.sus[cur];
-        }
-        __syncthreads();
-        narrow_flush(P, Z, st, cur, l);
-        order_point();
-        handed = OP_LEVEL;
-        break;
       }
       if (threadIdx.x == 0) have = 1;
       __syncthreads();
     }
     // process level l from LDS list `cur`
     const int nx = cur ^ 1;
-    if (threadIdx.x == 0) {
-      Z.cnt[nx] = 0;
-      Z.wds[nx] = 0;
-      Z.sus[nx] = 0;
-    }
+    if (threadIdx.x == 0) Z.cnt[nx] = 0;
     __syncthreads();
     if (Z.cnt[cur] == 0) {  // nothing ready: the round is finished
+      __syncthreads();
       if (threadIdx.x == 0) {
         jp_begin_round(S, r - 1);
         have = 0;
@@ -1481,17 +1603,26 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_narrow(Params P, int max_steps
       __syncthreads();
       continue;
     }
-    narrow_level(P, Z, st, cur, nx, l);
-    const unsigned nn = Z.cnt[nx];
-    const bool fits = jp_fits_narrow(nn, Z.wds[nx], Z.sus[nx]);
-    if (nn > 0 && !fits) {
-      // the next level goes to the grid: its overflow entries are already in
-      // the global lists; add the LDS ones
-      if (threadIdx.x == 0) {
-        S.psum[(l + 1) % 3] = Z.wds[nx];
-        S.ssum[(l + 1) % 3] = Z.sus[nx];
+    if (!narrow_level(P, Z, st, cur, nx, l)) {
+      // too much work for one block: the level goes to the grid
+      if (!in_global) {
+        narrow_flush(P, Z, st, cur, l);
+        order_point();
       }
       __syncthreads();
+      if (threadIdx.x == 0) {
+        S.psum[l % 3] = Z.woff[Z.cnt[cur]];
+        S.ssum[l % 3] = Z.soff[Z.cnt[cur]];
+        have = 0;
+      }
+      handed = OP_LEVEL;
+      break;
+    }
+    const unsigned nn = Z.cnt[nx];
+    const bool wide = nn > (unsigned)NARROW_MAX;
+    if (wide) {
+      // the next level goes to the grid: its overflow entries are already in
+      // the global lists; add the LDS ones
       narrow_flush(P, Z, st, nx, l + 1);
       order_point();
     }
@@ -1501,13 +1632,14 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_narrow(Params P, int max_steps
       if (nn == 0) {
         jp_begin_round(S, r - 1);
         have = 0;
-      } else if (!fits) {
+      } else if (wide) {
         have = 0;
       }
     }
     __syncthreads();
     cur = nx;
-    if (nn > 0 && !fits) {
+    in_global = false;
+    if (wide) {
       handed = OP_LEVEL;
       break;
     }
@@ -1529,13 +1661,26 @@ __global__ __launch_bounds__(BS) void k_jp_grid(Params P) {
   Ctrl* c = P.ctrl;
   const int op = c->grid_op;
   if (c->js.done || op == OP_NONE || c->grid_ran) return;
+  {
+    // blocks past the step's work leave at once (block 0 stays: it reports)
+    const int r = c->js.round, l = c->js.level;
+    long long items;
+    if (op == OP_XPULL) items = (seg_size(P, r) + WAVE - 1) / WAVE;
+    else if (op == OP_SPLIT) items = ((long long)P.l0n[r] + WAVE - 1) / WAVE;
+    else items = ((long long)c->js.fcnt[l % 3] + WAVE - 1) / WAVE + (long long)(c->js.hctr[l % 3] >> 32);
+    if (blockIdx.x > 0 && (long long)blockIdx.x * WPB >= items) return;
+  }
   __shared__ unsigned fbuf[FB_CAP];
   __shared__ unsigned fcnt;
   __shared__ unsigned long long flds[FAN_LDS];
   __shared__ WaveLds wl[WPB];
-  if (threadIdx.x == 0) fcnt = 0;
+  __shared__ unsigned long long acc[2];
+  if (threadIdx.x == 0) {
+    fcnt = 0;
+    acc[0] = acc[1] = 0;
+  }
   __syncthreads();
-  JpStage st{fbuf, &fcnt, c->js.fcnt, c->js.hctr, c->js.psum, c->js.ssum};
+  JpStage st{fbuf, &fcnt, c->js.fcnt, c->js.hctr, c->js.psum, c->js.ssum, acc};
   const int r = c->js.round;
   const long long gw = (long long)blockIdx.x * WPB + threadIdx.x / WAVE;
   const long long gstride = (long long)gridDim.x * WPB;
@@ -1653,7 +1798,7 @@ namespace adg {
 // ---- optional per-kernel timing with HIP events on the launch stream
 namespace {
 const char* kclass_names[KC_NUM] = {"init", "stats", "count", "scan", "scatter", "update", "part1",
-                                    "jp_prep", "jp", "finish", "batched", "jp_narrow"};
+                                    "jp_prep", "jp", "finish", "batched", "jp_narrow", "update_huge"};
 struct ProfRec {
   int cls;
   hipEvent_t a, b;
@@ -1703,10 +1848,11 @@ namespace {
 
 struct Layout {
   size_t ctrl, bcount, boff, bsum, xpart, D, status, UL0, UL1, ORD, roundN, round, dag, npred, nsr, cnt, rec, B,
-      bm_cap, L0, l0n, F0, F1, H0, H1, hub_cap, total;
+      bm_cap, L0, l0n, F0, F1, H0, H1, hub_cap, HL, HC, huge_cap, total;
 };
 
 constexpr int UPD_BLOCKS = 2048;
+constexpr int HUGE_BLOCKS = 1024;
 
 Layout make_layout(int64_t n, int64_t nnz) {
   Layout L{};
@@ -1746,6 +1892,10 @@ Layout make_layout(int64_t n, int64_t nnz) {
   L.hub_cap = (size_t)nnz / (2 * JP_SMALL) + 64;
   L.H0 = take(8 * L.hub_cap);
   L.H1 = take(8 * L.hub_cap);
+  // rows longer than HUGE_DEG in one round: at most nnz / HUGE_DEG
+  L.huge_cap = (size_t)nnz / HUGE_DEG + 64;
+  L.HL = take(8 * L.huge_cap);
+  L.HC = take(4 * 8 * L.huge_cap);
   L.total = off;
   return L;
 }
@@ -1808,6 +1958,9 @@ Params make_params(const adg_csr_t* g, void* ws, uint64_t p, uint64_t q, uint64_
   P.H[0] = (unsigned long long*)(base + L.H0);
   P.H[1] = (unsigned long long*)(base + L.H1);
   P.hub_cap = (unsigned)L.hub_cap;
+  P.HL = (unsigned long long*)(base + L.HL);
+  P.HC = (unsigned*)(base + L.HC);
+  P.huge_cap = (unsigned)L.huge_cap;
   P.color = color;
   // Round-count bound from the ADG depth lemma: |U| shrinks by a factor
   // 1/(1+eps) per round, so L <= ceil(log n / log(1+eps)) + 1; +1 margin.
@@ -1888,6 +2041,15 @@ int run_adg(Params& P, hipStream_t s, bool fused, int* num_rounds_host) {
           hipLaunchKernelGGL(k_update<true>, dim3(P.upd_blocks), dim3(BS), 0, s, P, l);
         else
           hipLaunchKernelGGL(k_update<false>, dim3(P.upd_blocks), dim3(BS), 0, s, P, l);
+      }
+      {
+        TIMED(KC_UPDATE_HUGE, s);
+        if (fused) {
+          hipLaunchKernelGGL(k_update_huge_count<true>, dim3(HUGE_BLOCKS), dim3(BS), 0, s, P, l);
+          hipLaunchKernelGGL(k_update_huge_place, dim3(HUGE_BLOCKS), dim3(BS), 0, s, P, l);
+        } else {
+          hipLaunchKernelGGL(k_update_huge_count<false>, dim3(HUGE_BLOCKS), dim3(BS), 0, s, P, l);
+        }
       }
     }
     // one more stats call ends the loop on the device when U is empty

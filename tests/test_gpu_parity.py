@@ -163,3 +163,27 @@ def test_validate_csr(dev):
     bad = col.copy()
     bad[0] = 0  # vertex 0 lists itself or breaks symmetry
     assert not dev.validate_csr(dev.Graph(rp, bad))
+
+
+def test_hub_rows_longer_than_the_chunk_threshold(dev):
+    """Rows above 16384 entries are split into chunks across wavefronts in
+    UPDATE: 20 hubs forming a clique (same round, so same-round predecessors
+    and successors among them), each with 17000 private leaves and a few
+    random extra edges."""
+    rng = np.random.default_rng(11)
+    hubs, leaves = 20, 17_000
+    n = hubs * (leaves + 1)
+    edges = [(a, b) for a in range(hubs) for b in range(a + 1, hubs)]
+    src = np.repeat(np.arange(hubs), leaves)
+    dst = hubs + np.arange(hubs * leaves)
+    extra = rng.integers(hubs, n, size=(5000, 2))
+    es = np.concatenate([np.array(edges).T, np.stack([src, dst]), extra.T], axis=1)
+    rp, col = graphgen.from_edges(n, es[0], es[1])
+    assert np.diff(rp).max() > 16384
+    for p, q in [(1, 10), (0, 1), (1, 2)]:
+        _compare(dev, rp, col, p, q, 7, "hubs eps %d/%d" % (p, q))
+    import torch
+    rho, L, _ = oracle.adg(rp, col, 1, 10)
+    rnd, nr = dev.adg_order(dev.Graph(rp, col), 1, 10)
+    torch.cuda.synchronize()
+    assert int(nr.item()) == L and np.array_equal(rnd.cpu().numpy(), rho)
