@@ -41,7 +41,8 @@ WORKLOADS = {
     "rmat26_e05": dict(kind="rmat", scale=26, edge_factor=16, eps=(1, 2), seed=3, cpu_sample_scale=24),
     "er": dict(kind="er", n=10_000, mean_deg=10.0, eps=(1, 100), seed=1),
     "batched": dict(kind="batched", num_graphs=4096, eps=(1, 10), seed=4),
-    "serving": dict(kind="serving", requests=240, eps=(1, 10), seed=5, load=0.7),
+    "serving": dict(kind="serving", requests=240, eps=(1, 10), seed=5, load=0.7, scale_down=False),
+    "serving_small": dict(kind="serving", requests=48, eps=(1, 10), seed=5, load=0.7, scale_down=True),
 }
 
 # kernel sources each timed kernel class is built from (for matching
@@ -328,11 +329,18 @@ def run_serving(args, w):
     import graphgen
     import paper_2008_11321_amd.serving as sv
 
+    if not w["scale_down"]:
+        # The full-size stream (R-MAT scale 20-23 and Chung-Lu up to 1e6
+        # vertices among the requests) ended in a GPU memory fault once and
+        # its cause has not been found; it stays disabled until it is.
+        print("the full-size serving stream is disabled (see the design notes); use --workload serving_small",
+              file=sys.stderr)
+        sys.exit(3)
     t0 = time.time()
     specs = graphgen.serving_specs(w["requests"], seed=w["seed"])
     graphs = []
     for k, sp in enumerate(specs):
-        graphs.append(graphgen.serving_graph(sp))
+        graphs.append(graphgen.serving_graph(sp, scale_down=w["scale_down"]))
         if k % 40 == 39:
             log("generated %d/%d requests" % (k + 1, len(specs)))
     n_tot = sum(rp.size - 1 for rp, _ in graphs)
@@ -343,8 +351,8 @@ def run_serving(args, w):
         (len(graphs), kinds, n_tot, nnz_tot, time.time() - t0))
     p, q = w["eps"]
     seed = w["seed"]
-    arena = 24 << 30
-    opts = dict(eps=(p, q), seed=seed, workers=4, small_nnz=1 << 20, max_group=64, max_bypass=16)
+    arena = 4 << 30
+    opts = dict(eps=(p, q), seed=seed, workers=4, small_nnz=1 << 18, max_group=16, max_bypass=16)
     with sv.Server(arena, **opts) as srv:
         sv.replay(srv, graphs[:min(16, len(graphs))])   # warm-up
         sat = sv.latency_summary(sv.replay(srv, graphs))
@@ -358,7 +366,7 @@ def run_serving(args, w):
         log("poisson at %.1f req/s: p50 %.2f ms p99 %.2f ms, %.3g edges/s" %
             (qps, served["p50_ms"], served["p99_ms"], served["edges_per_s"]))
     assert all(r["status"] == 0 for r in res)
-    with sv.Server(arena, eps=(p, q), seed=seed, workers=1, small_nnz=-1, max_group=1, max_bypass=0) as srv:
+    with sv.Server(arena, eps=(p, q), seed=seed, workers=1, small_nnz=0, max_group=1, max_bypass=0) as srv:
         sv.replay(srv, graphs[:min(16, len(graphs))])
         plain_res = sv.replay(srv, graphs)
     plain = sv.latency_summary(plain_res)
@@ -385,7 +393,7 @@ def run_serving(args, w):
         cdt = time.perf_counter() - t0
         cpu = {"value": me / cdt, "unit": "edges/s", "cores": 1, "kind": "oracle",
                "sample": "the first %d requests in arrival order, one serial oracle run each, %.2f s" % (k, cdt)}
-    cfg = {"workload": "serving", "requests": len(graphs), "mix": kinds, "n": n_tot, "nnz": nnz_tot, "m": m,
+    cfg = {"workload": args.workload, "requests": len(graphs), "scaled_down": w["scale_down"], "mix": kinds, "n": n_tot, "nnz": nnz_tot, "m": m,
            "eps": "%d/%d" % (p, q), "seed": seed, "offered_qps": qps, "load_vs_saturation": w["load"],
            "server": dict(opts, arena_bytes=arena, eps="%d/%d" % (p, q))}
     extra = {"latency_ms": {"p50": served["p50_ms"], "p99": served["p99_ms"], "mean": served["mean_ms"],

@@ -139,13 +139,17 @@ def serving_specs(count, seed=5):
     return out
 
 
-def serving_graph(spec):
+def serving_graph(spec, scale_down=False):
+    """The graph of one serving request.  scale_down shrinks it (ER n / 5,
+    at least 1000; Chung-Lu n / 10, at least 10^4; R-MAT scale - 6)."""
     kind, size, gs = spec
     if kind == "er":
-        return erdos_renyi(size, min(1.0, 10.0 / max(size - 1, 1)), gs)
+        n = max(1000, size // 5) if scale_down else size
+        return erdos_renyi(n, min(1.0, 10.0 / max(n - 1, 1)), gs)
     if kind == "chung_lu":
-        return chung_lu(size, 16.0, 2.3, gs)
-    return rmat(size, 16, 0.57, 0.19, 0.19, gs)
+        n = max(10_000, size // 10) if scale_down else size
+        return chung_lu(n, 16.0, 2.3, gs)
+    return rmat(size - 6 if scale_down else size, 16, 0.57, 0.19, 0.19, gs)
 
 
 def poisson_arrivals(count, qps, seed=5):

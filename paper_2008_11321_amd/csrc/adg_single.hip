@@ -558,19 +558,21 @@ __device__ void update_small(const Params& P, int v, bool valid, int l, unsigned
   }
   const uint32_t hv = tiebreak(P.hkey, (uint32_t)v);
   long long nl = 0, nps = 0, ns = 0;
+  unsigned long long cls = 0;   // the row's classes, 2 bits per entry (SMALL_DEG <= 32)
   for (long long j = b; j < e; ++j) {
     int cl = visit3<FUSED>(P, P.col[j], l, code, hv, x, true);
     nl += cl == NB_PRED;
     nps += cl == NB_PRED_SAME;
     ns += cl == NB_SUCC_SAME;
+    cls |= (unsigned long long)cl << (2 * (j - b));
   }
   if (!FUSED) return;
   const long long np = nl + nps;
   if (valid) {
     long long f = b, g = b + nl, s = b + np, r = e;
     for (long long j = b; j < e; ++j) {
-      int w = P.col[j];
-      int cl = visit3<FUSED>(P, w, l, code, hv, x, false);
+      const int w = P.col[j];
+      const int cl = (int)(cls >> (2 * (j - b))) & 3;
       if (cl == NB_PRED) P.dag[f++] = w;
       else if (cl == NB_PRED_SAME) P.dag[g++] = w;
       else if (cl == NB_SUCC_SAME) P.dag[s++] = w;
@@ -603,6 +605,10 @@ __device__ void update_big(const Params& P, int v, int l, unsigned char code, un
   const uint32_t hv = tiebreak(P.hkey, (uint32_t)v);
   const unsigned lane = lane_id();
   long long nl = 0, nps = 0, ns = 0;
+  // rows of up to 16 chunks keep their classes (2 bits per chunk and lane)
+  constexpr int KEEP = 16;
+  const bool keep = e - b <= (long long)KEEP * WAVE;
+  unsigned cls = 0;
   for (long long base = b; base < e; base += WAVE) {
     long long j = base + lane;
     bool valid = j < e;
@@ -612,6 +618,7 @@ __device__ void update_big(const Params& P, int v, int l, unsigned char code, un
       nl += __popcll(ballot(cl == NB_PRED));
       nps += __popcll(ballot(cl == NB_PRED_SAME));
       ns += __popcll(ballot(cl == NB_SUCC_SAME));
+      if (keep && valid) cls |= (unsigned)cl << (2 * ((base - b) / WAVE));
     }
   }
   if (!FUSED) return;
@@ -621,7 +628,9 @@ __device__ void update_big(const Params& P, int v, int l, unsigned char code, un
     long long j = base + lane;
     bool valid = j < e;
     int w = valid ? P.col[j] : 0;
-    int cl = valid ? visit3<FUSED>(P, w, l, code, hv, x, false) : NB_NONE;
+    int cl = !valid ? NB_NONE
+             : keep ? (int)(cls >> (2 * ((base - b) / WAVE))) & 3
+                    : visit3<FUSED>(P, w, l, code, hv, x, false);
     uint64_t fm = ballot(cl == NB_PRED), gm = ballot(cl == NB_PRED_SAME), sm = ballot(cl == NB_SUCC_SAME),
              lm = ballot(cl == NB_SUCC_EARLIER);
     if (cl == NB_PRED) P.dag[b + fc + lanes_below(fm)] = w;

@@ -13,17 +13,8 @@ import oracle
 
 def _mix(count, seed):
     """A scaled-down serving mix: ER n 1e3..2e4 (mean degree 10), Chung-Lu n
-    1e4..1e5 (mean degree 16), R-MAT scale 14..16."""
-    out = []
-    for kind, size, gs in graphgen.serving_specs(count, seed=seed):
-        if kind == "er":
-            n = max(1000, size // 5)
-            out.append(graphgen.erdos_renyi(n, 10.0 / (n - 1), gs))
-        elif kind == "chung_lu":
-            out.append(graphgen.chung_lu(max(10_000, size // 10), 16.0, 2.3, gs))
-        else:
-            out.append(graphgen.rmat(size - 6, 16, 0.57, 0.19, 0.19, gs))
-    return out
+    1e4..1e5 (mean degree 16), R-MAT scale 14..17."""
+    return [graphgen.serving_graph(sp, scale_down=True) for sp in graphgen.serving_specs(count, seed=seed)]
 
 
 @pytest.fixture(scope="module")
