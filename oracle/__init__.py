@@ -35,6 +35,10 @@ def _load():
         lib.or_color_graph.argtypes = [i64, vp, vp, i64, i64, u64, vp, vp, vp, vp]
         lib.or_pred_counts.restype = i64
         lib.or_pred_counts.argtypes = [i64, vp, vp, vp, u64, vp]
+        lib.or_adg_ex.restype = i64
+        lib.or_adg_ex.argtypes = [i64, vp, vp, i64, i64, u64, ctypes.c_uint32, vp, vp, vp]
+        lib.or_jp_total.restype = i64
+        lib.or_jp_total.argtypes = [i64, vp, vp, vp, vp]
         lib.or_degeneracy.restype = i64
         lib.or_degeneracy.argtypes = [i64, vp, vp]
         lib.or_tiebreak.restype = u32
@@ -121,3 +125,42 @@ def fmix32(x):
 
 def splitmix64_first(s):
     return int(_load().or_splitmix64_first(int(s) & (2**64 - 1)))
+
+
+
+SORTED = 1   # ADG-O: R sorted by D at selection, ties by rho_R
+MEDIAN = 2   # ADG-M: lower median of D times (1+eps), R capped at ceil(|U|/2)
+
+
+def adg_ex(row_ptr, col, eps_num, eps_den, seed, flags):
+    """ADG with variant flags (SORTED, MEDIAN; or_adg_ex).  Returns
+    (round int32[n], pos int64[n], L, stats); pos is the total order JP
+    colours by (larger = first)."""
+    rp, c, n = _csr(row_ptr, col)
+    rnd = np.zeros(max(n, 1), dtype=np.int32)
+    pos = np.zeros(max(n, 1), dtype=np.int64)
+    st = np.zeros(4, dtype=np.int64)
+    L = _load().or_adg_ex(n, rp.ctypes.data, c.ctypes.data, int(eps_num), int(eps_den),
+                          int(seed) & (2**64 - 1), int(flags), rnd.ctypes.data, pos.ctypes.data, st.ctypes.data)
+    if L < 0:
+        raise ValueError("or_adg_ex failed (%d)" % L)
+    return rnd[:n], pos[:n], int(L), {"sum_active": int(st[0]), "cut_edges": int(st[1])}
+
+
+def jp_total(row_ptr, col, pos):
+    """JP under a total order pos (larger = coloured first) = greedy in that order."""
+    rp, c, n = _csr(row_ptr, col)
+    p = np.ascontiguousarray(pos, dtype=np.int64)
+    color = np.zeros(max(n, 1), dtype=np.int32)
+    k = _load().or_jp_total(n, rp.ctypes.data, c.ctypes.data, p.ctypes.data, color.ctypes.data)
+    if k < 0:
+        raise ValueError("or_jp_total failed")
+    return color[:n], int(k)
+
+
+def color_graph_ex(row_ptr, col, eps_num, eps_den, seed, flags):
+    """JP-ADG with variant flags: adg_ex, then JP under its total order.
+    Returns (color, num_colors, round, L, pos, stats)."""
+    rnd, pos, L, st = adg_ex(row_ptr, col, eps_num, eps_den, seed, flags)
+    color, k = jp_total(row_ptr, col, pos)
+    return color, k, rnd, L, pos, st

@@ -171,6 +171,184 @@ int64_t or_adg(int64_t n, const int64_t* row_ptr, const int32_t* col, int64_t p,
   return l - 1;
 }
 
+/* ---- ADG variants: ADG-O (sorted R) and ADG-M (median threshold) --------- */
+
+#define OR_SORTED 1u  /* ADG-O: rho_ADG(r_i) = l + i over R sorted by D (listing ADG-O) */
+#define OR_MEDIAN 2u  /* ADG-M: median instead of average (section on the degree median) */
+
+typedef struct {
+  int64_t d;   /* D[u] at selection */
+  uint32_t h;  /* rho_R(u) */
+  int64_t u;
+} okey_t;
+
+static int cmp_okey_asc(const void* a, const void* b) {
+  const okey_t* x = (const okey_t*)a;
+  const okey_t* y = (const okey_t*)b;
+  if (x->d != y->d) return x->d < y->d ? -1 : 1;
+  if (x->h != y->h) return x->h < y->h ? -1 : 1;
+  return x->u < y->u ? -1 : (x->u > y->u);
+}
+
+static int cmp_i64(const void* a, const void* b) {
+  int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+  return x < y ? -1 : (x > y);
+}
+
+/* ADG with optional variant flags, in the paper's steps:
+ *  - every round takes N = |U| and D over U (D[u] = deg_U(u), kept by the
+ *    decrements of UPDATE);
+ *  - default (Algorithm 1): R = {u : D[u] <= (1+p/q) * sum(D) / N};
+ *  - OR_MEDIAN (ADG-M): delta_m = the lower median of D over U (the value at
+ *    rank ceil(N/2) in increasing order; a reading, the paper does not say
+ *    which median), R = {u : D[u] <= (1+p/q) delta_m}, and when R holds more
+ *    than ceil(N/2) vertices (half of U, +1 if N is odd) it keeps the
+ *    ceil(N/2) lowest by D, ties by increasing rho_R (a reading: the paper
+ *    removes the lowest-degree vertices and leaves ties open);
+ *  - OR_SORTED (ADG-O): R is sorted by increasing D, ties by increasing rho_R
+ *    (a reading: the paper leaves ties to its sort), and rho_ADG(r_i) = l + i
+ *    with l the number of vertices removed before; UPDATE decrements D[w] for
+ *    neighbours w with a larger rho_ADG (w still in U has rho_ADG = n).
+ *    Without OR_SORTED the order inside a round is JP's tie-break: pos ranks
+ *    R by increasing rho_R.
+ * Writes the round (1..L) of each vertex to round_out and the total order
+ * JP colours by to pos_out: a permutation of 0..n-1, larger = coloured
+ * first (with OR_SORTED it is rho_ADG-O itself).  Returns L, or -1 (bad
+ * arguments / out of memory), -3 (an empty R). */
+int64_t or_adg_ex(int64_t n, const int64_t* row_ptr, const int32_t* col, int64_t p, int64_t q, uint64_t seed,
+                  uint32_t flags, int32_t* round_out, int64_t* pos_out, int64_t* stats_out) {
+  if (n < 0 || p < 0 || q < 1 || (flags & ~(OR_SORTED | OR_MEDIAN))) return -1;
+  size_t nn = (size_t)(n ? n : 1);
+  int64_t* D = (int64_t*)malloc(sizeof(int64_t) * nn);
+  int64_t* rho = (int64_t*)malloc(sizeof(int64_t) * nn);
+  int64_t* U = (int64_t*)malloc(sizeof(int64_t) * nn);
+  int64_t* Dsorted = (int64_t*)malloc(sizeof(int64_t) * nn);
+  okey_t* R = (okey_t*)malloc(sizeof(okey_t) * nn);
+  if (!D || !rho || !U || !Dsorted || !R) {
+    free(D); free(rho); free(U); free(Dsorted); free(R);
+    return -1;
+  }
+  int64_t sum_U = 0, cut = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    D[v] = row_ptr[v + 1] - row_ptr[v];
+    rho[v] = n; /* not removed yet */
+    U[v] = v;
+  }
+  int64_t sizeU = n, removed = 0, l = 1;
+  int64_t rc = 0;
+  while (sizeU > 0) {
+    sum_U += sizeU;
+    /* the threshold and R */
+    int64_t sizeR = 0, k = 0;
+    u128 lhs_scale, rhs;
+    if (flags & OR_MEDIAN) {
+      for (int64_t i = 0; i < sizeU; ++i) Dsorted[i] = D[U[i]];
+      qsort(Dsorted, (size_t)sizeU, sizeof(int64_t), cmp_i64);
+      const int64_t dm = Dsorted[(sizeU + 1) / 2 - 1];
+      lhs_scale = (u128)(uint64_t)q;                    /* q D <= (q+p) dm */
+      rhs = (u128)(uint64_t)(q + p) * (u128)(uint64_t)dm;
+    } else {
+      int64_t cntD = 0;
+      for (int64_t i = 0; i < sizeU; ++i) cntD += D[U[i]];
+      lhs_scale = (u128)(uint64_t)q * (u128)(uint64_t)sizeU; /* q N D <= (q+p) cnt */
+      rhs = (u128)(uint64_t)(q + p) * (u128)(uint64_t)cntD;
+    }
+    for (int64_t i = 0; i < sizeU; ++i) {
+      int64_t u = U[i];
+      if (lhs_scale * (u128)(uint64_t)D[u] <= rhs) {
+        R[sizeR].d = D[u];
+        R[sizeR].h = or_tiebreak(seed, (uint32_t)u);
+        R[sizeR].u = u;
+        ++sizeR;
+      } else {
+        U[k++] = u;
+      }
+    }
+    if (sizeR == 0) {
+      rc = -3;
+      break;
+    }
+    qsort(R, (size_t)sizeR, sizeof(okey_t), cmp_okey_asc);
+    if ((flags & OR_MEDIAN) && sizeR > (sizeU + 1) / 2) {
+      /* keep the lowest half; the rest stays in U */
+      for (int64_t i = (sizeU + 1) / 2; i < sizeR; ++i) U[k++] = R[i].u;
+      sizeR = (sizeU + 1) / 2;
+    }
+    /* order inside the round: by (D, rho_R) for ADG-O, else by rho_R */
+    if (!(flags & OR_SORTED))
+      for (int64_t i = 0; i < sizeR; ++i) R[i].d = 0;
+    qsort(R, (size_t)sizeR, sizeof(okey_t), cmp_okey_asc);
+    for (int64_t i = 0; i < sizeR; ++i) {
+      rho[R[i].u] = removed + i;
+      round_out[R[i].u] = (int32_t)l;
+    }
+    /* UPDATE: decrement D[w] of the neighbours w with a larger rho_ADG */
+    for (int64_t i = 0; i < sizeR; ++i) {
+      int64_t v = R[i].u;
+      for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+        int64_t w = col[e];
+        if (rho[w] > rho[v]) {
+          D[w] -= 1;
+          if (rho[w] == n) cut += 1;
+        }
+      }
+    }
+    sizeU = k;
+    removed += sizeR;
+    l += 1;
+  }
+  if (rc == 0) {
+    for (int64_t v = 0; v < n; ++v) pos_out[v] = rho[v];
+    if (stats_out) {
+      stats_out[0] = sum_U;
+      stats_out[1] = cut;
+      stats_out[2] = n;
+      stats_out[3] = l - 1;
+    }
+    rc = l - 1;
+  }
+  free(D); free(rho); free(U); free(Dsorted); free(R);
+  return rc;
+}
+
+/* Greedy colouring in decreasing order of a total order pos (a permutation
+ * of 0..n-1): JP's result under rho = pos.  Returns num_colors, or -1. */
+int64_t or_jp_total(int64_t n, const int64_t* row_ptr, const int32_t* col, const int64_t* pos,
+                    int32_t* color_out) {
+  if (n < 0) return -1;
+  if (n == 0) return 0;
+  int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  int64_t* stamp = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 2));
+  if (!order || !stamp) {
+    free(order); free(stamp);
+    return -1;
+  }
+  for (int64_t v = 0; v < n; ++v) order[v] = -1;
+  for (int64_t v = 0; v < n; ++v) {
+    if (pos[v] < 0 || pos[v] >= n || order[n - 1 - pos[v]] != -1) {
+      free(order); free(stamp);
+      return -1;
+    }
+    order[n - 1 - pos[v]] = v;
+    color_out[v] = 0;
+  }
+  for (int64_t c = 0; c < n + 2; ++c) stamp[c] = -1;
+  int64_t num_colors = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t v = order[i];
+    for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+      int32_t c = color_out[col[e]];
+      if (c > 0 && c <= n + 1) stamp[c] = v;
+    }
+    int64_t c = 1;
+    while (stamp[c] == v) ++c;
+    color_out[v] = (int32_t)c;
+    if (c > num_colors) num_colors = c;
+  }
+  free(order); free(stamp);
+  return num_colors;
+}
+
 /* ---- JP under rho = <rho_ADG, rho_R> (greedy definition) ------------------ */
 
 typedef struct {

@@ -103,16 +103,24 @@ def check_adg(row_ptr, col, p, q, rho, L):
 
 def check_jp(row_ptr, col, rho, seed, color):
     """Proper, and colour(v) = smallest colour >= 1 not used by pred(v)."""
+    check_jp_order(row_ptr, col, priority_keys(rho, seed), color)
+
+
+def check_jp_order(row_ptr, col, key, color):
+    """JP's output for the total order `key` (distinct; larger = coloured
+    first): proper, and colour(v) = smallest colour >= 1 not used by the
+    neighbours with a larger key."""
     row_ptr = np.asarray(row_ptr, dtype=np.int64)
     col = np.asarray(col, dtype=np.int64)
     color = np.asarray(color, dtype=np.int64)
+    key = np.asarray(key)
     n = row_ptr.size - 1
     if n == 0:
         return
+    assert np.unique(key).size == n, "not a total order"
     assert color.min() >= 1
     src = _src(row_ptr)
     assert not np.any(color[src] == color[col]), "improper colouring"
-    key = priority_keys(rho, seed)
     pred = key[col] > key[src]  # col is a predecessor of src
     # pred colours below colour(v), distinct per v: must be exactly colour(v)-1 of them
     s, c = src[pred], color[col[pred]]
@@ -162,3 +170,57 @@ def brute_degeneracy(n, edges):
                 mn = d if mn is None or d < mn else mn
         best = max(best, mn)
     return best
+
+
+SORTED, MEDIAN = 1, 2
+
+
+def check_adg_variant(row_ptr, col, p, q, seed, flags, rnd, pos, L):
+    """The ADG variants from their definitions, every degree recomputed from
+    the graph (deg_U over U_l = {v : round(v) >= l}):
+    * MEDIAN (ADG-M): R_l is the ceil(|U_l|/2) vertices of U_l lowest by
+      (deg_U, rho_R) -- the cap of half of U always binds, because at least
+      ceil(|U|/2) vertices have deg_U <= the lower median <= (1+eps) times
+      it, and this is checked too;
+    * otherwise R_l follows Algorithm 1's selection rule (check_adg);
+    * pos is the total order JP colours by: rounds in increasing order, and
+      inside a round increasing (deg_U at selection, rho_R) with SORTED
+      (ADG-O), increasing rho_R without.
+    Returns D at selection per vertex."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    rnd = np.asarray(rnd, dtype=np.int64)
+    pos = np.asarray(pos, dtype=np.int64)
+    n = row_ptr.size - 1
+    if n == 0:
+        assert L == 0
+        return np.zeros(0, dtype=np.int64)
+    assert rnd.min() >= 1 and rnd.max() == L
+    assert np.array_equal(np.sort(pos), np.arange(n)), "pos is not a permutation"
+    h = tiebreak_np(seed, n).astype(np.int64)
+    src = _src(row_ptr)
+    dsel = np.zeros(n, dtype=np.int64)
+    if not flags & MEDIAN:
+        check_adg(row_ptr, col, p, q, rnd, L)
+    for l in range(1, L + 1):
+        inU = rnd >= l
+        sizeU = int(inU.sum())
+        edge_in = inU[src] & inU[col]
+        degU = np.bincount(src[edge_in], minlength=n)
+        removed = rnd == l
+        dsel[removed] = degU[removed]
+        if flags & MEDIAN:
+            ids = np.flatnonzero(inU)
+            k = (sizeU + 1) // 2
+            dm = int(np.sort(degU[ids])[k - 1])
+            assert int(np.sum(q * degU[ids] <= (q + p) * dm)) >= k
+            low = ids[np.lexsort((h[ids], degU[ids]))[:k]]
+            expect = np.zeros(n, dtype=bool)
+            expect[low] = True
+            assert np.array_equal(expect, removed), "round %d: not the lowest half" % l
+    inner = dsel * (1 << 32) + h if flags & SORTED else h
+    order = np.lexsort((inner, rnd))
+    rank = np.empty(n, dtype=np.int64)
+    rank[order] = np.arange(n)
+    assert np.array_equal(rank, pos), "order inside the rounds"
+    return dsel

@@ -13,7 +13,11 @@ mathematics fix, never against itself or the GPU path.
   (ADG approximation lemma) and the colour bound 2(1+eps)d + 1 (JP-ADG colour
   corollary);
 * published test vectors of the hash building blocks (SplitMix64,
-  MurmurHash3's fmix32) and the bijectivity of the tie-break hash.
+  MurmurHash3's fmix32) and the bijectivity of the tie-break hash;
+* the variants ADG-O (sorted R, the ADG-O listing) and ADG-M (median, the
+  section on the degree median): definition checks per round, ADG-M's round
+  count (halving), ADG-O's full 2(1+eps)-approximate order, ADG-M's partial
+  4-approximate order and 4d + 1 colours, hand-worked small cases.
 """
 import itertools
 import math
@@ -23,8 +27,8 @@ import pytest
 
 import graphgen
 import oracle
-from checkers import (brute_degeneracy, check_adg, check_jp, edges_to_csr, fmix32_np, pred_count,
-                      priority_keys, splitmix64_first, tiebreak_np)
+from checkers import (MEDIAN, SORTED, brute_degeneracy, check_adg, check_adg_variant, check_jp, check_jp_order,
+                      edges_to_csr, fmix32_np, pred_count, priority_keys, splitmix64_first, tiebreak_np)
 
 EPS = [(0, 1), (1, 100), (1, 10), (1, 2), (1, 1), (10**6, 1)]
 
@@ -294,3 +298,130 @@ def test_priority_key_orientation():
     # higher round => higher priority regardless of hash
     k = priority_keys(np.array([1, 2]), 0)
     assert k[1] > k[0]
+
+
+# ---------------------------------------------------------------- ADG-O and ADG-M
+
+def _variant_bounds(rp, col, p, q, seed, flags, color, k, rnd, L, pos):
+    n = rp.size - 1
+    check_adg_variant(rp, col, p, q, seed, flags, rnd, pos, L)
+    check_jp_order(rp, col, pos, color)
+    assert k == (color.max() if n else 0)
+    if n == 0:
+        return
+    d = oracle.degeneracy(rp, col)
+    src = np.repeat(np.arange(n), np.diff(rp))
+    later = np.bincount(src[pos[col] > pos[src]], minlength=n)   # neighbours coloured earlier
+    same_or_later = np.bincount(src[rnd[col] >= rnd[src]], minlength=n)
+    if flags & MEDIAN:
+        # ADG-M halves U: |U_{l+1}| = floor(|U_l| / 2), so L = bit length of n
+        assert L == n.bit_length()
+        # partial 4-approximate order and JP-ADG-M's colour bound 4d + 1
+        assert np.all(same_or_later <= 4 * d)
+        assert k <= 4 * d + 1
+    else:
+        # ADG-O's order is total: at most 2(1+eps)d neighbours come later
+        if flags & SORTED:
+            assert np.all(q * later <= (q + p) * 2 * d)
+        assert k <= (q + p) * 2 * d // q + 1
+
+
+@pytest.mark.parametrize("flags", [SORTED, MEDIAN, SORTED | MEDIAN])
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 4, 5])
+def test_variants_all_graphs_up_to_5_vertices(n, flags):
+    pairs = [(u, v) for u in range(n) for v in range(u + 1, n)]
+    for mask in range(1 << len(pairs)):
+        edges = [pairs[i] for i in range(len(pairs)) if mask >> i & 1]
+        rp, col = edges_to_csr(n, edges)
+        for (p, q) in [(0, 1), (1, 10), (10**6, 1)]:
+            color, k, rnd, L, pos, _ = oracle.color_graph_ex(rp, col, p, q, mask, flags)
+            _variant_bounds(rp, col, p, q, mask, flags, color, k, rnd, L, pos)
+
+
+@pytest.mark.parametrize("flags", [0, SORTED, MEDIAN, SORTED | MEDIAN])
+@pytest.mark.parametrize("seed", range(3))
+def test_variants_random_graphs(seed, flags):
+    rng = np.random.default_rng(300 + seed)
+    for trial in range(4):
+        n = int(rng.integers(20, 300))
+        if trial % 2:
+            rp, col = graphgen.chung_lu(n, float(rng.uniform(2, 12)), 2.3, seed * 10 + trial)
+        else:
+            rp, col = graphgen.erdos_renyi(n, float(rng.uniform(0.01, 0.2)), seed * 10 + trial)
+        for (p, q) in [(0, 1), (1, 10), (1, 2)]:
+            color, k, rnd, L, pos, st = oracle.color_graph_ex(rp, col, p, q, trial, flags)
+            _variant_bounds(rp, col, p, q, trial, flags, color, k, rnd, L, pos)
+            if flags & MEDIAN:
+                # sum of |U_l| over the halving sequence n, floor(n/2), ...
+                sizes, m = [], n
+                while m:
+                    sizes.append(m)
+                    m //= 2
+                assert st["sum_active"] == sum(sizes)
+            else:
+                # Algorithm 1's rounds; with no flag, also its JP colouring
+                c0, k0, r0, L0, st0 = oracle.color_graph(rp, col, p, q, trial)
+                assert np.array_equal(rnd, r0) and L == L0 and st == st0
+                if not flags:
+                    assert np.array_equal(color, c0) and k == k0
+
+
+def test_sorted_star_colours_the_centre_first():
+    """One round (huge eps): ADG-O puts the centre (largest D) last in R, so
+    it has the highest rho and takes colour 1; the leaves take colour 2, in
+    increasing order of rho_R among themselves."""
+    s = 9
+    rp, col = edges_to_csr(s + 1, [(0, i) for i in range(1, s + 1)])
+    for seed in range(5):
+        color, k, rnd, L, pos, _ = oracle.color_graph_ex(rp, col, 10**6, 1, seed, SORTED)
+        assert L == 1 and k == 2 and color[0] == 1 and np.all(color[1:] == 2)
+        assert pos[0] == s
+        h = tiebreak_np(seed, s + 1)
+        assert np.array_equal(np.argsort(pos[1:]), np.argsort(h[1:]))
+
+
+def test_sorted_path_order_by_hand():
+    """P_5 in one round: ends (D = 1) at positions 0 and 1, inner vertices
+    (D = 2) at 2, 3, 4; each pair ordered by rho_R."""
+    rp, col = edges_to_csr(5, [(0, 1), (1, 2), (2, 3), (3, 4)])
+    seed = 7
+    h = tiebreak_np(seed, 5)
+    _, pos, L, _ = oracle.adg_ex(rp, col, 10**6, 1, seed, SORTED)
+    ends = sorted([0, 4], key=lambda v: h[v])
+    inner = sorted([1, 2, 3], key=lambda v: h[v])
+    expect = np.zeros(5, dtype=np.int64)
+    for i, v in enumerate(ends + inner):
+        expect[v] = i
+    assert L == 1 and np.array_equal(pos, expect)
+
+
+def test_median_path_by_hand():
+    """P_4 under ADG-M: round 1 removes the two ends (D = 1), round 2 the
+    inner vertex with the smaller rho_R (both have D = 1 then), round 3 the
+    other, for every eps."""
+    rp, col = edges_to_csr(4, [(0, 1), (1, 2), (2, 3)])
+    for seed in range(4):
+        h = tiebreak_np(seed, 4)
+        first, second = (1, 2) if h[1] < h[2] else (2, 1)
+        for (p, q) in [(0, 1), (1, 10), (10**6, 1)]:
+            rnd, pos, L, _ = oracle.adg_ex(rp, col, p, q, seed, MEDIAN)
+            assert L == 3 and rnd[0] == 1 and rnd[3] == 1 and rnd[first] == 2 and rnd[second] == 3
+
+
+def test_median_complete_graph():
+    """K_n: every D equal, so ADG-M removes the lower half by rho_R each round."""
+    n = 11
+    rp, col = edges_to_csr(n, [(u, v) for u in range(n) for v in range(u + 1, n)])
+    seed = 3
+    h = tiebreak_np(seed, n)
+    rnd, pos, L, _ = oracle.adg_ex(rp, col, 1, 10, seed, MEDIAN)
+    order = np.argsort(h)          # increasing rho_R
+    sizes = [11, 5, 2, 1]          # |U| per round; ceil(|U|/2) removed
+    start = 0
+    for l, m in enumerate(sizes, 1):
+        take = (m + 1) // 2
+        assert np.all(rnd[order[start:start + take]] == l)
+        start += take
+    assert L == 4
+    color, k = oracle.jp_total(rp, col, pos)
+    assert k == n and np.array_equal(np.argsort(-pos), np.argsort(color))
