@@ -116,7 +116,7 @@ def measured_traffic(kernel, workload):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline_graph(w, rp, col, m):
+def cpu_baseline_graph(w, rp, col, m, variant=0):
     """The oracle on the workload's graph; for RMAT-26 on the same generator
     at a smaller scale (a bounded sample of about 10-30 s of CPU work)."""
     import oracle
@@ -127,10 +127,15 @@ def cpu_baseline_graph(w, rp, col, m):
         m = col.size // 2
         sample = "R-MAT scale %d, same generator parameters and seed (m = %d)" % (w["cpu_sample_scale"], m)
     t0 = time.perf_counter()
-    oracle.color_graph(rp, col, w["eps"][0], w["eps"][1], w["seed"])
+    if variant:
+        oracle.color_graph_ex(rp, col, w["eps"][0], w["eps"][1], w["seed"], variant)
+        what = "ADG variant %d then greedy JP" % variant
+    else:
+        oracle.color_graph(rp, col, w["eps"][0], w["eps"][1], w["seed"])
+        what = "ADG then greedy JP"
     dt = time.perf_counter() - t0
     return {"value": m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": "%s: one serial run of the C oracle (ADG then greedy JP), %.2f s" % (sample, dt)}
+            "sample": "%s: one serial run of the C oracle (%s), %.2f s" % (sample, what, dt)}
 
 
 def calibration_copy(mib):
@@ -177,8 +182,13 @@ def run_single(args, w):
     p, q = w["eps"]
     seed = w["seed"]
 
+    variant = VARIANTS[args.variant]
+
     def step():
-        adg.color_graph(g, p, q, seed, workspace=ws, out=out)
+        if variant:
+            adg.color_graph_ex(g, p, q, seed, variant, workspace=ws)
+        else:
+            adg.color_graph(g, p, q, seed, workspace=ws, out=out)
 
     calibration_copy(args.calib_mib)
     for _ in range(args.warmup):
@@ -222,9 +232,11 @@ def run_single(args, w):
             log("  %-8s %8.3f ms  %4d launches" % (k, ms, cnt))
         log("  stats", st)
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline_graph(w, rp, col, m)
+    cpu = None if args.no_cpu_baseline else cpu_baseline_graph(w, rp, col, m, variant)
     cfg = {"workload": args.workload, "graph": w["kind"], "n": n, "nnz": nnz, "m": m, "eps": "%d/%d" % (p, q),
            "seed": seed, "rounds": st["num_rounds"], "colors": st["num_colors"]}
+    if variant:
+        cfg["variant"] = args.variant
     if w["kind"] == "rmat":
         cfg.update(scale=w["scale"], edge_factor=w["edge_factor"], abcd=[0.57, 0.19, 0.19, 0.05])
     return m / (dt / args.steps), dt * 1000 / args.steps, cfg, roofline, cpu, {}
@@ -407,6 +419,10 @@ def run_serving(args, w):
     return served["edges_per_s"], served["span_s"] * 1000, cfg, roofline, cpu, extra
 
 
+# ADG variant bits of color_graph_ex (0 = Algorithm 1)
+VARIANTS = {"adg": 0, "sorted": 1, "median": 2, "sorted_median": 3}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -414,6 +430,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variant", default="adg", choices=sorted(VARIANTS),
+                    help="single-graph workloads: adg = Algorithm 1 (default), sorted = ADG-O, median = ADG-M")
     ap.add_argument("--breakdown", action="store_true", help="print per-kernel-class times to stderr")
     ap.add_argument("--calib-mib", type=int, default=256,
                     help="size of a plain device copy issued before the run, so that profiler byte counters "

@@ -116,6 +116,48 @@ int color_graph(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_t s
                 int32_t* color_out, int32_t* round_out, int32_t* num_colors_out,
                 int32_t* num_rounds_out, void* workspace, size_t ws_bytes, void* stream);
 
+/* ---- Variants of ADG (the _ex entry points).
+ *
+ * variant is a bit set:
+ *   ADG_VARIANT_SORTED  ADG-O (the ADG-O listing of "Detailed Algorithm
+ *       Specifications", the variant the evaluation runs): the rounds are
+ *       Algorithm 1's; inside a round the order is increasing D at selection
+ *       (= the degree in G[U] when the round starts), equal D by rho_R.  JP
+ *       colours by this total order: larger (round, D, rho_R) first.
+ *   ADG_VARIANT_MEDIAN  ADG-M (section "Degree Median Instead of Degree
+ *       Average"): R is the ceil(|U|/2) vertices of U lowest by (D, rho_R).
+ *       This is the paper's R = {D <= (1+eps) median} limited to half of U:
+ *       at least ceil(|U|/2) vertices satisfy the bound for every eps >= 0,
+ *       so the limit always decides and eps has no effect.  L is the bit
+ *       length of n; JP-ADG-M uses at most 4d + 1 colours.  The tie-break
+ *       seed decides which vertices of equal D fall in the lower half.
+ * Both may be combined.  variant = 0 is Algorithm 1 (adg_order,
+ * color_graph).  Other bits: ADG_ERR_ARG. */
+enum { ADG_VARIANT_SORTED = 1, ADG_VARIANT_MEDIAN = 2 };
+
+/* Workspace bytes for adg_order_ex with a pos output (adg_workspace_bytes
+ * plus sort buffers of 24 n bytes); 0 for invalid sizes. */
+size_t adg_order_workspace_bytes(int64_t n, int64_t nnz);
+
+/* ADG with a variant.  round_out[v] in 1..L as adg_order; pos_out (device
+ * int32[n], may be NULL) receives the total order JP colours by as ranks
+ * 0..n-1 (larger = coloured first): rounds increasing, inside a round
+ * increasing (D at selection, rho_R) with ADG_VARIANT_SORTED -- that is
+ * ADG-O's rho, "rho(r_i) = l + i" -- else increasing rho_R(v) = the 32-bit
+ * hash of v under seed.  seed matters for pos and for ADG_VARIANT_MEDIAN.
+ * With pos_out, ws_bytes must be at least adg_order_workspace_bytes.
+ * Errors: as adg_order. */
+int adg_order_ex(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_t seed, uint32_t variant,
+                 int32_t* round_out, int32_t* pos_out, int32_t* num_rounds_out, void* workspace,
+                 size_t ws_bytes, void* stream);
+
+/* JP-ADG with a variant: JP (Algorithm 3) under the total order pos of
+ * adg_order_ex, with JP Part 1 fused into the update as color_graph.
+ * variant = 0 is color_graph.  Errors: as color_graph. */
+int color_graph_ex(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_t seed, uint32_t variant,
+                   int32_t* color_out, int32_t* round_out, int32_t* num_colors_out,
+                   int32_t* num_rounds_out, void* workspace, size_t ws_bytes, void* stream);
+
 /* ---- Many independent graphs in one call.
  *
  * The batch is one concatenated CSR: graph g owns global vertex slots

@@ -47,7 +47,11 @@ class _Profile(ctypes.Structure):
 
 
 KERNEL_CLASSES = ["init", "stats", "count", "scan", "scatter", "update", "part1", "jp_prep", "jp", "finish",
-                  "batched", "jp_narrow", "update_huge"]
+                  "batched", "jp_narrow", "update_huge", "median_select", "order_sort"]
+
+# ADG variants (bit set): ADG-O's sorted rounds and ADG-M's median selection
+SORTED = 1
+MEDIAN = 2
 
 _lib = None
 
@@ -70,6 +74,12 @@ def lib():
     L.jp_color.argtypes = [P(_Csr), vp, u64, vp, vp, vp, sz, vp]
     L.color_graph.restype = ctypes.c_int
     L.color_graph.argtypes = [P(_Csr), i32, i32, u64, vp, vp, vp, vp, vp, sz, vp]
+    L.adg_order_workspace_bytes.restype = sz
+    L.adg_order_workspace_bytes.argtypes = [i64, i64]
+    L.adg_order_ex.restype = ctypes.c_int
+    L.adg_order_ex.argtypes = [P(_Csr), i32, i32, u64, ctypes.c_uint32, vp, vp, vp, vp, sz, vp]
+    L.color_graph_ex.restype = ctypes.c_int
+    L.color_graph_ex.argtypes = [P(_Csr), i32, i32, u64, ctypes.c_uint32, vp, vp, vp, vp, vp, sz, vp]
     L.adg_get_stats.restype = ctypes.c_int
     L.adg_get_stats.argtypes = [vp, sz, P(_Stats), vp]
     L.adg_validate_csr.restype = ctypes.c_int
@@ -193,6 +203,49 @@ def color_graph(g, eps_num, eps_den, seed, workspace=None, stream=None, want_rou
                            _ptr(rnd) if rnd is not None else ctypes.c_void_p(0), _ptr(nc), _ptr(nr), _ptr(ws),
                            ws.numel(), _stream(stream))
     _check(rc, "color_graph")
+    return color[:g.n], nc, (rnd[:g.n] if rnd is not None else None), nr
+
+
+def order_workspace_bytes(n, nnz):
+    b = lib().adg_order_workspace_bytes(int(n), int(nnz))
+    if b == 0:
+        raise ValueError("invalid graph size")
+    return b
+
+
+def adg_order_ex(g, eps_num, eps_den, seed, variant, want_pos=True, workspace=None, stream=None):
+    """ADG with a variant (SORTED, MEDIAN).  Returns (round int32[n], pos int32[n] or None,
+    num_rounds int32[1]); pos ranks the vertices in the order JP colours by (larger first)."""
+    torch = _torch()
+    need = order_workspace_bytes(g.n, g.nnz) if want_pos else workspace_bytes(g.n, g.nnz)
+    ws = workspace if workspace is not None else torch.empty(need, dtype=torch.uint8, device=g.device)
+    if ws.numel() < need:
+        raise ValueError("workspace too small: %d < %d bytes" % (ws.numel(), need))
+    rnd = torch.empty(max(g.n, 1), dtype=torch.int32, device=g.device)
+    pos = torch.empty(max(g.n, 1), dtype=torch.int32, device=g.device) if want_pos else None
+    nr = torch.zeros(1, dtype=torch.int32, device=g.device)
+    csr = g.csr()
+    rc = lib().adg_order_ex(ctypes.byref(csr), int(eps_num), int(eps_den), int(seed) & (2**64 - 1), int(variant),
+                            _ptr(rnd), _ptr(pos) if pos is not None else ctypes.c_void_p(0), _ptr(nr), _ptr(ws),
+                            ws.numel(), _stream(stream))
+    _check(rc, "adg_order_ex")
+    return rnd[:g.n], (pos[:g.n] if pos is not None else None), nr
+
+
+def color_graph_ex(g, eps_num, eps_den, seed, variant, workspace=None, stream=None, want_rounds=True):
+    """JP-ADG with a variant (SORTED = JP-ADG-O, MEDIAN = JP-ADG-M).  Returns
+    (color, num_colors, round or None, num_rounds) as GPU tensors."""
+    torch = _torch()
+    ws = _workspace(g, workspace)
+    color = torch.empty(max(g.n, 1), dtype=torch.int32, device=g.device)
+    rnd = torch.empty(max(g.n, 1), dtype=torch.int32, device=g.device) if want_rounds else None
+    nc = torch.zeros(1, dtype=torch.int32, device=g.device)
+    nr = torch.zeros(1, dtype=torch.int32, device=g.device)
+    csr = g.csr()
+    rc = lib().color_graph_ex(ctypes.byref(csr), int(eps_num), int(eps_den), int(seed) & (2**64 - 1), int(variant),
+                              _ptr(color), _ptr(rnd) if rnd is not None else ctypes.c_void_p(0), _ptr(nc), _ptr(nr),
+                              _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "color_graph_ex")
     return color[:g.n], nc, (rnd[:g.n] if rnd is not None else None), nr
 
 

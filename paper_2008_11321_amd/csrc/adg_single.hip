@@ -32,6 +32,17 @@
 // over same-round successors only; then one bulk kernel pushes the round's
 // colours to its earlier-round successors.  Narrow levels (and whole small
 // rounds) run in a single block with block barriers; wide ones over the grid.
+//
+// Variants (flags of the _ex entry points):
+//   ADG-O (the ADG-O listing): R is ordered by D at selection, so JP's order
+//     inside a round is (D, rho_R) instead of rho_R.  D of a vertex removed in
+//     round l stays at its selection value (UPDATE only touches vertices still
+//     in U), so the key is available to UPDATE when it partitions the rows.
+//   ADG-M (degree median): R is the ceil(|U|/2) vertices lowest by (D, rho_R).
+//     Its threshold (1+eps) times the median always admits at least that
+//     many, so the cap of half of U decides R; k_msel finds the
+//     ceil(|U|/2)-th smallest 64-bit key (D << 32 | rho_R) by radix selection
+//     and the selection kernels compare against it.
 
 #include <hip/hip_runtime.h>
 
@@ -45,6 +56,7 @@
 #include "../../include/adg.h"
 #include "adg_device.h"
 #include "adg_host.h"
+#include "radix_sort.h"
 
 namespace adg {
 
@@ -65,6 +77,9 @@ constexpr int NARROW_WORDS = 4096;           // colour bitmap words of a level i
 constexpr int NARROW_SUCC = 4096;            // same-round successor entries of a level it takes
 constexpr int NARROW_XPULL = 512;            // round size whose later-round colours it pulls in
 constexpr int NARROW_UNROLL = 4;             // edges per thread in flight in a narrow level
+constexpr int MSEL_BINS = 2048;              // radix selection: 11-bit digits
+constexpr int MSEL_PASSES = 6;               // 11 x 5 + 9 bits cover a 64-bit key
+constexpr int MSEL_BLOCKS = 512;
 
 enum { OP_NONE = 0, OP_SPLIT = 1, OP_LEVEL = 2, OP_XPULL = 3 };
 
@@ -110,6 +125,13 @@ struct Ctrl {
   int grid_ran;                // the grid kernel has run grid_op
   int num_colors;
   int pad_jp;
+  // ADG-M radix selection of round l: keys whose masked bits are below
+  // msel_prefix are in R, and so are those equal to it once msel_found is set
+  unsigned long long msel_prefix;
+  unsigned long long msel_mask;
+  unsigned long long msel_k;   // rank still to find among the keys matching the prefix
+  unsigned int msel_blocks;    // blocks of the current pass that have added their histogram
+  int msel_found;
   JpState js;
 };
 
@@ -123,6 +145,9 @@ struct Params {
   int fused;                   // JP Part 1 fused into UPDATE
   int max_rounds;
   int ord_identity;            // ORD is the identity (one pseudo-round: jp_color)
+  int sorted;                  // ADG-O: same-round order by (D at selection, rho_R)
+  int median;                  // ADG-M: R = the lower half of U by (D, rho_R)
+  unsigned* mhist;             // [MSEL_BINS] radix selection histogram
   Ctrl* ctrl;
   int* round;                  // rho_ADG (user output or workspace)
   int* D;
@@ -216,6 +241,9 @@ __global__ void k_init(Params P) {
   c->bm_next = 0;
   c->huge_ctr = 0;
   c->xhuge = 0;
+  c->msel_prefix = c->msel_mask = c->msel_k = 0;
+  c->msel_blocks = 0;
+  c->msel_found = 0;
   JpState& j = c->js;
   j.round = 0;
   j.level = 0;
@@ -232,6 +260,8 @@ __global__ void k_init(Params P) {
     j.ssum[k] = 0;
   }
   for (int k = 0; k < 3; ++k) P.l0n[k] = 0;
+  if (P.median)
+    for (int k = 0; k < MSEL_BINS; ++k) P.mhist[k] = 0;
 }
 
 // One block.  Computes N_l, S_l and T_l for round l, or ends the loop.
@@ -284,6 +314,13 @@ __global__ void k_stats(Params P, int l) {
   c->T = (unsigned)(T > 0x7fffffffull ? 0x7fffffffull : T);
   c->round = l;
   c->sum_active += N;
+  if (P.median) {
+    c->msel_prefix = 0;
+    c->msel_mask = 0;
+    c->msel_k = (N + 1) / 2;
+    c->msel_found = 0;
+    c->msel_blocks = 0;
+  }
 }
 
 struct Chunk {
@@ -307,17 +344,47 @@ struct Sel {
   int d;
   int cat;
 };
-__device__ __forceinline__ Sel classify(const Params& P, int l, long long i, unsigned T, const int* Uin) {
+// Selection threshold of a round: T for Algorithm 1, the radix-selected key
+// for ADG-M.
+struct Thr {
+  unsigned T;
+  int median;
+  uint32_t hkey;
+  unsigned long long mask, prefix;
+};
+__device__ __forceinline__ Thr load_thr(const Params& P, const Ctrl* c) {
+  return {c->T, P.median, P.hkey, c->msel_mask, c->msel_prefix};
+}
+// ADG-M's key of u: D at selection, then rho_R.
+__device__ __forceinline__ unsigned long long msel_key(uint32_t hkey, int u, int d) {
+  return ((unsigned long long)(unsigned)d << 32) | tiebreak(hkey, (uint32_t)u);
+}
+__device__ __forceinline__ bool in_R(const Thr& t, int u, int d) {
+  if (!t.median) return (unsigned)d <= t.T;
+  return (msel_key(t.hkey, u, d) & t.mask) <= t.prefix;
+}
+// Element i of U_l and its D (round 1: U_1 = V, D = the degree).
+__device__ __forceinline__ void u_elem(const Params& P, int l, long long i, const int* Uin, int* u, int* d) {
+  if (l == 1) {
+    *u = (int)i;
+    *d = (int)(P.rp[i + 1] - P.rp[i]);
+  } else {
+    *u = Uin[i];
+    *d = P.D[*u];
+  }
+}
+
+__device__ __forceinline__ Sel classify(const Params& P, int l, long long i, const Thr& T, const int* Uin) {
   Sel s;
   if (l == 1) {
     s.u = (int)i;
     s.d = (int)(P.rp[i + 1] - P.rp[i]);
-    if ((unsigned)s.d <= T) s.cat = s.d <= SMALL_DEG ? 0 : 1;
+    if (in_R(T, s.u, s.d)) s.cat = s.d <= SMALL_DEG ? 0 : 1;
     else s.cat = 2;
   } else {
     s.u = Uin[i];
     s.d = P.D[s.u];
-    if ((unsigned)s.d <= T) {
+    if (in_R(T, s.u, s.d)) {
       int deg = (int)(P.rp[s.u + 1] - P.rp[s.u]);
       s.cat = deg <= SMALL_DEG ? 0 : 1;
     } else {
@@ -327,11 +394,79 @@ __device__ __forceinline__ Sel classify(const Params& P, int l, long long i, uns
   return s;
 }
 
+// One pass of ADG-M's radix selection (pass 0 takes the top 11 bits of the
+// key, pass 5 the last 9).  Every block histograms the digit of the keys of
+// U_l that match the prefix chosen so far; the last block to finish picks the
+// digit holding the msel_k-th smallest key, extends the prefix and clears the
+// histogram for the next pass.  A pass stops the selection early when all
+// keys of the picked digit are in R.
+__global__ __launch_bounds__(BS) void k_msel(Params P, int l, int pass) {
+  Ctrl* c = P.ctrl;
+  if (c->done || c->msel_found) return;
+  __shared__ unsigned hist[MSEL_BINS];
+  __shared__ int last;
+  const int shift = pass == MSEL_PASSES - 1 ? 0 : 64 - 11 * (pass + 1);
+  const unsigned width = pass == MSEL_PASSES - 1 ? 9 : 11;
+  const unsigned long long dmask = ((1ull << width) - 1) << shift;
+  const unsigned long long N = c->N, mask = c->msel_mask, prefix = c->msel_prefix;
+  const int* Uin = P.UL[(l + 1) & 1];
+  for (int k = threadIdx.x; k < MSEL_BINS; k += BS) hist[k] = 0;
+  __syncthreads();
+  for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < (long long)N; i += (long long)gridDim.x * BS) {
+    int u, d;
+    u_elem(P, l, i, Uin, &u, &d);
+    const unsigned long long key = msel_key(P.hkey, u, d);
+    if ((key & mask) == prefix) atomicAdd(&hist[(key & dmask) >> shift], 1u);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < MSEL_BINS; k += BS)
+    if (hist[k]) __hip_atomic_fetch_add(&P.mhist[k], hist[k], __ATOMIC_RELAXED, SC_AGENT);
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0)
+    last = __hip_atomic_fetch_add(&c->msel_blocks, 1u, __ATOMIC_ACQ_REL, SC_AGENT) == gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  // the last block: inclusive scan of the histogram, 8 bins per thread
+  constexpr int PER = MSEL_BINS / BS;
+  unsigned loc[PER];
+  unsigned run = 0;
+  for (int k = 0; k < PER; ++k) {
+    loc[k] = __hip_atomic_load(&P.mhist[threadIdx.x * PER + k], __ATOMIC_RELAXED, SC_AGENT);
+    run += loc[k];
+  }
+  __shared__ unsigned part[BS];
+  part[threadIdx.x] = run;
+  __syncthreads();
+  for (int off = 1; off < BS; off <<= 1) {
+    const unsigned v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  const unsigned long long want = c->msel_k;
+  unsigned long long before = part[threadIdx.x] - run;
+  for (int k = 0; k < PER; ++k) {
+    // the bin where the running count first reaches `want`
+    if (before < want && before + loc[k] >= want) {
+      const unsigned long long bin = (unsigned long long)(threadIdx.x * PER + k);
+      c->msel_prefix = prefix | (bin << shift);
+      c->msel_mask = mask | dmask;
+      c->msel_k = want - before;
+      c->msel_found = (before + loc[k] == want) || pass == MSEL_PASSES - 1;
+    }
+    before += loc[k];
+  }
+  for (int k = threadIdx.x; k < MSEL_BINS; k += BS) P.mhist[k] = 0;
+  if (threadIdx.x == 0) c->msel_blocks = 0;
+}
+
 __global__ __launch_bounds__(BS) void k_count(Params P, int l) {
   Ctrl* c = P.ctrl;
   if (c->done) return;
   const unsigned long long N = c->N;
-  const unsigned T = c->T;
+  const Thr T = load_thr(P, c);
   const int* Uin = P.UL[(l + 1) & 1];
   Chunk ch = sel_chunk(N);
   unsigned c0 = 0, c1 = 0, c2 = 0;
@@ -417,7 +552,7 @@ __global__ __launch_bounds__(BS) void k_scatter(Params P, int l) {
   Ctrl* c = P.ctrl;
   if (c->done) return;
   const unsigned long long N = c->N;
-  const unsigned T = c->T;
+  const Thr T = load_thr(P, c);
   const unsigned nRs = c->nRs;
   const int* Uin = P.UL[(l + 1) & 1];
   int* Uout = P.UL[l & 1];
@@ -454,6 +589,7 @@ __global__ __launch_bounds__(BS) void k_scatter(Params P, int l) {
       if (s.cat != 2) {
         P.round[s.u] = l;
         P.status[s.u] = code;
+        if (P.sorted && l == 1) P.D[s.u] = s.d;   // ADG-O's same-round key
       } else if (l == 1) {
         P.round[s.u] = 0;
         P.status[s.u] = 0;
@@ -472,9 +608,15 @@ __global__ __launch_bounds__(BS) void k_scatter(Params P, int l) {
 // successor, 2 = successor from an earlier round.  Decrements D[w] for w
 // still in U.
 enum { NB_PRED = 0, NB_SUCC_SAME = 1, NB_SUCC_EARLIER = 2, NB_PRED_SAME = 3, NB_NONE = 5 };
+// JP's order inside a round: rho_R, after D at selection for ADG-O.
+__device__ __forceinline__ unsigned long long same_key(const Params& P, int v) {
+  const unsigned long long h = tiebreak(P.hkey, (uint32_t)v);
+  return P.sorted ? ((unsigned long long)(unsigned)P.D[v] << 32) | h : h;
+}
+
 template <bool FUSED>
-__device__ __forceinline__ int visit3(const Params& P, int w, int l, unsigned char code, uint32_t hv, unsigned& x,
-                                      bool decrement) {
+__device__ __forceinline__ int visit3(const Params& P, int w, int l, unsigned char code, unsigned long long hv,
+                                      unsigned& x, bool decrement) {
   unsigned char st = P.status[w];
   if (st == 0) {
     if (decrement) {
@@ -484,7 +626,7 @@ __device__ __forceinline__ int visit3(const Params& P, int w, int l, unsigned ch
     return NB_PRED;
   }
   if (FUSED && st == code && P.round[w] == l)
-    return tiebreak(P.hkey, (uint32_t)w) > hv ? NB_PRED_SAME : NB_SUCC_SAME;
+    return same_key(P, w) > hv ? NB_PRED_SAME : NB_SUCC_SAME;
   return NB_SUCC_EARLIER;
 }
 
@@ -556,7 +698,7 @@ __device__ void update_small(const Params& P, int v, bool valid, int l, unsigned
     b = P.rp[v];
     e = P.rp[v + 1];
   }
-  const uint32_t hv = tiebreak(P.hkey, (uint32_t)v);
+  const unsigned long long hv = same_key(P, v);
   long long nl = 0, nps = 0, ns = 0;
   unsigned long long cls = 0;   // the row's classes, 2 bits per entry (SMALL_DEG <= 32)
   for (long long j = b; j < e; ++j) {
@@ -602,7 +744,7 @@ __device__ void update_big(const Params& P, int v, int l, unsigned char code, un
     }
     return;
   }
-  const uint32_t hv = tiebreak(P.hkey, (uint32_t)v);
+  const unsigned long long hv = same_key(P, v);
   const unsigned lane = lane_id();
   long long nl = 0, nps = 0, ns = 0;
   // rows of up to 16 chunks keep their classes (2 bits per chunk and lane)
@@ -714,7 +856,7 @@ __global__ __launch_bounds__(BS) void k_update_huge_count(Params P, int l) {
     const long long b = P.rp[v], e = P.rp[v + 1];
     const long long c0 = b + ((long long)k - first) * HUGE_CHUNK;
     const long long c1 = c0 + HUGE_CHUNK < e ? c0 + HUGE_CHUNK : e;
-    const uint32_t hv = tiebreak(P.hkey, (uint32_t)v);
+    const unsigned long long hv = same_key(P, v);
     unsigned cnt[4] = {0, 0, 0, 0};
     for (long long base = c0; base < c1; base += WAVE) {
       const long long j = base + lane;
@@ -751,7 +893,7 @@ __global__ __launch_bounds__(BS) void k_update_huge_place(Params P, int l) {
     const long long b = P.rp[v], e = P.rp[v + 1];
     const long long c0 = b + ((long long)k - first) * HUGE_CHUNK;
     const long long c1 = c0 + HUGE_CHUNK < e ? c0 + HUGE_CHUNK : e;
-    const uint32_t hv = tiebreak(P.hkey, (uint32_t)v);
+    const unsigned long long hv = same_key(P, v);
     unsigned* C = P.HC + 8 * (size_t)h;
     const long long nl = C[NB_PRED], nps = C[NB_PRED_SAME], ns = C[NB_SUCC_SAME];
     const long long np = nl + nps;
@@ -1752,6 +1894,24 @@ __global__ void k_finish(Params P, int* num_colors_out, int* num_rounds_out) {
 
 // ================================================================ CSR validation
 
+// ---- the total order JP colours by (adg_order_ex's pos output): rounds in
+// increasing order, inside a round the same-round key (rho_R, after D at
+// selection for ADG-O), as ranks 0 .. n-1.
+__global__ __launch_bounds__(BS) void k_order_keys(Params P, unsigned long long* keys, unsigned* vals) {
+  for (long long v = (long long)blockIdx.x * BS + threadIdx.x; v < P.n; v += (long long)gridDim.x * BS) {
+    keys[v] = same_key(P, (int)v);
+    vals[v] = (unsigned)v;
+  }
+}
+__global__ __launch_bounds__(BS) void k_order_round_keys(Params P, unsigned long long* keys, const unsigned* vals) {
+  for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < P.n; i += (long long)gridDim.x * BS)
+    keys[i] = (unsigned)P.round[vals[i]];
+}
+__global__ __launch_bounds__(BS) void k_order_pos(Params P, const unsigned* vals, int* pos) {
+  for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < P.n; i += (long long)gridDim.x * BS)
+    pos[vals[i]] = (int)i;
+}
+
 __global__ void k_validate(int n, long long nnz, const long long* rp, const int* col, int* bad) {
   long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   long long stride = (long long)gridDim.x * blockDim.x;
@@ -1807,7 +1967,8 @@ namespace adg {
 // ---- optional per-kernel timing with HIP events on the launch stream
 namespace {
 const char* kclass_names[KC_NUM] = {"init", "stats", "count", "scan", "scatter", "update", "part1",
-                                    "jp_prep", "jp", "finish", "batched", "jp_narrow", "update_huge"};
+                                    "jp_prep", "jp", "finish", "batched", "jp_narrow", "update_huge",
+                                    "median_select", "order_sort"};
 struct ProfRec {
   int cls;
   hipEvent_t a, b;
@@ -1857,7 +2018,7 @@ namespace {
 
 struct Layout {
   size_t ctrl, bcount, boff, bsum, xpart, D, status, UL0, UL1, ORD, roundN, round, dag, npred, nsr, cnt, rec, B,
-      bm_cap, L0, l0n, F0, F1, H0, H1, hub_cap, HL, HC, huge_cap, total;
+      bm_cap, L0, l0n, F0, F1, H0, H1, hub_cap, HL, HC, huge_cap, mhist, total;
 };
 
 constexpr int UPD_BLOCKS = 2048;
@@ -1905,8 +2066,31 @@ Layout make_layout(int64_t n, int64_t nnz) {
   L.huge_cap = (size_t)nnz / HUGE_DEG + 64;
   L.HL = take(8 * L.huge_cap);
   L.HC = take(4 * 8 * L.huge_cap);
+  L.mhist = take(4 * MSEL_BINS);
   L.total = off;
   return L;
+}
+
+// Sort buffers of adg_order_ex's pos output, after the main layout.
+struct OrderLayout {
+  size_t keys0, keys1, vals0, vals1, counts, total;
+};
+OrderLayout make_order_layout(int64_t n, int64_t nnz) {
+  OrderLayout O{};
+  size_t off = make_layout(n, nnz).total;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + (bytes ? bytes : 1), 256);
+    return o;
+  };
+  const size_t nn = (size_t)n;
+  O.keys0 = take(8 * nn);
+  O.keys1 = take(8 * nn);
+  O.vals0 = take(4 * nn);
+  O.vals1 = take(4 * nn);
+  O.counts = take(rs::count_bytes());
+  O.total = off;
+  return O;
 }
 
 int check_graph(const adg_csr_t* g) {
@@ -1927,7 +2111,7 @@ int check_ws(void* ws, size_t ws_bytes, int64_t n, int64_t nnz) {
 }
 
 Params make_params(const adg_csr_t* g, void* ws, uint64_t p, uint64_t q, uint64_t seed, int fused, int* round_buf,
-                   int* color) {
+                   int* color, uint32_t variant = 0) {
   Layout L = make_layout(g->n, g->nnz);
   char* base = (char*)ws;
   Params P{};
@@ -1940,6 +2124,9 @@ Params make_params(const adg_csr_t* g, void* ws, uint64_t p, uint64_t q, uint64_
   P.hkey = hash_key_from_seed(seed);
   P.fused = fused;
   P.ord_identity = 0;
+  P.sorted = (variant & ADG_VARIANT_SORTED) != 0;
+  P.median = (variant & ADG_VARIANT_MEDIAN) != 0;
+  P.mhist = (unsigned*)(base + L.mhist);
   P.ctrl = (Ctrl*)(base + L.ctrl);
   P.round = round_buf ? round_buf : (int*)(base + L.round);
   P.D = (int*)(base + L.D);
@@ -1977,6 +2164,12 @@ Params make_params(const adg_csr_t* g, void* ws, uint64_t p, uint64_t q, uint64_
   if (p > 0 && g->n > 1) {
     double b = std::ceil(std::log((double)g->n) / std::log1p((double)p / (double)q)) + 2.0;
     if (b < (double)bound) bound = (long long)b;
+  }
+  if (P.median) {
+    // ADG-M removes ceil(|U|/2) vertices per round: L = bit length of n
+    bound = 1;
+    while ((1LL << bound) <= (long long)g->n) ++bound;
+    bound += 1;
   }
   if (bound < 1) bound = 1;
   P.max_rounds = (int)std::min<long long>(bound, 0x7fffffff);
@@ -2031,6 +2224,11 @@ int run_adg(Params& P, hipStream_t s, bool fused, int* num_rounds_host) {
       {
         TIMED(KC_STATS, s);
         hipLaunchKernelGGL(k_stats, dim3(1), dim3(BS), 0, s, P, l);
+      }
+      if (P.median) {
+        TIMED(KC_MSEL, s);
+        for (int pass = 0; pass < MSEL_PASSES; ++pass)
+          hipLaunchKernelGGL(k_msel, dim3(MSEL_BLOCKS), dim3(BS), 0, s, P, l, pass);
       }
       {
         TIMED(KC_COUNT, s);
@@ -2127,6 +2325,34 @@ int run_jp(Params& P, hipStream_t s, int rounds) {
   return ADG_OK;
 }
 
+// pos[v] = rank of v in JP's order, by a stable sort of the same-round keys
+// and then of the rounds.
+int run_order(Params& P, hipStream_t s, int rounds, void* ws, int32_t* pos_out) {
+  TIMED(KC_ORDER, s);
+  const OrderLayout O = make_order_layout(P.n, P.nnz);
+  char* base = (char*)ws;
+  uint64_t* keys[2] = {(uint64_t*)(base + O.keys0), (uint64_t*)(base + O.keys1)};
+  uint32_t* vals[2] = {(uint32_t*)(base + O.vals0), (uint32_t*)(base + O.vals1)};
+  uint32_t* counts = (uint32_t*)(base + O.counts);
+  const unsigned blocks = (unsigned)std::min<long long>(((long long)P.n + BS - 1) / BS, 4096);
+  hipLaunchKernelGGL(k_order_keys, dim3(blocks), dim3(BS), 0, s, P, (unsigned long long*)keys[0], vals[0]);
+  HIPCHK(hipGetLastError());
+  int cur = 0;
+  HIPCHK(rs::sort_pairs(keys, vals, P.n, 0, P.sorted ? 64 : 32, counts, s, &cur));
+  int bits = 0;
+  while (bits < 31 && (1 << bits) <= rounds) ++bits;
+  hipLaunchKernelGGL(k_order_round_keys, dim3(blocks), dim3(BS), 0, s, P, (unsigned long long*)keys[cur],
+                     vals[cur]);
+  HIPCHK(hipGetLastError());
+  uint64_t* k2[2] = {keys[cur], keys[cur ^ 1]};
+  uint32_t* v2[2] = {vals[cur], vals[cur ^ 1]};
+  int cur2 = 0;
+  HIPCHK(rs::sort_pairs(k2, v2, P.n, 0, bits, counts, s, &cur2));
+  hipLaunchKernelGGL(k_order_pos, dim3(blocks), dim3(BS), 0, s, P, v2[cur2], pos_out);
+  HIPCHK(hipGetLastError());
+  return ADG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2136,16 +2362,30 @@ size_t adg_workspace_bytes(int64_t n, int64_t nnz) {
   return make_layout(n, nnz).total;
 }
 
+size_t adg_order_workspace_bytes(int64_t n, int64_t nnz) {
+  if (n < 0 || nnz < 0 || n > 0x7ffffffeLL) return 0;
+  return make_order_layout(n, nnz).total;
+}
+
 int adg_order(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, int32_t* round_out, int32_t* num_rounds_out,
               void* workspace, size_t ws_bytes, void* stream) {
+  return adg_order_ex(g, eps_num, eps_den, 0, 0, round_out, nullptr, num_rounds_out, workspace, ws_bytes, stream);
+}
+
+int adg_order_ex(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_t seed, uint32_t variant,
+                 int32_t* round_out, int32_t* pos_out, int32_t* num_rounds_out, void* workspace, size_t ws_bytes,
+                 void* stream) {
   int rc = check_graph(g);
   if (rc) return rc;
   if (eps_num < 0 || eps_den < 1 || (g->n > 0 && !round_out)) return ADG_ERR_ARG;
+  if (variant & ~(uint32_t)(ADG_VARIANT_SORTED | ADG_VARIANT_MEDIAN)) return ADG_ERR_ARG;
   if ((rc = check_ws(workspace, ws_bytes, g->n, g->nnz))) return rc;
+  if (pos_out && ws_bytes < make_order_layout(g->n, g->nnz).total) return ADG_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
-  Params P = make_params(g, workspace, (uint64_t)eps_num, (uint64_t)eps_den, 0, 0, round_out, nullptr);
+  Params P = make_params(g, workspace, (uint64_t)eps_num, (uint64_t)eps_den, seed, 0, round_out, nullptr, variant);
   int L = 0;
   if ((rc = run_adg(P, s, false, &L))) return rc;
+  if (pos_out && P.n > 0 && (rc = run_order(P, s, L, workspace, pos_out))) return rc;
   {
     TIMED(KC_FINISH, s);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, P, (int*)nullptr, num_rounds_out);
@@ -2191,12 +2431,20 @@ int jp_color(const adg_csr_t* g, const int32_t* round, uint64_t seed, int32_t* c
 int color_graph(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_t seed, int32_t* color_out,
                 int32_t* round_out, int32_t* num_colors_out, int32_t* num_rounds_out, void* workspace,
                 size_t ws_bytes, void* stream) {
+  return color_graph_ex(g, eps_num, eps_den, seed, 0, color_out, round_out, num_colors_out, num_rounds_out,
+                        workspace, ws_bytes, stream);
+}
+
+int color_graph_ex(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_t seed, uint32_t variant,
+                   int32_t* color_out, int32_t* round_out, int32_t* num_colors_out, int32_t* num_rounds_out,
+                   void* workspace, size_t ws_bytes, void* stream) {
   int rc = check_graph(g);
   if (rc) return rc;
   if (eps_num < 0 || eps_den < 1 || (g->n > 0 && !color_out)) return ADG_ERR_ARG;
+  if (variant & ~(uint32_t)(ADG_VARIANT_SORTED | ADG_VARIANT_MEDIAN)) return ADG_ERR_ARG;
   if ((rc = check_ws(workspace, ws_bytes, g->n, g->nnz))) return rc;
   hipStream_t s = (hipStream_t)stream;
-  Params P = make_params(g, workspace, (uint64_t)eps_num, (uint64_t)eps_den, seed, 1, round_out, color_out);
+  Params P = make_params(g, workspace, (uint64_t)eps_num, (uint64_t)eps_den, seed, 1, round_out, color_out, variant);
   int L = 0;
   if ((rc = run_adg(P, s, true, &L))) return rc;
   if ((rc = run_jp(P, s, L))) return rc;

@@ -85,3 +85,18 @@ def test_batched_entry_points_reject_bad_arguments_without_gpu():
     assert L.color_graph_batched(ctypes.byref(b2), *out, ctypes.byref(good), fake + 8, 1 << 30, None) == -2
     assert L.color_graph_batched(ctypes.byref(b2), -1, 10, 0, fake, None, fake, None, None, fake, 1 << 30,
                                  None) == -1
+
+
+def test_variant_entry_points_reject_bad_arguments_without_gpu():
+    L = pkg.lib()
+    assert L.adg_order_workspace_bytes(-1, 0) == 0
+    assert L.adg_order_workspace_bytes(1000, 10_000) > L.adg_workspace_bytes(1000, 10_000)
+    fake = 1 << 20
+    csr = pkg._Csr(5, 8, fake, fake)
+    ws = L.adg_workspace_bytes(5, 8)
+    # unknown variant bits
+    assert L.color_graph_ex(ctypes.byref(csr), 1, 10, 0, 4, fake, None, None, None, fake, ws, None) == -1
+    assert L.adg_order_ex(ctypes.byref(csr), 1, 10, 0, 8, fake, None, None, fake, ws, None) == -1
+    # a pos output needs the larger workspace
+    assert L.adg_order_ex(ctypes.byref(csr), 1, 10, 0, 1, fake, fake, None, fake, ws, None) == -2
+    assert L.adg_order_ex(None, 1, 10, 0, 1, fake, fake, None, fake, ws, None) == -1
