@@ -37,6 +37,8 @@ def _load():
         lib.or_pred_counts.argtypes = [i64, vp, vp, vp, u64, vp]
         lib.or_adg_ex.restype = i64
         lib.or_adg_ex.argtypes = [i64, vp, vp, i64, i64, u64, ctypes.c_uint32, vp, vp, vp]
+        lib.or_dec_itr.restype = i64
+        lib.or_dec_itr.argtypes = [i64, vp, vp, vp, u64, vp, vp, vp]
         lib.or_jp_total.restype = i64
         lib.or_jp_total.argtypes = [i64, vp, vp, vp, vp]
         lib.or_degeneracy.restype = i64
@@ -164,3 +166,26 @@ def color_graph_ex(row_ptr, col, eps_num, eps_den, seed, flags):
     rnd, pos, L, st = adg_ex(row_ptr, col, eps_num, eps_den, seed, flags)
     color, k = jp_total(row_ptr, col, pos)
     return color, k, rnd, L, pos, st
+
+
+def dec_itr(row_ptr, col, rho, seed):
+    """DEC-ADG-ITR's colouring of the ADG partitions rho (or_dec_itr).
+    Returns (color int32[n], num_colors, step int64[n], iterations)."""
+    rp, c, n = _csr(row_ptr, col)
+    r = np.ascontiguousarray(rho, dtype=np.int32)
+    color = np.zeros(max(n, 1), dtype=np.int32)
+    step = np.zeros(max(n, 1), dtype=np.int64)
+    st = np.zeros(2, dtype=np.int64)
+    k = _load().or_dec_itr(n, rp.ctypes.data, c.ctypes.data, r.ctypes.data, int(seed) & (2**64 - 1),
+                           color.ctypes.data, step.ctypes.data, st.ctypes.data)
+    if k < 0:
+        raise ValueError("or_dec_itr failed")
+    return color[:n], int(k), step[:n], int(st[0])
+
+
+def color_graph_dec(row_ptr, col, eps_num, eps_den, seed):
+    """DEC-ADG-ITR end to end: ADG (Algorithm 1), then dec_itr.  Returns
+    (color, num_colors, round, L, step, iterations)."""
+    rho, L, _ = adg(row_ptr, col, eps_num, eps_den)
+    color, k, step, it = dec_itr(row_ptr, col, rho, seed)
+    return color, k, rho, L, step, it

@@ -483,3 +483,137 @@ int64_t or_degeneracy(int64_t n, const int64_t* row_ptr, const int32_t* col) {
   free(deg); free(head); free(next); free(prev); free(gone);
   return d_out;
 }
+
+/* ---- DEC-ADG-ITR (section "Enhancing Existing Coloring Algorithms") -------
+ *
+ * DEC-ADG's outer loop (the DEC-ADG listing): the ADG partitions
+ * R(l) = {v : rho_ADG(v) = l} are coloured from the highest l down to 1.
+ * Before partition l, B_v (the colours v may not take) receives the colours
+ * of v's neighbours in the partitions already coloured.  The partition is
+ * then coloured by SIM-COL (the SIM-COL listing) with ITR's choice: in every
+ * iteration each uncoloured v of the partition takes the smallest colour not
+ * in B_v (Part 1); v gives it up when a neighbour still uncoloured in the
+ * partition took the same colour (Part 2) -- reading: only the endpoint with
+ * the smaller rho_R gives it up, since with a deterministic choice both
+ * giving up could repeat forever (two adjacent vertices with equal B_v); the
+ * vertices that keep a colour are coloured and their colours enter the B_u
+ * of their still-uncoloured neighbours in the partition (Part 3).
+ * Iterations are synchronous: every Part reads the state the previous Part
+ * left.  B_v has bits for colours 1 .. deg(v) + 1 (v never has more than
+ * deg(v) coloured neighbours).
+ * Writes colours (>= 1), the global iteration at which each vertex was
+ * coloured (1-based, increasing over the partitions) and returns the number
+ * of colours; stats_out[0] = iterations.  Returns -1 on bad input. */
+int64_t or_dec_itr(int64_t n, const int64_t* row_ptr, const int32_t* col, const int32_t* rho, uint64_t seed,
+                   int32_t* color_out, int64_t* step_out, int64_t* stats_out) {
+  if (n < 0) return -1;
+  if (n == 0) {
+    if (stats_out) stats_out[0] = 0;
+    return 0;
+  }
+  int64_t L = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    if (rho[v] < 1) return -1;
+    if (rho[v] > L) L = rho[v];
+  }
+  int64_t* boff = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+  int64_t* start = (int64_t*)calloc((size_t)(L + 2), sizeof(int64_t));
+  int64_t* part = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  int64_t* U = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  int32_t* T = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  char* inU = (char*)calloc((size_t)n, 1);
+  char* lose = (char*)calloc((size_t)n, 1);
+  if (!boff || !start || !part || !U || !T || !inU || !lose) {
+    free(boff); free(start); free(part); free(U); free(T); free(inU); free(lose);
+    return -1;
+  }
+  boff[0] = 0;
+  for (int64_t v = 0; v < n; ++v) boff[v + 1] = boff[v] + (row_ptr[v + 1] - row_ptr[v] + 1 + 63) / 64;
+  uint64_t* B = (uint64_t*)calloc((size_t)(boff[n] ? boff[n] : 1), sizeof(uint64_t));
+  if (!B) {
+    free(boff); free(start); free(part); free(U); free(T); free(inU); free(lose);
+    return -1;
+  }
+  /* the partitions, as lists (counting sort by rho) */
+  for (int64_t v = 0; v < n; ++v) start[rho[v] + 1] += 1;
+  for (int64_t l = 1; l <= L + 1; ++l) start[l] += start[l - 1];
+  {
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(L + 1));
+    if (!fill) {
+      free(B); free(boff); free(start); free(part); free(U); free(T); free(inU); free(lose);
+      return -1;
+    }
+    for (int64_t l = 0; l <= L; ++l) fill[l] = start[l];
+    for (int64_t v = 0; v < n; ++v) part[fill[rho[v]]++] = v;
+    free(fill);
+  }
+  for (int64_t v = 0; v < n; ++v) color_out[v] = 0;
+  int64_t step = 0, num_colors = 0;
+  for (int64_t l = L; l >= 1; --l) {
+    int64_t sizeU = 0;
+    for (int64_t i = start[l]; i < start[l + 1]; ++i) U[sizeU++] = part[i];
+    /* B_v gets the colours of v's neighbours in the partitions coloured so far */
+    for (int64_t i = 0; i < sizeU; ++i) {
+      int64_t v = U[i];
+      for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+        int64_t u = col[e];
+        if (rho[u] > l) {
+          int64_t c = color_out[u];
+          B[boff[v] + (c - 1) / 64] |= 1ull << ((c - 1) % 64);
+        }
+      }
+    }
+    while (sizeU > 0) {
+      step += 1;
+      for (int64_t i = 0; i < sizeU; ++i) inU[U[i]] = 1;
+      /* Part 1: the smallest colour not in B_v */
+      for (int64_t i = 0; i < sizeU; ++i) {
+        int64_t v = U[i];
+        int64_t c = 1;
+        while (B[boff[v] + (c - 1) / 64] >> ((c - 1) % 64) & 1) ++c;
+        T[v] = (int32_t)c;
+      }
+      /* Part 2: conflicts with neighbours in U (the smaller rho_R gives up) */
+      for (int64_t i = 0; i < sizeU; ++i) {
+        int64_t v = U[i];
+        uint32_t hv = or_tiebreak(seed, (uint32_t)v);
+        lose[v] = 0;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+          int64_t u = col[e];
+          if (inU[u] && T[u] == T[v] && or_tiebreak(seed, (uint32_t)u) > hv) lose[v] = 1;
+        }
+        int64_t c = T[v];
+        if (B[boff[v] + (c - 1) / 64] >> ((c - 1) % 64) & 1) lose[v] = 1;
+      }
+      for (int64_t i = 0; i < sizeU; ++i) {
+        int64_t v = U[i];
+        if (!lose[v]) {
+          color_out[v] = T[v];
+          step_out[v] = step;
+          if (T[v] > num_colors) num_colors = T[v];
+        }
+      }
+      /* Part 3: colours fixed in this iteration enter the B of the others in U */
+      for (int64_t i = 0; i < sizeU; ++i) {
+        int64_t v = U[i];
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+          int64_t u = col[e];
+          if (inU[u] && color_out[u] > 0) {
+            int64_t c = color_out[u];
+            B[boff[v] + (c - 1) / 64] |= 1ull << ((c - 1) % 64);
+          }
+        }
+      }
+      /* U = U \ {coloured} */
+      int64_t k = 0;
+      for (int64_t i = 0; i < sizeU; ++i) {
+        inU[U[i]] = 0;
+        if (color_out[U[i]] == 0) U[k++] = U[i];
+      }
+      sizeU = k;
+    }
+  }
+  if (stats_out) stats_out[0] = step;
+  free(B); free(boff); free(start); free(part); free(U); free(T); free(inU); free(lose);
+  return num_colors;
+}

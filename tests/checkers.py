@@ -224,3 +224,63 @@ def check_adg_variant(row_ptr, col, p, q, seed, flags, rnd, pos, L):
     rank[order] = np.arange(n)
     assert np.array_equal(rank, pos), "order inside the rounds"
     return dsel
+
+
+def _mex(colors):
+    s = set(int(c) for c in colors)
+    c = 1
+    while c in s:
+        c += 1
+    return c
+
+
+def check_dec_itr(row_ptr, col, rho, seed, color, step):
+    """DEC-ADG-ITR's output characterised iteration by iteration (not
+    simulated): with step(v) the iteration that coloured v,
+    * the colouring is proper and partitions are coloured from the highest
+      rho down, each over a contiguous range of iterations;
+    * at iteration s every uncoloured v of the running partition tries
+      t_s(v) = the smallest colour missing among its neighbours coloured
+      before s (B_v), and color(v) = t_{step(v)}(v);
+    * v is not coloured at s < step(v) exactly when some neighbour u of the
+      same partition, still uncoloured at s, tried the same colour and has a
+      larger rho_R (and at step(v) no such neighbour exists).
+    Small graphs only (Python loops)."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    rho = np.asarray(rho, dtype=np.int64)
+    color = np.asarray(color, dtype=np.int64)
+    step = np.asarray(step, dtype=np.int64)
+    n = row_ptr.size - 1
+    if n == 0:
+        return
+    assert color.min() >= 1 and step.min() >= 1
+    src = _src(row_ptr)
+    assert not np.any(color[src] == color[col]), "improper colouring"
+    h = tiebreak_np(seed, n).astype(np.int64)
+    nb = [col[row_ptr[v]:row_ptr[v + 1]] for v in range(n)]
+    # partitions in decreasing rho, over contiguous iteration ranges
+    L = int(rho.max())
+    prev_last = 0
+    first = {}
+    for l in range(L, 0, -1):
+        vs = np.flatnonzero(rho == l)
+        if vs.size == 0:
+            continue
+        lo, hi = int(step[vs].min()), int(step[vs].max())
+        assert lo == prev_last + 1, "partition %d does not start right after the previous one" % l
+        first[l] = lo
+        prev_last = hi
+        for s in range(lo, hi + 1):
+            assert np.any(step[vs] == s), "iteration %d colours nothing" % s
+
+    def tried(v, s):
+        return _mex(color[u] for u in nb[v] if step[u] < s)
+
+    for v in range(n):
+        l = int(rho[v])
+        assert tried(v, step[v]) == color[v], "vertex %d: not the smallest free colour" % v
+        for s in range(first[l], int(step[v]) + 1):
+            tv = tried(v, s)
+            beaten = any(rho[u] == l and step[u] >= s and h[u] > h[v] and tried(u, s) == tv for u in nb[v])
+            assert beaten == (s < step[v]), "vertex %d at iteration %d" % (v, s)

@@ -17,7 +17,10 @@ mathematics fix, never against itself or the GPU path.
 * the variants ADG-O (sorted R, the ADG-O listing) and ADG-M (median, the
   section on the degree median): definition checks per round, ADG-M's round
   count (halving), ADG-O's full 2(1+eps)-approximate order, ADG-M's partial
-  4-approximate order and 4d + 1 colours, hand-worked small cases.
+  4-approximate order and 4d + 1 colours, hand-worked small cases;
+* DEC-ADG-ITR (section "Enhancing Existing Coloring Algorithms"): its
+  iterations characterised vertex by vertex (check_dec_itr), the colour
+  bound 2(1+eps)d + 1, hand-worked K_2, K_n, edgeless and K_{a,b}.
 """
 import itertools
 import math
@@ -27,8 +30,9 @@ import pytest
 
 import graphgen
 import oracle
-from checkers import (MEDIAN, SORTED, brute_degeneracy, check_adg, check_adg_variant, check_jp, check_jp_order,
-                      edges_to_csr, fmix32_np, pred_count, priority_keys, splitmix64_first, tiebreak_np)
+from checkers import (MEDIAN, SORTED, brute_degeneracy, check_adg, check_adg_variant, check_dec_itr, check_jp,
+                      check_jp_order, edges_to_csr, fmix32_np, pred_count, priority_keys, splitmix64_first,
+                      tiebreak_np)
 
 EPS = [(0, 1), (1, 100), (1, 10), (1, 2), (1, 1), (10**6, 1)]
 
@@ -425,3 +429,78 @@ def test_median_complete_graph():
     assert L == 4
     color, k = oracle.jp_total(rp, col, pos)
     assert k == n and np.array_equal(np.argsort(-pos), np.argsort(color))
+
+
+# ---------------------------------------------------------------- DEC-ADG-ITR
+
+def _dec_bounds(rp, col, p, q, seed):
+    color, k, rho, L, step, it = oracle.color_graph_dec(rp, col, p, q, seed)
+    n = rp.size - 1
+    check_dec_itr(rp, col, rho, seed, color, step)
+    assert k == (color.max() if n else 0)
+    assert it == (step.max() if n else 0)
+    if n:
+        d = oracle.degeneracy(rp, col)
+        # each vertex has at most 2(1+eps)d neighbours coloured before it
+        assert k <= (q + p) * 2 * d // q + 1
+    return color, k, rho, L, step, it
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 4, 5])
+def test_dec_itr_all_graphs_up_to_5_vertices(n):
+    pairs = [(u, v) for u in range(n) for v in range(u + 1, n)]
+    for mask in range(1 << len(pairs)):
+        edges = [pairs[i] for i in range(len(pairs)) if mask >> i & 1]
+        rp, col = edges_to_csr(n, edges)
+        for (p, q) in [(0, 1), (1, 10), (10**6, 1)]:
+            _dec_bounds(rp, col, p, q, mask)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_dec_itr_random_graphs(seed):
+    rng = np.random.default_rng(700 + seed)
+    for trial in range(4):
+        n = int(rng.integers(20, 200))
+        if trial % 2:
+            rp, col = graphgen.chung_lu(n, float(rng.uniform(2, 12)), 2.3, seed * 10 + trial)
+        else:
+            rp, col = graphgen.erdos_renyi(n, float(rng.uniform(0.02, 0.3)), seed * 10 + trial)
+        for (p, q) in [(0, 1), (1, 10), (1, 2)]:
+            _dec_bounds(rp, col, p, q, trial)
+
+
+def test_dec_itr_k2_by_hand():
+    """One partition {0, 1}: both try colour 1, the larger rho_R keeps it;
+    the other takes colour 2 in the second iteration."""
+    rp, col = edges_to_csr(2, [(0, 1)])
+    for seed in range(6):
+        h = tiebreak_np(seed, 2)
+        win = 0 if h[0] > h[1] else 1
+        color, k, step, it = oracle.dec_itr(rp, col, np.ones(2, np.int32), seed)
+        assert it == 2 and k == 2
+        assert color[win] == 1 and step[win] == 1 and color[1 - win] == 2 and step[1 - win] == 2
+
+
+def test_dec_itr_complete_graph_by_hash_rank():
+    """K_n in one partition: iteration i colours the vertex of i-th largest
+    rho_R with colour i."""
+    n = 9
+    rp, col = edges_to_csr(n, [(u, v) for u in range(n) for v in range(u + 1, n)])
+    seed = 4
+    color, k, step, it = oracle.dec_itr(rp, col, np.ones(n, np.int32), seed)
+    rank = np.argsort(np.argsort(-tiebreak_np(seed, n).astype(np.int64))) + 1
+    assert k == n and it == n and np.array_equal(color, rank) and np.array_equal(step, rank)
+
+
+def test_dec_itr_edgeless_and_bipartite():
+    rp, col = edges_to_csr(7, [])
+    color, k, rho, L, step, it = oracle.color_graph_dec(rp, col, 1, 10, 1)
+    assert k == 1 and it == 1 and np.all(color == 1)
+    # K_{3,8}: ADG removes the larger side first, so the smaller side (a
+    # higher partition) is coloured first, with colour 1, in one iteration;
+    # the larger side then takes colour 2 in one iteration
+    a, b = 3, 8
+    rp, col = edges_to_csr(a + b, [(i, a + j) for i in range(a) for j in range(b)])
+    color, k, rho, L, step, it = oracle.color_graph_dec(rp, col, 0, 1, 2)
+    assert L == 2 and k == 2 and it == 2
+    assert np.all(color[:a] == 1) and np.all(color[a:] == 2)
