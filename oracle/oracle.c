@@ -500,7 +500,9 @@ int64_t or_degeneracy(int64_t n, const int64_t* row_ptr, const int32_t* col) {
  * of their still-uncoloured neighbours in the partition (Part 3).
  * Iterations are synchronous: every Part reads the state the previous Part
  * left.  B_v has bits for colours 1 .. deg(v) + 1 (v never has more than
- * deg(v) coloured neighbours).
+ * deg(v) coloured neighbours, so its smallest free colour is at most
+ * deg(v) + 1 and larger colours of its neighbours cannot matter; they are
+ * not recorded).
  * Writes colours (>= 1), the global iteration at which each vertex was
  * coloured (1-based, increasing over the partitions) and returns the number
  * of colours; stats_out[0] = iterations.  Returns -1 on bad input. */
@@ -559,7 +561,7 @@ int64_t or_dec_itr(int64_t n, const int64_t* row_ptr, const int32_t* col, const 
         int64_t u = col[e];
         if (rho[u] > l) {
           int64_t c = color_out[u];
-          B[boff[v] + (c - 1) / 64] |= 1ull << ((c - 1) % 64);
+          if (c <= row_ptr[v + 1] - row_ptr[v] + 1) B[boff[v] + (c - 1) / 64] |= 1ull << ((c - 1) % 64);
         }
       }
     }
@@ -600,7 +602,7 @@ int64_t or_dec_itr(int64_t n, const int64_t* row_ptr, const int32_t* col, const 
           int64_t u = col[e];
           if (inU[u] && color_out[u] > 0) {
             int64_t c = color_out[u];
-            B[boff[v] + (c - 1) / 64] |= 1ull << ((c - 1) % 64);
+            if (c <= row_ptr[v + 1] - row_ptr[v] + 1) B[boff[v] + (c - 1) / 64] |= 1ull << ((c - 1) % 64);
           }
         }
       }

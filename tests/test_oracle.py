@@ -504,3 +504,23 @@ def test_dec_itr_edgeless_and_bipartite():
     color, k, rho, L, step, it = oracle.color_graph_dec(rp, col, 0, 1, 2)
     assert L == 2 and k == 2 and it == 2
     assert np.all(color[:a] == 1) and np.all(color[a:] == 2)
+
+
+def test_dec_itr_colours_beyond_small_bitmaps():
+    """K_70 coloured first (colours 1..70), then pendant vertices of degree
+    1 and 2 hanging off it: a pendant's bitmap holds a few colours only, and
+    its neighbours' large colours must neither count nor spill into other
+    vertices' bitmaps."""
+    k = 70
+    edges = [(u, v) for u in range(k) for v in range(u + 1, k)]
+    n = k
+    for i in range(k):
+        edges.append((i, n))            # a pendant of degree 1
+        edges.append((i, n + 1))        # and one of degree 2
+        edges.append(((i + 1) % k, n + 1))
+        n += 2
+    rp, col = edges_to_csr(n, edges)
+    color, kk, rho, L, step, it = oracle.color_graph_dec(rp, col, 0, 1, 5)
+    check_dec_itr(rp, col, rho, 5, color, step)
+    assert kk == k
+    assert np.all(color[k:] <= 3)
