@@ -127,7 +127,10 @@ def cpu_baseline_graph(w, rp, col, m, variant=0):
         m = col.size // 2
         sample = "R-MAT scale %d, same generator parameters and seed (m = %d)" % (w["cpu_sample_scale"], m)
     t0 = time.perf_counter()
-    if variant:
+    if variant & 4:
+        oracle.color_graph_dec(rp, col, w["eps"][0], w["eps"][1], w["seed"], variant & 3)
+        what = "ADG then DEC-ADG-ITR"
+    elif variant:
         oracle.color_graph_ex(rp, col, w["eps"][0], w["eps"][1], w["seed"], variant)
         what = "ADG variant %d then greedy JP" % variant
     else:
@@ -196,7 +199,7 @@ def run_single(args, w):
     torch.cuda.synchronize()
     log("warm-up done")
     adg.profile_read()  # drop anything recorded so far
-    adg.profile_enable(["update", "update_huge", "jp", "jp_narrow"])
+    adg.profile_enable(["update", "update_huge", "jp", "jp_narrow", "dec_itr"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -211,12 +214,14 @@ def run_single(args, w):
     # dominant kernel class: largest share of the timed region.  JP runs as
     # single-block steps (jp_narrow) and grid-wide steps (jp); its algorithmic
     # bytes are charged to the two together.
-    jp_ms = prof.get("jp", (0, 0))[0] + prof.get("jp_narrow", (0, 0))[0]
-    jp_launches = prof.get("jp", (0, 0))[1] + prof.get("jp_narrow", (0, 0))[1]
+    # (DEC-ADG-ITR's triples of pull, pick and resolve take JP's place)
+    jp_ms = prof.get("jp", (0, 0))[0] + prof.get("jp_narrow", (0, 0))[0] + prof.get("dec_itr", (0, 0))[0]
+    jp_launches = prof.get("jp", (0, 0))[1] + prof.get("jp_narrow", (0, 0))[1] + prof.get("dec_itr", (0, 0))[1]
     upd_ms = prof.get("update", (0.0, 0))[0] + prof.get("update_huge", (0.0, 0))[0]
     upd_launches = prof.get("update", (0.0, 0))[1]
     if jp_ms >= upd_ms:
-        dom, tot_ms, launches, kname = "jp", jp_ms, jp_launches, "k_jp_narrow+k_jp_grid"
+        dom, tot_ms, launches, kname = "jp", jp_ms, jp_launches, (
+            "k_dec_pull+k_dec_pick+k_dec_resolve" if variant & 4 else "k_jp_narrow+k_jp_grid")
     else:
         dom, tot_ms, launches, kname = "update", upd_ms, upd_launches, "k_update"
     roofline = roofline_record(dom, tot_ms, launches, args.steps, algorithmic_bytes(dom, n, nnz, st), kname,
@@ -420,7 +425,7 @@ def run_serving(args, w):
 
 
 # ADG variant bits of color_graph_ex (0 = Algorithm 1)
-VARIANTS = {"adg": 0, "sorted": 1, "median": 2, "sorted_median": 3}
+VARIANTS = {"adg": 0, "sorted": 1, "median": 2, "sorted_median": 3, "dec": 4, "dec_median": 6}
 
 
 def main():
@@ -431,7 +436,7 @@ def main():
     ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", default="adg", choices=sorted(VARIANTS),
-                    help="single-graph workloads: adg = Algorithm 1 (default), sorted = ADG-O, median = ADG-M")
+                    help="single-graph workloads: adg = JP-ADG (default), sorted = JP-ADG-O, median = JP-ADG-M, dec = DEC-ADG-ITR")
     ap.add_argument("--breakdown", action="store_true", help="print per-kernel-class times to stderr")
     ap.add_argument("--calib-mib", type=int, default=256,
                     help="size of a plain device copy issued before the run, so that profiler byte counters "

@@ -63,7 +63,7 @@ enum {
   ADG_ERR_WORKSPACE = -2,   /* workspace missing, misaligned or too small */
   ADG_ERR_HIP = -3,         /* a HIP runtime call failed */
   ADG_ERR_INTERNAL = -4,    /* round-count watchdog tripped or device-side check failed */
-  ADG_ERR_UNSUPPORTED = -5  /* input outside the supported range: nnz / 64 + 2 n >= 2^32 for the
+  ADG_ERR_UNSUPPORTED = -5  /* input outside the supported range: nnz / 32 + 2 n >= 2^32 for the
                                single-graph calls; a serving request larger than the arena */
 };
 
@@ -82,7 +82,8 @@ typedef struct adg_stats {
   int64_t sum_active;      /* sum over rounds of |U_l| */
   int64_t cut_edges;       /* decrements that hit a vertex staying in U */
   int64_t frontier;        /* vertices that started a JP level (all preds done) */
-  int64_t jp_levels;       /* JP levels processed, summed over rounds */
+  int64_t jp_levels;       /* JP levels processed, summed over rounds; with
+                              ADG_VARIANT_DEC_ITR the DEC-ADG-ITR iterations */
   int64_t error;           /* device-side error flag (0 = none) */
 } adg_stats_t;
 
@@ -131,9 +132,19 @@ int color_graph(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_t s
  *       so the limit always decides and eps has no effect.  L is the bit
  *       length of n; JP-ADG-M uses at most 4d + 1 colours.  The tie-break
  *       seed decides which vertices of equal D fall in the lower half.
- * Both may be combined.  variant = 0 is Algorithm 1 (adg_order,
- * color_graph).  Other bits: ADG_ERR_ARG. */
-enum { ADG_VARIANT_SORTED = 1, ADG_VARIANT_MEDIAN = 2 };
+ *   ADG_VARIANT_DEC_ITR  (color_graph_ex only) colour by DEC-ADG-ITR (section
+ *       "Enhancing Existing Coloring Algorithms") instead of JP: the ADG
+ *       partitions R(L), ..., R(1) are coloured one after the other (the
+ *       DEC-ADG listing's outer loop); inside R(l), synchronous iterations
+ *       of the SIM-COL listing where every uncoloured vertex tries the
+ *       smallest colour not used by its coloured neighbours, keeps it
+ *       unless an uncoloured neighbour of R(l) with a larger rho_R tried
+ *       the same colour, and the kept colours are final.  Deterministic for
+ *       a given seed; at most 2(1+eps)d + 1 colours.  May be combined with
+ *       ADG_VARIANT_MEDIAN, not with ADG_VARIANT_SORTED.
+ * SORTED and MEDIAN may be combined.  variant = 0 is Algorithm 1 (adg_order,
+ * color_graph).  Other bits or combinations: ADG_ERR_ARG. */
+enum { ADG_VARIANT_SORTED = 1, ADG_VARIANT_MEDIAN = 2, ADG_VARIANT_DEC_ITR = 4 };
 
 /* Workspace bytes for adg_order_ex with a pos output (adg_workspace_bytes
  * plus sort buffers of 24 n bytes); 0 for invalid sizes. */

@@ -47,11 +47,12 @@ class _Profile(ctypes.Structure):
 
 
 KERNEL_CLASSES = ["init", "stats", "count", "scan", "scatter", "update", "part1", "jp_prep", "jp", "finish",
-                  "batched", "jp_narrow", "update_huge", "median_select", "order_sort"]
+                  "batched", "jp_narrow", "update_huge", "median_select", "order_sort", "dec_itr"]
 
 # ADG variants (bit set): ADG-O's sorted rounds and ADG-M's median selection
 SORTED = 1
 MEDIAN = 2
+DEC_ITR = 4   # colouring by DEC-ADG-ITR instead of JP (color_graph_ex only)
 
 _lib = None
 
@@ -233,7 +234,8 @@ def adg_order_ex(g, eps_num, eps_den, seed, variant, want_pos=True, workspace=No
 
 
 def color_graph_ex(g, eps_num, eps_den, seed, variant, workspace=None, stream=None, want_rounds=True):
-    """JP-ADG with a variant (SORTED = JP-ADG-O, MEDIAN = JP-ADG-M).  Returns
+    """JP-ADG with a variant (SORTED = JP-ADG-O, MEDIAN = JP-ADG-M; DEC_ITR =
+    DEC-ADG-ITR's colouring instead of JP, alone or with MEDIAN).  Returns
     (color, num_colors, round or None, num_rounds) as GPU tensors."""
     torch = _torch()
     ws = _workspace(g, workspace)

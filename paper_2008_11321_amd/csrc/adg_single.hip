@@ -43,6 +43,12 @@
 //     many, so the cap of half of U decides R; k_msel finds the
 //     ceil(|U|/2)-th smallest 64-bit key (D << 32 | rho_R) by radix selection
 //     and the selection kernels compare against it.
+//   DEC-ADG-ITR ("Enhancing Existing Coloring Algorithms"): instead of JP, the
+//     ADG partitions are coloured from the highest round down; inside a
+//     partition, synchronous iterations let every uncoloured vertex try the
+//     smallest colour free in its bitmap, keep it unless a same-round
+//     predecessor (larger hash) tried the same colour, and push kept colours
+//     to its same-round neighbours' bitmaps (k_dec_*).
 
 #include <hip/hip_runtime.h>
 
@@ -101,6 +107,19 @@ struct JpState {
   unsigned long long ssum[3];  // same-round successors summed over each level's vertices
 };
 
+// DEC-ADG-ITR progress (between kernels).
+struct DecState {
+  int round;                   // partition being coloured (L .. 1)
+  int first;                   // its first iteration: U is the partition's ORD slot
+  int pull;                    // the partition still has to pull its later-round colours
+  int cur;                     // U of later iterations: UL[cur]
+  unsigned ucnt;               // |U|
+  unsigned unext;              // vertices that gave up their colour (the next U)
+  unsigned blocks;             // blocks of k_dec_resolve done (last-block hand-off)
+  int done;
+  long long iters;             // iterations run, all partitions
+};
+
 // Device-resident control block (one per workspace).
 struct Ctrl {
   // ADG round state
@@ -133,6 +152,7 @@ struct Ctrl {
   unsigned int msel_blocks;    // blocks of the current pass that have added their histogram
   int msel_found;
   JpState js;
+  DecState dec;
 };
 
 struct Params {
@@ -147,6 +167,8 @@ struct Params {
   int ord_identity;            // ORD is the identity (one pseudo-round: jp_color)
   int sorted;                  // ADG-O: same-round order by (D at selection, rho_R)
   int median;                  // ADG-M: R = the lower half of U by (D, rho_R)
+  int dec;                     // DEC-ADG-ITR colours the partitions (bitmaps for all same-round neighbours)
+  unsigned* tent;              // DEC-ADG-ITR: colour each vertex tried in its latest iteration
   unsigned* mhist;             // [MSEL_BINS] radix selection histogram
   Ctrl* ctrl;
   int* round;                  // rho_ADG (user output or workspace)
@@ -244,6 +266,10 @@ __global__ void k_init(Params P) {
   c->msel_prefix = c->msel_mask = c->msel_k = 0;
   c->msel_blocks = 0;
   c->msel_found = 0;
+  c->dec.done = 0;
+  c->dec.iters = 0;
+  c->dec.blocks = 0;
+  c->dec.unext = 0;
   JpState& j = c->js;
   j.round = 0;
   j.level = 0;
@@ -654,7 +680,9 @@ __device__ __forceinline__ T wave_excl_scan(T x, T* total) {
 // to be coloured (cnt = nps), and a cleared colour bitmap from the bump
 // allocator; rec[v] = (bitmap offset << 32) | np.
 __device__ __forceinline__ void jp_row(const Params& P, bool has, int v, long long np, long long ns, long long nps) {
-  const unsigned w = has ? bm_words((int)np) : 0;
+  // JP: bits for colours 1 .. np+2; DEC-ADG-ITR: also the same-round successors
+  const long long nb = P.dec ? np + ns : np;
+  const unsigned w = has ? bm_words((int)nb) : 0;
   unsigned tot;
   const unsigned pre = wave_excl_scan<unsigned>(w, &tot);
   unsigned long long base = 0;
@@ -666,13 +694,15 @@ __device__ __forceinline__ void jp_row(const Params& P, bool has, int v, long lo
     atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
     off = 0;
     np = 0;
+    ns = 0;
+    nps = 0;
   } else {
     for (unsigned k = 0; k < w; ++k) P.B[off + k] = 0;
   }
   P.npred[v] = (int)np;
   P.nsr[v] = (int)ns;
   P.cnt[v] = (int)nps;
-  P.rec[v] = (off << 32) | (unsigned)np;
+  P.rec[v] = (off << 32) | (unsigned)(P.dec ? np + ns : np);
 }
 
 // Wavefront: append the lanes' vertices with z set to the first JP level of
@@ -1872,6 +1902,178 @@ __global__ void k_jp_start(Params P, int rounds) {
 }
 
 // Largest colour: per-block maxima, one atomic per block.
+// ================================================================ DEC-ADG-ITR
+
+__device__ __forceinline__ const int* dec_list(const Params& P, const DecState& d) {
+  return d.first ? P.ORD + ((long long)P.n - P.roundN[d.round]) : P.UL[d.cur];
+}
+
+__global__ void k_dec_start(Params P, int rounds) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  DecState& d = P.ctrl->dec;
+  d.round = rounds;
+  d.first = 1;
+  d.pull = 1;
+  d.cur = 0;
+  d.ucnt = rounds > 0 ? P.roundN[rounds] - P.roundN[rounds + 1] : 0;
+  d.unext = 0;
+  d.blocks = 0;
+  d.done = rounds == 0;
+  d.iters = 0;
+}
+
+// Before a partition's first iteration: OR the colours of every neighbour in
+// a later round (all final) into the vertex's bitmap.
+__global__ __launch_bounds__(BS) void k_dec_pull(Params P) {
+  const DecState d = P.ctrl->dec;
+  if (d.done || !d.pull) return;
+  const int* U = dec_list(P, d);
+  const long long stride = (long long)gridDim.x * BS;
+  for (long long t = (long long)blockIdx.x * BS; t < d.ucnt; t += stride) {
+    const long long i = t + threadIdx.x;
+    const bool has = i < d.ucnt;
+    const int v = has ? U[i] : 0;
+    long long b = 0, e = 0;
+    unsigned long long rec = 0;
+    if (has) {
+      b = P.rp[v];
+      e = b + (P.npred[v] - P.cnt[v]);
+      rec = P.rec[v];
+    }
+    // the wavefront walks long rows together; each entry marks in its row's bitmap
+    const bool longrow = has && e - b > WAVE;
+    if (has && !longrow)
+      for (long long j = b; j < e; ++j) bm_mark<SC_AGENT>(P, rec, P.color[P.dag[j]]);
+    uint64_t m = ballot(longrow);
+    while (m) {
+      const int src = __ffsll((long long)m) - 1;
+      m &= m - 1;
+      const long long bb = readlane_i64(b, src), ee = readlane_i64(e, src);
+      const unsigned long long rr = readlane_u64(rec, src);
+      for (long long j = bb + lane_id(); j < ee; j += WAVE) bm_mark<SC_AGENT>(P, rr, P.color[P.dag[j]]);
+    }
+  }
+}
+
+// Part 1: every vertex of U tries the smallest colour not in its bitmap.
+__global__ __launch_bounds__(BS) void k_dec_pick(Params P) {
+  const DecState d = P.ctrl->dec;
+  if (d.done) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) P.ctrl->dec.pull = 0;
+  const int* U = dec_list(P, d);
+  for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < d.ucnt; i += (long long)gridDim.x * BS) {
+    const int v = U[i];
+    const unsigned long long rec = P.rec[v];
+    const unsigned nw = bm_words((int)(unsigned)rec);
+    unsigned c = 0;
+    for (unsigned w = 0; w < nw; ++w) {
+      const unsigned wd = bm_load(P, (rec >> 32) + w);
+      if (wd != ~0u) {
+        c = 32 * w + (unsigned)__builtin_ctz(~wd) + 1;
+        break;
+      }
+    }
+    // a vertex never has more coloured neighbours than its bitmap has bits
+    if (c == 0) {
+      atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
+      c = 32 * nw + 1;
+    }
+    P.tent[v] = c;
+  }
+}
+
+// Parts 2 and 3: a vertex keeps its colour unless a same-round predecessor
+// (a same-round neighbour with a larger hash) tried the same one; kept
+// colours go into the bitmaps of the same-round neighbours, the others form
+// the next U.  The last block moves to the next iteration or partition.
+__global__ __launch_bounds__(BS) void k_dec_resolve(Params P) {
+  Ctrl* c = P.ctrl;
+  const DecState d = c->dec;
+  if (d.done) return;
+  const int* U = dec_list(P, d);
+  int* Unext = P.UL[d.cur ^ 1];
+  __shared__ int last;
+  const long long stride = (long long)gridDim.x * BS;
+  for (long long t = (long long)blockIdx.x * BS; t < d.ucnt; t += stride) {
+    const long long i = t + threadIdx.x;
+    const bool has = i < d.ucnt;
+    int v = 0;
+    unsigned tv = 0;
+    long long b = 0, e = 0, e2 = 0;
+    if (has) {
+      v = U[i];
+      tv = P.tent[v];
+      const int nps = P.cnt[v];
+      b = P.rp[v] + (P.npred[v] - nps);   // same-round predecessors: [b, e)
+      e = b + nps;
+      e2 = e + P.nsr[v];                  // and successors: [e, e2)
+    }
+    // Part 2: any same-round predecessor with the same tried colour?
+    bool lose = false;
+    const bool longrow = has && e - b > WAVE;
+    if (has && !longrow)
+      for (long long j = b; j < e && !lose; ++j) lose = P.tent[P.dag[j]] == tv;
+    uint64_t m = ballot(longrow);
+    while (m) {
+      const int src = __ffsll((long long)m) - 1;
+      m &= m - 1;
+      const long long bb = readlane_i64(b, src), ee = readlane_i64(e, src);
+      const unsigned ts = readlane_u(tv, src);
+      bool hit = false;
+      for (long long j = bb + lane_id(); j < ee; j += WAVE) hit |= P.tent[P.dag[j]] == ts;
+      if (ballot(hit) && lane_id() == (unsigned)src) lose = true;
+    }
+    // Part 3: a kept colour goes to the same-round neighbours
+    const bool keep = has && !lose;
+    if (keep) P.color[v] = (int)tv;
+    const long long pb = keep ? b : 0, pe = keep ? e2 : 0;
+    const bool longpush = keep && pe - pb > WAVE;
+    if (keep && !longpush)
+      for (long long j = pb; j < pe; ++j) bm_mark<SC_AGENT>(P, P.rec[P.dag[j]], (int)tv);
+    m = ballot(longpush);
+    while (m) {
+      const int src = __ffsll((long long)m) - 1;
+      m &= m - 1;
+      const long long bb = readlane_i64(pb, src), ee = readlane_i64(pe, src);
+      const int ts = (int)readlane_u(tv, src);
+      for (long long j = bb + lane_id(); j < ee; j += WAVE) bm_mark<SC_AGENT>(P, P.rec[P.dag[j]], ts);
+    }
+    // the others form the next U
+    const uint64_t lm = ballot(has && lose);
+    if (lm) {
+      const int leader = __ffsll((long long)lm) - 1;
+      unsigned at = 0;
+      if (lane_id() == (unsigned)leader) at = atomicAdd(&c->dec.unext, (unsigned)__popcll(lm));
+      at = readlane_u(at, leader);
+      if (has && lose) Unext[at + lanes_below(lm)] = v;
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0)
+    last = __hip_atomic_fetch_add(&c->dec.blocks, 1u, __ATOMIC_ACQ_REL, SC_AGENT) == gridDim.x - 1;
+  __syncthreads();
+  if (!last || threadIdx.x != 0) return;
+  __threadfence();
+  DecState& g = c->dec;
+  g.blocks = 0;
+  g.iters += 1;
+  const unsigned nx = __hip_atomic_load(&g.unext, __ATOMIC_RELAXED, SC_AGENT);
+  g.unext = 0;
+  if (nx > 0) {
+    g.ucnt = nx;
+    g.cur ^= 1;
+    g.first = 0;
+  } else if (g.round > 1) {
+    g.round -= 1;
+    g.first = 1;
+    g.pull = 1;
+    g.ucnt = P.roundN[g.round] - P.roundN[g.round + 1];
+  } else {
+    g.done = 1;
+  }
+}
+
 __global__ __launch_bounds__(BS) void k_max_color(Params P) {
   int m = 0;
   for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < P.n; i += (long long)gridDim.x * BS)
@@ -1968,7 +2170,7 @@ namespace adg {
 namespace {
 const char* kclass_names[KC_NUM] = {"init", "stats", "count", "scan", "scatter", "update", "part1",
                                     "jp_prep", "jp", "finish", "batched", "jp_narrow", "update_huge",
-                                    "median_select", "order_sort"};
+                                    "median_select", "order_sort", "dec_itr"};
 struct ProfRec {
   int cls;
   hipEvent_t a, b;
@@ -2050,8 +2252,10 @@ Layout make_layout(int64_t n, int64_t nnz) {
   L.nsr = take(4 * nn);
   L.cnt = take(4 * nn);
   L.rec = take(8 * nn);
-  // colour bitmaps: sum over v of ceil((|pred|+2)/32) <= m/32 + 33n/32 words
-  L.bm_cap = (size_t)nnz / 64 + 2 * nn + 64;
+  // colour bitmaps: sum over v of ceil((bits+2)/32) words, bits = |pred(v)|
+  // for JP (<= nnz/2 in total), all non-earlier neighbours for DEC-ADG-ITR
+  // (<= nnz): at most nnz/32 + 33n/32 words
+  L.bm_cap = (size_t)nnz / 32 + 2 * nn + 64;
   L.B = take(4 * L.bm_cap);
   L.L0 = take(4 * nn);
   L.l0n = take(4 * (nn + 4));
@@ -2098,8 +2302,8 @@ int check_graph(const adg_csr_t* g) {
   if (g->n < 0 || g->n > 0x7ffffffeLL || g->nnz < 0) return ADG_ERR_ARG;
   if (g->n > 0 && (!g->row_ptr)) return ADG_ERR_ARG;
   if (g->nnz > 0 && !g->col_idx) return ADG_ERR_ARG;
-  // JP's colour bitmaps are addressed with 32-bit word offsets
-  if ((unsigned long long)g->nnz / 64 + 2ull * (unsigned long long)g->n + 64 >= (1ull << 32)) return ADG_ERR_UNSUPPORTED;
+  // the colour bitmaps are addressed with 32-bit word offsets
+  if ((unsigned long long)g->nnz / 32 + 2ull * (unsigned long long)g->n + 64 >= (1ull << 32)) return ADG_ERR_UNSUPPORTED;
   return ADG_OK;
 }
 
@@ -2126,7 +2330,9 @@ Params make_params(const adg_csr_t* g, void* ws, uint64_t p, uint64_t q, uint64_
   P.ord_identity = 0;
   P.sorted = (variant & ADG_VARIANT_SORTED) != 0;
   P.median = (variant & ADG_VARIANT_MEDIAN) != 0;
+  P.dec = (variant & ADG_VARIANT_DEC_ITR) != 0;
   P.mhist = (unsigned*)(base + L.mhist);
+  P.tent = (unsigned*)(base + L.F0);   // JP's level lists are not used by DEC-ADG-ITR
   P.ctrl = (Ctrl*)(base + L.ctrl);
   P.round = round_buf ? round_buf : (int*)(base + L.round);
   P.D = (int*)(base + L.D);
@@ -2325,6 +2531,48 @@ int run_jp(Params& P, hipStream_t s, int rounds) {
   return ADG_OK;
 }
 
+// DEC-ADG-ITR over the partitions, issued in growing chunks of (pull, pick,
+// resolve) triples; the host reads the finish flag between chunks.  Every
+// iteration colours at least the vertex of U with the largest hash, so at
+// most n + L triples are needed.
+int run_dec(Params& P, hipStream_t s, int rounds) {
+  if (P.n == 0) return ADG_OK;
+  {
+    TIMED(KC_JP_PREP, s);
+    hipLaunchKernelGGL(k_dec_start, dim3(1), dim3(64), 0, s, P, rounds);
+  }
+  HIPCHK(hipGetLastError());
+  PinnedFlags pf;
+  int* h = pf.h;
+  if (!h) return ADG_ERR_HIP;
+  int chunk = 4;
+  long long triples = 0;
+  const long long max_triples = (long long)P.n + rounds + 8;
+  while (true) {
+    for (int k = 0; k < chunk; ++k) {
+      TIMED(KC_DEC, s);
+      hipLaunchKernelGGL(k_dec_pull, dim3(P.upd_blocks), dim3(BS), 0, s, P);
+      hipLaunchKernelGGL(k_dec_pick, dim3(P.upd_blocks), dim3(BS), 0, s, P);
+      hipLaunchKernelGGL(k_dec_resolve, dim3(P.upd_blocks), dim3(BS), 0, s, P);
+    }
+    triples += chunk;
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(&h[0], &P.ctrl->dec.done, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&h[1], &P.ctrl->error, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (h[1]) return h[1];
+    if (h[0]) break;
+    if (triples > max_triples) return ADG_ERR_INTERNAL;
+    chunk = std::min(chunk * 2, 256);
+  }
+  {
+    TIMED(KC_FINISH, s);
+    hipLaunchKernelGGL(k_max_color, dim3(1024), dim3(BS), 0, s, P);
+  }
+  HIPCHK(hipGetLastError());
+  return ADG_OK;
+}
+
 // pos[v] = rank of v in JP's order, by a stable sort of the same-round keys
 // and then of the rounds.
 int run_order(Params& P, hipStream_t s, int rounds, void* ws, int32_t* pos_out) {
@@ -2378,7 +2626,7 @@ int adg_order_ex(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_t 
   int rc = check_graph(g);
   if (rc) return rc;
   if (eps_num < 0 || eps_den < 1 || (g->n > 0 && !round_out)) return ADG_ERR_ARG;
-  if (variant & ~(uint32_t)(ADG_VARIANT_SORTED | ADG_VARIANT_MEDIAN)) return ADG_ERR_ARG;
+  if (variant & ~(uint32_t)(ADG_VARIANT_SORTED | ADG_VARIANT_MEDIAN)) return ADG_ERR_ARG;   // no colouring here
   if ((rc = check_ws(workspace, ws_bytes, g->n, g->nnz))) return rc;
   if (pos_out && ws_bytes < make_order_layout(g->n, g->nnz).total) return ADG_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
@@ -2441,13 +2689,14 @@ int color_graph_ex(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_
   int rc = check_graph(g);
   if (rc) return rc;
   if (eps_num < 0 || eps_den < 1 || (g->n > 0 && !color_out)) return ADG_ERR_ARG;
-  if (variant & ~(uint32_t)(ADG_VARIANT_SORTED | ADG_VARIANT_MEDIAN)) return ADG_ERR_ARG;
+  if (variant & ~(uint32_t)(ADG_VARIANT_SORTED | ADG_VARIANT_MEDIAN | ADG_VARIANT_DEC_ITR)) return ADG_ERR_ARG;
+  if ((variant & ADG_VARIANT_DEC_ITR) && (variant & ADG_VARIANT_SORTED)) return ADG_ERR_ARG;
   if ((rc = check_ws(workspace, ws_bytes, g->n, g->nnz))) return rc;
   hipStream_t s = (hipStream_t)stream;
   Params P = make_params(g, workspace, (uint64_t)eps_num, (uint64_t)eps_den, seed, 1, round_out, color_out, variant);
   int L = 0;
   if ((rc = run_adg(P, s, true, &L))) return rc;
-  if ((rc = run_jp(P, s, L))) return rc;
+  if ((rc = P.dec ? run_dec(P, s, L) : run_jp(P, s, L))) return rc;
   {
     TIMED(KC_FINISH, s);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, P, num_colors_out, num_rounds_out);
@@ -2468,7 +2717,7 @@ int adg_get_stats(const void* workspace, size_t ws_bytes, adg_stats_t* out, void
   out->sum_active = (int64_t)h.sum_active;
   out->cut_edges = (int64_t)h.cut_edges;
   out->frontier = (int64_t)h.js.F;
-  out->jp_levels = h.js.levels;
+  out->jp_levels = h.js.levels + h.dec.iters;
   out->error = h.error;
   return ADG_OK;
 }
