@@ -127,6 +127,7 @@ def cpu_baseline_graph(w, rp, col, m, variant=0):
         m = col.size // 2
         sample = "R-MAT scale %d, same generator parameters and seed (m = %d)" % (w["cpu_sample_scale"], m)
     t0 = time.perf_counter()
+    variant &= 7   # pull UPDATE has the same output; the oracle pushes
     if variant & 4:
         oracle.color_graph_dec(rp, col, w["eps"][0], w["eps"][1], w["seed"], variant & 3)
         what = "ADG then DEC-ADG-ITR"
@@ -199,7 +200,7 @@ def run_single(args, w):
     torch.cuda.synchronize()
     log("warm-up done")
     adg.profile_read()  # drop anything recorded so far
-    adg.profile_enable(["update", "update_huge", "jp", "jp_narrow", "dec_itr"])
+    adg.profile_enable(["update", "update_huge", "update_pull", "jp", "jp_narrow", "dec_itr"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -217,7 +218,8 @@ def run_single(args, w):
     # (DEC-ADG-ITR's triples of pull, pick and resolve take JP's place)
     jp_ms = prof.get("jp", (0, 0))[0] + prof.get("jp_narrow", (0, 0))[0] + prof.get("dec_itr", (0, 0))[0]
     jp_launches = prof.get("jp", (0, 0))[1] + prof.get("jp_narrow", (0, 0))[1] + prof.get("dec_itr", (0, 0))[1]
-    upd_ms = prof.get("update", (0.0, 0))[0] + prof.get("update_huge", (0.0, 0))[0]
+    upd_ms = prof.get("update", (0.0, 0))[0] + prof.get("update_huge", (0.0, 0))[0] + \
+        prof.get("update_pull", (0.0, 0))[0]
     upd_launches = prof.get("update", (0.0, 0))[1]
     if jp_ms >= upd_ms:
         dom, tot_ms, launches, kname = "jp", jp_ms, jp_launches, (
@@ -425,7 +427,7 @@ def run_serving(args, w):
 
 
 # ADG variant bits of color_graph_ex (0 = Algorithm 1)
-VARIANTS = {"adg": 0, "sorted": 1, "median": 2, "sorted_median": 3, "dec": 4, "dec_median": 6}
+VARIANTS = {"adg": 0, "sorted": 1, "median": 2, "sorted_median": 3, "dec": 4, "dec_median": 6, "pull": 8}
 
 
 def main():
@@ -436,7 +438,7 @@ def main():
     ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variant", default="adg", choices=sorted(VARIANTS),
-                    help="single-graph workloads: adg = JP-ADG (default), sorted = JP-ADG-O, median = JP-ADG-M, dec = DEC-ADG-ITR")
+                    help="single-graph workloads: adg = JP-ADG (default), sorted = JP-ADG-O, median = JP-ADG-M, dec = DEC-ADG-ITR, pull = JP-ADG with pull UPDATE")
     ap.add_argument("--breakdown", action="store_true", help="print per-kernel-class times to stderr")
     ap.add_argument("--calib-mib", type=int, default=256,
                     help="size of a plain device copy issued before the run, so that profiler byte counters "

@@ -142,9 +142,14 @@ int color_graph(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_t s
  *       the same colour, and the kept colours are final.  Deterministic for
  *       a given seed; at most 2(1+eps)d + 1 colours.  May be combined with
  *       ADG_VARIANT_MEDIAN, not with ADG_VARIANT_SORTED.
+ *   ADG_VARIANT_PULL  UPDATE pulls instead of pushing (section "Using Only
+ *       Concurrent Reads", and "Push vs. Pull"): every vertex that stays in U
+ *       subtracts from its own D the number of its neighbours in R, so no
+ *       atomics touch D; the rows of the remaining vertices are read every
+ *       round.  The output is identical to pushing.  Combines with all.
  * SORTED and MEDIAN may be combined.  variant = 0 is Algorithm 1 (adg_order,
  * color_graph).  Other bits or combinations: ADG_ERR_ARG. */
-enum { ADG_VARIANT_SORTED = 1, ADG_VARIANT_MEDIAN = 2, ADG_VARIANT_DEC_ITR = 4 };
+enum { ADG_VARIANT_SORTED = 1, ADG_VARIANT_MEDIAN = 2, ADG_VARIANT_DEC_ITR = 4, ADG_VARIANT_PULL = 8 };
 
 /* Workspace bytes for adg_order_ex with a pos output (adg_workspace_bytes
  * plus sort buffers of 24 n bytes); 0 for invalid sizes. */
@@ -320,12 +325,14 @@ int adg_validate_csr(const adg_csr_t* g, void* workspace, size_t ws_bytes, void*
  * bit is set in `mask` (classes: 0 init, 1 stats, 2 count, 3 scan,
  * 4 scatter, 5 update, 6 part1, 7 jp_prep, 8 jp (grid-wide JP steps),
  * 9 finish, 10 batched, 11 jp_narrow (single-block JP steps), 12 update_huge
- * (UPDATE of rows longer than 16384 entries, cut into chunks))
+ * (UPDATE of rows longer than 16384 entries, cut into chunks), 13
+ * median_select (ADG-M), 14 order_sort (adg_order_ex's pos), 15 dec_itr
+ * (DEC-ADG-ITR triples), 16 update_pull)
  * record a pair of HIP events on its launch stream; 0 disables it.
  * adg_profile_read waits for the recorded events, adds up the elapsed time
  * and launch count per class into *out and forgets the records.  Process-wide,
  * guarded by a mutex. */
-#define ADG_PROFILE_CLASSES 16
+#define ADG_PROFILE_CLASSES 32
 typedef struct adg_profile {
   double ms[ADG_PROFILE_CLASSES];
   int64_t launches[ADG_PROFILE_CLASSES];

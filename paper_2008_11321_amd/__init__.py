@@ -43,16 +43,17 @@ class _Stats(ctypes.Structure):
 
 
 class _Profile(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 16), ("launches", ctypes.c_int64 * 16)]
+    _fields_ = [("ms", ctypes.c_double * 32), ("launches", ctypes.c_int64 * 32)]
 
 
 KERNEL_CLASSES = ["init", "stats", "count", "scan", "scatter", "update", "part1", "jp_prep", "jp", "finish",
-                  "batched", "jp_narrow", "update_huge", "median_select", "order_sort", "dec_itr"]
+                  "batched", "jp_narrow", "update_huge", "median_select", "order_sort", "dec_itr", "update_pull"]
 
 # ADG variants (bit set): ADG-O's sorted rounds and ADG-M's median selection
 SORTED = 1
 MEDIAN = 2
 DEC_ITR = 4   # colouring by DEC-ADG-ITR instead of JP (color_graph_ex only)
+PULL = 8      # pull (CREW) UPDATE: same output, no atomics on D
 
 _lib = None
 

@@ -49,6 +49,10 @@
 //     smallest colour free in its bitmap, keep it unless a same-round
 //     predecessor (larger hash) tried the same colour, and push kept colours
 //     to its same-round neighbours' bitmaps (k_dec_*).
+//   Pull UPDATE (the CREW UPDATE of "Using Only Concurrent Reads", the pull
+//     side of "Push vs. Pull"): k_update only partitions the rows of R, and
+//     k_update_pull lets every vertex that stays in U count its neighbours
+//     removed in the round and lower its own D -- no atomics on D, more reads.
 
 #include <hip/hip_runtime.h>
 
@@ -168,6 +172,7 @@ struct Params {
   int sorted;                  // ADG-O: same-round order by (D at selection, rho_R)
   int median;                  // ADG-M: R = the lower half of U by (D, rho_R)
   int dec;                     // DEC-ADG-ITR colours the partitions (bitmaps for all same-round neighbours)
+  int pull;                    // UPDATE pulls: survivors lower their own D (k_update_pull)
   unsigned* tent;              // DEC-ADG-ITR: colour each vertex tried in its latest iteration
   unsigned* mhist;             // [MSEL_BINS] radix selection histogram
   Ctrl* ctrl;
@@ -732,7 +737,7 @@ __device__ void update_small(const Params& P, int v, bool valid, int l, unsigned
   long long nl = 0, nps = 0, ns = 0;
   unsigned long long cls = 0;   // the row's classes, 2 bits per entry (SMALL_DEG <= 32)
   for (long long j = b; j < e; ++j) {
-    int cl = visit3<FUSED>(P, P.col[j], l, code, hv, x, true);
+    int cl = visit3<FUSED>(P, P.col[j], l, code, hv, x, !P.pull);
     nl += cl == NB_PRED;
     nps += cl == NB_PRED_SAME;
     ns += cl == NB_SUCC_SAME;
@@ -785,7 +790,7 @@ __device__ void update_big(const Params& P, int v, int l, unsigned char code, un
     long long j = base + lane;
     bool valid = j < e;
     int w = valid ? P.col[j] : 0;
-    int cl = valid ? visit3<FUSED>(P, w, l, code, hv, x, true) : NB_NONE;
+    int cl = valid ? visit3<FUSED>(P, w, l, code, hv, x, !P.pull) : NB_NONE;
     if (FUSED) {
       nl += __popcll(ballot(cl == NB_PRED));
       nps += __popcll(ballot(cl == NB_PRED_SAME));
@@ -851,6 +856,63 @@ __global__ __launch_bounds__(BS) void k_update(Params P, int l) {
   }
 }
 
+// Pull UPDATE: every vertex of U_{l+1} subtracts from its own D the number of
+// its neighbours removed in round l.  Short rows are walked by their lane,
+// longer ones by the whole wavefront.  The decrements per block go to xpart
+// (the grid is upd_blocks, so every entry is written).
+__global__ __launch_bounds__(BS) void k_update_pull(Params P, int l) {
+  Ctrl* c = P.ctrl;
+  if (c->done) return;
+  const unsigned long long N = c->Nnext;
+  const int* Un = P.UL[l & 1];
+  const unsigned char code = round_code(l);
+  __shared__ unsigned long long xred[WPB];
+  unsigned long long x = 0;
+  const long long stride = (long long)gridDim.x * BS;
+  for (long long t = (long long)blockIdx.x * BS; t < (long long)N; t += stride) {
+    const long long i = t + threadIdx.x;
+    const bool has = i < (long long)N;
+    const int v = has ? Un[i] : 0;
+    long long b = 0, e = 0;
+    if (has) {
+      b = P.rp[v];
+      e = P.rp[v + 1];
+    }
+    unsigned cnt = 0;
+    const bool longrow = has && e - b > WAVE;
+    if (has && !longrow)
+      for (long long j = b; j < e; ++j) {
+        const int w = P.col[j];
+        cnt += P.status[w] == code && P.round[w] == l;
+      }
+    uint64_t m = ballot(longrow);
+    while (m) {
+      const int src = __ffsll((long long)m) - 1;
+      m &= m - 1;
+      const long long bb = readlane_i64(b, src), ee = readlane_i64(e, src);
+      unsigned part = 0;
+      for (long long j = bb + lane_id(); j < ee; j += WAVE) {
+        const int w = P.col[j];
+        part += P.status[w] == code && P.round[w] == l;
+      }
+      part = wave_sum(part);
+      if (lane_id() == (unsigned)src) cnt = part;
+    }
+    if (has && cnt) {
+      P.D[v] -= (int)cnt;
+      x += cnt;
+    }
+  }
+  x = wave_sum(x);
+  if (lane_id() == 0) xred[threadIdx.x / WAVE] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int k = 0; k < WPB; ++k) t += xred[k];
+    P.xpart[blockIdx.x] = t;
+  }
+}
+
 // ---- hubs: rows longer than HUGE_DEG, cut into HUGE_CHUNK-sized chunks
 
 // Hub entry of chunk k (entries are sorted by first chunk).
@@ -890,7 +952,7 @@ __global__ __launch_bounds__(BS) void k_update_huge_count(Params P, int l) {
     unsigned cnt[4] = {0, 0, 0, 0};
     for (long long base = c0; base < c1; base += WAVE) {
       const long long j = base + lane;
-      const int cl = j < c1 ? visit3<FUSED>(P, P.col[j], l, code, hv, x, true) : NB_NONE;
+      const int cl = j < c1 ? visit3<FUSED>(P, P.col[j], l, code, hv, x, !P.pull) : NB_NONE;
       cnt[NB_PRED] += __popcll(ballot(cl == NB_PRED));
       cnt[NB_PRED_SAME] += __popcll(ballot(cl == NB_PRED_SAME));
       cnt[NB_SUCC_SAME] += __popcll(ballot(cl == NB_SUCC_SAME));
@@ -2170,7 +2232,8 @@ namespace adg {
 namespace {
 const char* kclass_names[KC_NUM] = {"init", "stats", "count", "scan", "scatter", "update", "part1",
                                     "jp_prep", "jp", "finish", "batched", "jp_narrow", "update_huge",
-                                    "median_select", "order_sort", "dec_itr"};
+                                    "median_select", "order_sort", "dec_itr", "update_pull"};
+static_assert(KC_NUM <= ADG_PROFILE_CLASSES, "profile classes do not fit adg_profile_t");
 struct ProfRec {
   int cls;
   hipEvent_t a, b;
@@ -2331,6 +2394,7 @@ Params make_params(const adg_csr_t* g, void* ws, uint64_t p, uint64_t q, uint64_
   P.sorted = (variant & ADG_VARIANT_SORTED) != 0;
   P.median = (variant & ADG_VARIANT_MEDIAN) != 0;
   P.dec = (variant & ADG_VARIANT_DEC_ITR) != 0;
+  P.pull = (variant & ADG_VARIANT_PULL) != 0;
   P.mhist = (unsigned*)(base + L.mhist);
   P.tent = (unsigned*)(base + L.F0);   // JP's level lists are not used by DEC-ADG-ITR
   P.ctrl = (Ctrl*)(base + L.ctrl);
@@ -2448,14 +2512,15 @@ int run_adg(Params& P, hipStream_t s, bool fused, int* num_rounds_host) {
         TIMED(KC_SCATTER, s);
         hipLaunchKernelGGL(k_scatter, dim3(SEL_BLOCKS), dim3(BS), 0, s, P, l);
       }
-      {
+      // (with pull UPDATE and no fusion, the push kernels have nothing to do)
+      if (fused || !P.pull) {
         TIMED(KC_UPDATE, s);
         if (fused)
           hipLaunchKernelGGL(k_update<true>, dim3(P.upd_blocks), dim3(BS), 0, s, P, l);
         else
           hipLaunchKernelGGL(k_update<false>, dim3(P.upd_blocks), dim3(BS), 0, s, P, l);
       }
-      {
+      if (fused || !P.pull) {
         TIMED(KC_UPDATE_HUGE, s);
         if (fused) {
           hipLaunchKernelGGL(k_update_huge_count<true>, dim3(HUGE_BLOCKS), dim3(BS), 0, s, P, l);
@@ -2463,6 +2528,10 @@ int run_adg(Params& P, hipStream_t s, bool fused, int* num_rounds_host) {
         } else {
           hipLaunchKernelGGL(k_update_huge_count<false>, dim3(HUGE_BLOCKS), dim3(BS), 0, s, P, l);
         }
+      }
+      if (P.pull) {
+        TIMED(KC_UPDATE_PULL, s);
+        hipLaunchKernelGGL(k_update_pull, dim3(P.upd_blocks), dim3(BS), 0, s, P, l);
       }
     }
     // one more stats call ends the loop on the device when U is empty
@@ -2626,7 +2695,8 @@ int adg_order_ex(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_t 
   int rc = check_graph(g);
   if (rc) return rc;
   if (eps_num < 0 || eps_den < 1 || (g->n > 0 && !round_out)) return ADG_ERR_ARG;
-  if (variant & ~(uint32_t)(ADG_VARIANT_SORTED | ADG_VARIANT_MEDIAN)) return ADG_ERR_ARG;   // no colouring here
+  if (variant & ~(uint32_t)(ADG_VARIANT_SORTED | ADG_VARIANT_MEDIAN | ADG_VARIANT_PULL))
+    return ADG_ERR_ARG;   // no colouring here
   if ((rc = check_ws(workspace, ws_bytes, g->n, g->nnz))) return rc;
   if (pos_out && ws_bytes < make_order_layout(g->n, g->nnz).total) return ADG_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
@@ -2689,7 +2759,8 @@ int color_graph_ex(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_
   int rc = check_graph(g);
   if (rc) return rc;
   if (eps_num < 0 || eps_den < 1 || (g->n > 0 && !color_out)) return ADG_ERR_ARG;
-  if (variant & ~(uint32_t)(ADG_VARIANT_SORTED | ADG_VARIANT_MEDIAN | ADG_VARIANT_DEC_ITR)) return ADG_ERR_ARG;
+  if (variant & ~(uint32_t)(ADG_VARIANT_SORTED | ADG_VARIANT_MEDIAN | ADG_VARIANT_DEC_ITR | ADG_VARIANT_PULL))
+    return ADG_ERR_ARG;
   if ((variant & ADG_VARIANT_DEC_ITR) && (variant & ADG_VARIANT_SORTED)) return ADG_ERR_ARG;
   if ((rc = check_ws(workspace, ws_bytes, g->n, g->nnz))) return rc;
   hipStream_t s = (hipStream_t)stream;

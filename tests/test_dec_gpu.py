@@ -12,7 +12,7 @@ from checkers import check_dec_itr, edges_to_csr
 
 pytestmark = pytest.mark.gpu
 
-MEDIAN, DEC = 2, 4
+MEDIAN, DEC, PULL = 2, 4, 8
 
 
 @pytest.fixture(scope="module")
@@ -27,7 +27,7 @@ def dev():
 def _compare(pkg, rp, col, p, q, seed, flags=0, label="", ws=None):
     import torch
     print("case", label, "n", rp.size - 1, "nnz", col.size, "eps", p, q, "seed", seed, "flags", flags, flush=True)
-    color, k, rho, L, step, it = oracle.color_graph_dec(rp, col, p, q, seed, flags)
+    color, k, rho, L, step, it = oracle.color_graph_dec(rp, col, p, q, seed, flags & MEDIAN)
     g = pkg.Graph(rp, col)
     if ws is None:
         ws = torch.empty(pkg.workspace_bytes(g.n, g.nnz), dtype=torch.uint8, device="cuda")
@@ -100,6 +100,7 @@ def test_rmat_mid(dev, scale):
     rp, col = graphgen.rmat_config(scale, seed=2)
     _compare(dev, rp, col, 1, 10, 2, 0, "rmat%d" % scale)
     _compare(dev, rp, col, 1, 10, 2, MEDIAN, "rmat%d median" % scale)
+    _compare(dev, rp, col, 1, 10, 2, PULL, "rmat%d pull" % scale)
 
 
 def test_chung_lu_hubs(dev):

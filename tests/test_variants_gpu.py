@@ -1,7 +1,8 @@
 """Parity of the ADG variants on the GPU (color_graph_ex, adg_order_ex) with
 the CPU oracle, bit-exact: rounds, the total order pos, colours, counts.
 ADG-O = SORTED (R ordered by D at selection, then rho_R); ADG-M = MEDIAN
-(R = the lower half of U by (D, rho_R)).  GPU only."""
+(R = the lower half of U by (D, rho_R)); PULL (UPDATE pulls into the
+survivors' own D, no atomics) must not change any output.  GPU only."""
 import itertools
 
 import numpy as np
@@ -13,8 +14,9 @@ from checkers import check_adg_variant, check_jp_order, edges_to_csr
 
 pytestmark = pytest.mark.gpu
 
-SORTED, MEDIAN = 1, 2
+SORTED, MEDIAN, PULL = 1, 2, 8
 FLAGS = [SORTED, MEDIAN, SORTED | MEDIAN]
+PULL_FLAGS = [PULL, PULL | SORTED, PULL | MEDIAN]
 
 
 @pytest.fixture(scope="module")
@@ -22,14 +24,15 @@ def dev():
     import paper_2008_11321_amd as pkg
     import torch
     assert torch.cuda.is_available()
-    assert pkg.SORTED == SORTED and pkg.MEDIAN == MEDIAN
+    assert pkg.SORTED == SORTED and pkg.MEDIAN == MEDIAN and pkg.PULL == PULL
     return pkg
 
 
 def _compare(pkg, rp, col, p, q, seed, flags, label="", ws=None, order=True):
     import torch
     print("case", label, "n", rp.size - 1, "nnz", col.size, "eps", p, q, "seed", seed, "flags", flags, flush=True)
-    color, k, rnd, L, pos, st = oracle.color_graph_ex(rp, col, p, q, seed, flags)
+    # the oracle has no pull UPDATE: pulling must give the push output
+    color, k, rnd, L, pos, st = oracle.color_graph_ex(rp, col, p, q, seed, flags & (SORTED | MEDIAN))
     g = pkg.Graph(rp, col)
     if ws is None:
         ws = torch.empty(pkg.order_workspace_bytes(g.n, g.nnz), dtype=torch.uint8, device="cuda")
@@ -62,7 +65,7 @@ SMALL_CASES = [
 ]
 
 
-@pytest.mark.parametrize("flags", FLAGS)
+@pytest.mark.parametrize("flags", FLAGS + PULL_FLAGS)
 @pytest.mark.parametrize("name,n,edges", SMALL_CASES)
 def test_small_graphs(dev, name, n, edges, flags):
     rp, col = edges_to_csr(n, edges)
@@ -82,7 +85,7 @@ def test_empty_graph(dev, flags):
     assert int(L.item()) == 0
 
 
-@pytest.mark.parametrize("flags", FLAGS)
+@pytest.mark.parametrize("flags", FLAGS + PULL_FLAGS)
 @pytest.mark.parametrize("seed", range(3))
 def test_random_graphs(dev, seed, flags):
     rng = np.random.default_rng(50 + seed)
@@ -98,7 +101,7 @@ def test_random_graphs(dev, seed, flags):
             _compare(dev, rp, col, p, q, trial, flags, "random %d/%d" % (seed, trial))
 
 
-@pytest.mark.parametrize("flags", FLAGS)
+@pytest.mark.parametrize("flags", FLAGS + PULL_FLAGS)
 @pytest.mark.parametrize("scale", [16, 18])
 def test_rmat_mid(dev, scale, flags):
     rp, col = graphgen.rmat_config(scale, seed=2)
@@ -118,7 +121,7 @@ def test_median_many_equal_degrees(dev):
 
 def test_chung_lu_hubs(dev):
     rp, col = graphgen.chung_lu(200_000, 32, 2.3, seed=9)
-    for flags in FLAGS:
+    for flags in FLAGS + PULL_FLAGS:
         _compare(dev, rp, col, 1, 10, 4, flags, "chung-lu 2e5")
 
 
@@ -134,7 +137,7 @@ def test_hub_rows_longer_than_the_chunk_threshold(dev):
     extra = rng.integers(hubs, n, size=(5000, 2))
     es = np.concatenate([np.array(edges).T, np.stack([src, dst]), extra.T], axis=1)
     rp, col = graphgen.from_edges(n, es[0], es[1])
-    for flags in FLAGS:
+    for flags in FLAGS + PULL_FLAGS:
         _compare(dev, rp, col, 10**6, 1, 7, flags, "hubs, one round")
         _compare(dev, rp, col, 1, 10, 7, flags, "hubs")
 
@@ -167,3 +170,24 @@ def test_rmat20_median_definition(dev):
     r, pos, c = r.cpu().numpy(), pos.cpu().numpy().astype(np.int64), c.cpu().numpy()
     check_adg_variant(rp, col, 1, 10, 3, MEDIAN, r, pos, int(L.item()))
     check_jp_order(rp, col, pos, c)
+
+
+def test_pull_alone_equals_algorithm_1(dev):
+    """PULL with no other bit is JP-ADG exactly (colours, rounds, counters),
+    also through adg_order_ex, on graphs with long rows and many rounds."""
+    import torch
+    for label, (rp, col), eps in [("rmat17", graphgen.rmat_config(17, seed=8), (1, 10)),
+                                  ("chung-lu 1e5", graphgen.chung_lu(100_000, 24, 2.1, seed=5), (1, 100)),
+                                  ("path 3000", edges_to_csr(3000, [(i, i + 1) for i in range(2999)]), (0, 1))]:
+        p, q = eps
+        _compare(dev, rp, col, p, q, 6, PULL, label)
+        rho, L, st = oracle.adg(rp, col, p, q)
+        g = dev.Graph(rp, col)
+        r, pos, nr = dev.adg_order_ex(g, p, q, 6, PULL, want_pos=False)
+        torch.cuda.synchronize()
+        assert int(nr.item()) == L and np.array_equal(r.cpu().numpy(), rho), label
+
+
+def test_rmat22_pull_bit_exact(dev):
+    rp, col = graphgen.rmat_config(22, seed=2)
+    _compare(dev, rp, col, 1, 10, 2, PULL, "rmat22 pull", order=False)
