@@ -41,8 +41,8 @@ WORKLOADS = {
     "rmat26_e05": dict(kind="rmat", scale=26, edge_factor=16, eps=(1, 2), seed=3, cpu_sample_scale=24),
     "er": dict(kind="er", n=10_000, mean_deg=10.0, eps=(1, 100), seed=1),
     "batched": dict(kind="batched", num_graphs=4096, eps=(1, 10), seed=4),
-    "serving": dict(kind="serving", requests=240, eps=(1, 10), seed=5, load=0.7, scale_down=False),
-    "serving_small": dict(kind="serving", requests=48, eps=(1, 10), seed=5, load=0.7, scale_down=True),
+    "serving": dict(kind="serving", requests=240, eps=(1, 10), seed=5, load=0.75, scale_down=False),
+    "serving_small": dict(kind="serving", requests=48, eps=(1, 10), seed=5, load=0.75, scale_down=True),
 }
 
 # kernel sources each timed kernel class is built from (for matching
@@ -116,9 +116,40 @@ def measured_traffic(kernel, workload):
     return rec.get("bytes_per_launch")
 
 
+def step_stats(times):
+    """Per-step times: the first 1% dropped as warm-up, then mean, median and
+    a 95% percentile-bootstrap interval of the mean (seeded, 2000 resamples)."""
+    import numpy as np
+    t = np.asarray(times, dtype=np.float64) * 1000.0
+    t = t[int(np.ceil(0.01 * t.size)):] if t.size > 1 else t
+    rng = np.random.default_rng(0)
+    means = t[rng.integers(0, t.size, size=(2000, t.size))].mean(axis=1)
+    lo, hi = np.percentile(means, [2.5, 97.5])
+    return {"n": int(t.size), "mean": round(float(t.mean()), 4), "ci95": [round(float(lo), 4), round(float(hi), 4)],
+            "median": round(float(np.median(t)), 4), "min": round(float(t.min()), 4), "max": round(float(t.max()), 4)}
+
+
+def host_description():
+    """CPU model, logical CPUs and memory of the machine the oracle runs on."""
+    model, mem_kb = "unknown", 0
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                mem_kb = int(line.split()[1])
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "mem_gib": round(mem_kb / 2**20, 1)}
+
+
 def cpu_baseline_graph(w, rp, col, m, variant=0):
-    """The oracle on the workload's graph; for RMAT-26 on the same generator
-    at a smaller scale (a bounded sample of about 10-30 s of CPU work)."""
+    """The oracle on the workload's graph (for RMAT-26, on the same generator
+    at a smaller scale: a bounded sample of about 10-30 s of CPU work), serial
+    and pinned to one core, ADG and the colouring timed apart, repeated."""
     import oracle
     sample = "whole graph"
     if "cpu_sample_scale" in w:
@@ -126,20 +157,50 @@ def cpu_baseline_graph(w, rp, col, m, variant=0):
         rp, col = graphgen.rmat_config(w["cpu_sample_scale"], seed=w["seed"], edge_factor=w["edge_factor"])
         m = col.size // 2
         sample = "R-MAT scale %d, same generator parameters and seed (m = %d)" % (w["cpu_sample_scale"], m)
-    t0 = time.perf_counter()
+    p, q, seed = w["eps"][0], w["eps"][1], w["seed"]
     variant &= 7   # pull UPDATE has the same output; the oracle pushes
     if variant & 4:
-        oracle.color_graph_dec(rp, col, w["eps"][0], w["eps"][1], w["seed"], variant & 3)
-        what = "ADG then DEC-ADG-ITR"
+        what = "ADG%s then DEC-ADG-ITR" % (" (median)" if variant & 2 else "")
+        order = (lambda: oracle.adg_ex(rp, col, p, q, seed, variant & 3)[0]) if variant & 3 else \
+            (lambda: oracle.adg(rp, col, p, q)[0])
+        colour = lambda o: oracle.dec_itr(rp, col, o, seed)
     elif variant:
-        oracle.color_graph_ex(rp, col, w["eps"][0], w["eps"][1], w["seed"], variant)
         what = "ADG variant %d then greedy JP" % variant
+        order = lambda: oracle.adg_ex(rp, col, p, q, seed, variant)[1]
+        colour = lambda o: oracle.jp_total(rp, col, o)
     else:
-        oracle.color_graph(rp, col, w["eps"][0], w["eps"][1], w["seed"])
         what = "ADG then greedy JP"
-    dt = time.perf_counter() - t0
-    return {"value": m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": "%s: one serial run of the C oracle (%s), %.2f s" % (sample, what, dt)}
+        order = lambda: oracle.adg(rp, col, p, q)[0]
+        colour = lambda o: oracle.jp(rp, col, o, seed)
+    core = None
+    old = os.sched_getaffinity(0) if hasattr(os, "sched_getaffinity") else None
+    if old:
+        core = min(old)
+        os.sched_setaffinity(0, {core})
+    try:
+        t_ord, t_col = [], []
+        t_start = time.perf_counter()
+        while True:
+            t0 = time.perf_counter()
+            o = order()
+            t1 = time.perf_counter()
+            colour(o)
+            t2 = time.perf_counter()
+            t_ord.append(t1 - t0)
+            t_col.append(t2 - t1)
+            # repeat while the sample stays within about 15 s (at most 100 runs)
+            if len(t_ord) >= 100 or (t2 - t_start) + (t2 - t0) > 15.0:
+                break
+    finally:
+        if old:
+            os.sched_setaffinity(0, old)
+    a, c = sum(t_ord) / len(t_ord), sum(t_col) / len(t_col)
+    rec = {"value": m / (a + c), "unit": "edges/s", "cores": 1, "kind": "oracle",
+           "sample": "%s: the serial C oracle (%s), %d runs pinned to CPU %s, mean %.3f s ADG + %.3f s colouring" %
+                     (sample, what, len(t_ord), core, a, c),
+           "runs": len(t_ord), "order_s": round(a, 4), "colour_s": round(c, 4), "pinned_cpu": core}
+    rec.update(host_description())
+    return rec
 
 
 def calibration_copy(mib):
@@ -202,10 +263,13 @@ def run_single(args, w):
     adg.profile_read()  # drop anything recorded so far
     adg.profile_enable(["update", "update_huge", "update_pull", "jp", "jp_narrow", "dec_itr"])
     torch.cuda.synchronize()
+    times = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        ts = time.perf_counter()
         step()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
     dt = time.perf_counter() - t0
     adg.profile_enable([])
     prof = adg.profile_read()
@@ -246,7 +310,7 @@ def run_single(args, w):
         cfg["variant"] = args.variant
     if w["kind"] == "rmat":
         cfg.update(scale=w["scale"], edge_factor=w["edge_factor"], abcd=[0.57, 0.19, 0.19, 0.05])
-    return m / (dt / args.steps), dt * 1000 / args.steps, cfg, roofline, cpu, {}
+    return m / (dt / args.steps), dt * 1000 / args.steps, cfg, roofline, cpu, {"step_ms": step_stats(times)}
 
 
 def run_batched(args, w):
@@ -339,9 +403,10 @@ def run_batched(args, w):
 def run_serving(args, w):
     """Poisson stream of colouring requests (70% ER, 25% Chung-Lu, 5% R-MAT)
     through the serving loop.  The saturation rate is measured first (every
-    request submitted at once); the timed stream then arrives at `load` times
-    that rate.  The plain comparison colours the same requests one at a time
-    (one worker, no grouping)."""
+    request submitted at once); the stream then arrives at 0.25, 0.5, 0.75
+    and 0.9 times that rate, and the line reports the `load` one.  The plain
+    comparison colours the same requests one at a time (one worker, no
+    grouping)."""
     import numpy as np
     import torch
 
@@ -376,14 +441,20 @@ def run_serving(args, w):
         sv.replay(srv, graphs[:min(16, len(graphs))])   # warm-up
         sat = sv.latency_summary(sv.replay(srv, graphs))
         log("saturation: %.1f req/s, %.3g edges/s" % (sat["requests_per_s"], sat["edges_per_s"]))
-        qps = w["load"] * sat["requests_per_s"]
-        arrivals = graphgen.poisson_arrivals(len(graphs), qps, seed=seed)
-        c0 = srv.counters()
-        res = sv.replay(srv, graphs, arrivals)
-        c1 = srv.counters()
-        served = sv.latency_summary(res)
-        log("poisson at %.1f req/s: p50 %.2f ms p99 %.2f ms, %.3g edges/s" %
-            (qps, served["p50_ms"], served["p99_ms"], served["edges_per_s"]))
+        sweep = {}
+        for load in (0.25, 0.5, 0.75, 0.9):
+            rate = load * sat["requests_per_s"]
+            arrivals = graphgen.poisson_arrivals(len(graphs), rate, seed=seed)
+            a0 = srv.counters()
+            r = sv.replay(srv, graphs, arrivals)
+            a1 = srv.counters()
+            summ = sv.latency_summary(r)
+            log("poisson at %.2f x saturation (%.1f req/s): p50 %.2f ms p99 %.2f ms, %.3g edges/s" %
+                (load, rate, summ["p50_ms"], summ["p99_ms"], summ["edges_per_s"]))
+            sweep[str(load)] = {"offered_qps": round(rate, 1), "p50_ms": summ["p50_ms"], "p99_ms": summ["p99_ms"],
+                                "edges_per_s": summ["edges_per_s"]}
+            if load == w["load"]:
+                qps, res, served, c0, c1 = rate, r, summ, a0, a1
     assert all(r["status"] == 0 for r in res)
     with sv.Server(arena, eps=(p, q), seed=seed, workers=1, small_nnz=0, max_group=1, max_bypass=0) as srv:
         sv.replay(srv, graphs[:min(16, len(graphs))])
@@ -422,7 +493,8 @@ def run_serving(args, w):
              "grouped_requests": d["grouped_requests"], "grouped_launches": d["grouped_jobs"],
              "plain_per_graph": {"value": plain["edges_per_s"], "unit": "edges/s", "p50_ms": plain["p50_ms"],
                                  "p99_ms": plain["p99_ms"]},
-             "speedup_vs_plain_saturated": sat["edges_per_s"] / plain["edges_per_s"]}
+             "speedup_vs_plain_saturated": sat["edges_per_s"] / plain["edges_per_s"],
+             "load_sweep": sweep}
     return served["edges_per_s"], served["span_s"] * 1000, cfg, roofline, cpu, extra
 
 
@@ -433,7 +505,8 @@ VARIANTS = {"adg": 0, "sorted": 1, "median": 2, "sorted_median": 3, "dec": 4, "d
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 30 for single graphs, 5 at R-MAT scale 26, 20 batched)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -449,6 +522,8 @@ def main():
               "(use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     w = WORKLOADS[args.workload]
+    if args.steps is None:
+        args.steps = 20 if w["kind"] == "batched" else 5 if w.get("scale", 0) >= 26 else 30
     if w["kind"] == "batched":
         value, ms_per_step, cfg, roofline, cpu, extra = run_batched(args, w)
     elif w["kind"] == "serving":
