@@ -83,8 +83,16 @@ constexpr int JP_CHUNK = WAVE * JP_UNROLL;   // successors per wavefront step / 
 constexpr int FAN_LDS = 1024;                // fan-out list entries a grid block stages in LDS
 constexpr int NARROW_BS = 1024;              // threads of the single-block JP kernel
 constexpr int NARROW_MAX = 1024;             // level size the single block takes
-constexpr int NARROW_WORDS = 4096;           // colour bitmap words of a level it takes
-constexpr int NARROW_SUCC = 4096;            // same-round successor entries of a level it takes
+// Work of a level the single block takes (it walks larger ones in passes of
+// NARROW_BS * NARROW_UNROLL entries; beyond these sizes the grid is faster).
+#ifndef ADG_NARROW_WORDS
+#define ADG_NARROW_WORDS 4096
+#endif
+#ifndef ADG_NARROW_SUCC
+#define ADG_NARROW_SUCC 4096
+#endif
+constexpr int NARROW_WORDS = ADG_NARROW_WORDS;  // colour bitmap words of a level
+constexpr int NARROW_SUCC = ADG_NARROW_SUCC;    // same-round successor entries of a level
 constexpr int NARROW_XPULL = 512;            // round size whose later-round colours it pulls in
 constexpr int NARROW_UNROLL = 4;             // edges per thread in flight in a narrow level
 constexpr int MSEL_BINS = 2048;              // radix selection: 11-bit digits
@@ -194,6 +202,8 @@ struct Params {
   unsigned long long* rec;     // (colour bitmap offset << 32) | |pred(v)|
   unsigned* B;                 // colour bitmaps (bm_words(|pred|) words per vertex)
   unsigned long long bm_cap;   // words of B
+  unsigned long long* pool;    // per-wavefront bitmap pools of k_update / k_part1: (end << 32) | next
+  unsigned pool_chunk;         // words a pool takes from bm_next at a time
   unsigned long long* HL;      // rows of the round cut into chunks: (first chunk << 32) | vertex
   unsigned* HC;                // per such row: class counts [4] and placed counts [4]
   unsigned huge_cap;
@@ -252,7 +262,9 @@ __device__ __forceinline__ unsigned add32(unsigned* p, unsigned v) {
 
 __global__ void k_init(Params P) {
   Ctrl* c = P.ctrl;
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  if (blockIdx.x != 0) return;
+  for (int i = threadIdx.x; i < P.upd_blocks * WPB; i += blockDim.x) P.pool[i] = 0;
+  if (threadIdx.x != 0) return;
   c->N = c->S = c->Nnext = c->SUnext = 0;
   c->sum_active = c->cut_edges = 0;
   c->T = 0;
@@ -680,19 +692,55 @@ __device__ __forceinline__ T wave_excl_scan(T x, T* total) {
   return incl - x;
 }
 
+// Colour bitmap words come from one bump counter (bm_next).  A counter that
+// every wavefront hits once per row serialises (one same-address atomic per
+// vertex), so the kernels that build rows give each wavefront a pool: it
+// takes pool_chunk words at a time and hands them out itself.  Requests
+// above pool_chunk / 8 words go to the counter directly, so a chunk is at
+// least 7/8 used before the next one is taken.  Pool state lives in the
+// workspace by global wavefront index and carries over between launches;
+// k_init empties it.
+struct BmPool {
+  unsigned long long next, end;   // wave-uniform
+};
+__device__ __forceinline__ BmPool pool_load(const Params& P, long long gw) {
+  const unsigned long long s = P.pool[gw];
+  return {s & 0xffffffffull, s >> 32};
+}
+__device__ __forceinline__ void pool_store(const Params& P, long long gw, const BmPool& b) {
+  if (lane_id() == 0) P.pool[gw] = (b.end << 32) | b.next;
+}
+// `tot` words for the wavefront (wave-uniform); pl = nullptr: from the counter.
+__device__ __forceinline__ unsigned long long pool_alloc(const Params& P, BmPool* pl, unsigned tot) {
+  unsigned long long base = 0;
+  if (!pl || tot > P.pool_chunk / 8) {
+    if (lane_id() == 0) base = atomicAdd(&P.ctrl->bm_next, (unsigned long long)tot);
+    return readlane_u64(base, 0);
+  }
+  if (pl->next + tot > pl->end) {
+    if (lane_id() == 0) base = atomicAdd(&P.ctrl->bm_next, (unsigned long long)P.pool_chunk);
+    base = readlane_u64(base, 0);
+    pl->next = base;
+    pl->end = base + P.pool_chunk;
+  }
+  const unsigned long long off = pl->next;
+  pl->next += tot;
+  return off;
+}
+
 // Whole wavefront: JP bookkeeping of the lanes' vertices with `has` set --
 // |pred(v)| (np), same-round successors (ns), same-round predecessors still
-// to be coloured (cnt = nps), and a cleared colour bitmap from the bump
-// allocator; rec[v] = (bitmap offset << 32) | np.
-__device__ __forceinline__ void jp_row(const Params& P, bool has, int v, long long np, long long ns, long long nps) {
+// to be coloured (cnt = nps), and a cleared colour bitmap from the
+// wavefront's pool (pl) or the bump counter (pl = nullptr);
+// rec[v] = (bitmap offset << 32) | np.
+__device__ __forceinline__ void jp_row(const Params& P, BmPool* pl, bool has, int v, long long np, long long ns,
+                                       long long nps) {
   // JP: bits for colours 1 .. np+2; DEC-ADG-ITR: also the same-round successors
   const long long nb = P.dec ? np + ns : np;
   const unsigned w = has ? bm_words((int)nb) : 0;
   unsigned tot;
   const unsigned pre = wave_excl_scan<unsigned>(w, &tot);
-  unsigned long long base = 0;
-  if (lane_id() == 0 && tot) base = atomicAdd(&P.ctrl->bm_next, (unsigned long long)tot);
-  base = readlane_u64(base, 0);
+  const unsigned long long base = tot ? pool_alloc(P, pl, tot) : 0;
   if (!has) return;
   unsigned long long off = base + pre;
   if (off + w > P.bm_cap) {  // cannot happen (see the capacity); keep accesses in bounds
@@ -722,12 +770,34 @@ __device__ __forceinline__ void l0_append(const Params& P, int l, long long base
   if (z) P.L0[base + at + lanes_below(m)] = (unsigned)v;
 }
 
+// Wavefront-per-row kernels append one vertex at a time: they stage the
+// vertices in a register (lane k holds the k-th) and flush 64 with one atomic.
+struct L0Stage {
+  int v;
+  unsigned cnt;   // wave-uniform
+};
+__device__ __forceinline__ void l0_flush(const Params& P, L0Stage& s, int l, long long base) {
+  if (!s.cnt) return;
+  unsigned at = 0;
+  if (lane_id() == 0) at = atomicAdd(&P.l0n[l], s.cnt);
+  at = readlane_u(at, 0);
+  if (lane_id() < s.cnt) P.L0[base + at + lane_id()] = (unsigned)s.v;
+  s.cnt = 0;
+}
+// z and v wave-uniform
+__device__ __forceinline__ void l0_stage(const Params& P, L0Stage& s, int l, long long base, bool z, int v) {
+  if (!z) return;
+  if (lane_id() == s.cnt) s.v = v;
+  s.cnt += 1;
+  if (s.cnt == WAVE) l0_flush(P, s, l, base);
+}
+
 // Lane-per-vertex UPDATE for rows of at most SMALL_DEG entries: one pass to
 // count (and decrement), one pass to place the row as [predecessors from
 // later rounds | same-round predecessors | same-round successors |
 // successors from earlier rounds].
 template <bool FUSED>
-__device__ void update_small(const Params& P, int v, bool valid, int l, unsigned char code, unsigned& x) {
+__device__ void update_small(const Params& P, BmPool* pl, int v, bool valid, int l, unsigned char code, unsigned& x) {
   long long b = 0, e = 0;
   if (valid) {
     b = P.rp[v];
@@ -756,14 +826,15 @@ __device__ void update_small(const Params& P, int v, bool valid, int l, unsigned
       else P.dag[--r] = w;
     }
   }
-  jp_row(P, valid, v, np, ns, nps);
+  jp_row(P, pl, valid, v, np, ns, nps);
   l0_append(P, l, (long long)P.n - P.roundN[l], valid && nps == 0, v);
 }
 
 // Wave-per-vertex UPDATE for longer rows: count pass (with the decrements),
 // then a placing pass.
 template <bool FUSED>
-__device__ void update_big(const Params& P, int v, int l, unsigned char code, unsigned& x) {
+__device__ void update_big(const Params& P, BmPool* pl, L0Stage& l0s, int v, int l, unsigned char code,
+                           unsigned& x) {
   const long long b = P.rp[v], e = P.rp[v + 1];
   if (e - b > HUGE_DEG) {  // a hub: its chunks are spread over the grid by k_update_huge_*
     if (lane_id() == 0) {
@@ -819,8 +890,8 @@ __device__ void update_big(const Params& P, int v, int l, unsigned char code, un
     sc += __popcll(sm);
     lc += __popcll(lm);
   }
-  jp_row(P, lane == 0, v, np, ns, nps);
-  l0_append(P, l, (long long)P.n - P.roundN[l], lane == 0 && nps == 0, v);
+  jp_row(P, pl, lane == 0, v, np, ns, nps);
+  l0_stage(P, l0s, l, (long long)P.n - P.roundN[l], nps == 0, v);
 }
 
 template <bool FUSED>
@@ -836,15 +907,22 @@ __global__ __launch_bounds__(BS) void k_update(Params P, int l) {
   const long long gw = (long long)blockIdx.x * WPB + threadIdx.x / WAVE;
   const long long gstride = (long long)gridDim.x * WPB;
   unsigned x = 0;
+  BmPool pool = {0, 0};
+  L0Stage l0s = {0, 0};
+  if (FUSED) pool = pool_load(P, gw);
   for (long long it = gw; it < items; it += gstride) {
     if (it < nsg) {
       long long idx = it * WAVE + lane_id();
       bool valid = idx < nRs;
       int v = valid ? RL[idx] : 0;
-      update_small<FUSED>(P, v, valid, l, code, x);
+      update_small<FUSED>(P, &pool, v, valid, l, code, x);
     } else {
-      update_big<FUSED>(P, RL[nRs + (it - nsg)], l, code, x);
+      update_big<FUSED>(P, &pool, l0s, RL[nRs + (it - nsg)], l, code, x);
     }
+  }
+  if (FUSED) {
+    l0_flush(P, l0s, l, (long long)P.n - P.roundN[l]);
+    pool_store(P, gw, pool);
   }
   unsigned long long xs = wave_sum((unsigned long long)x);
   if (lane_id() == 0) xred[threadIdx.x / WAVE] = xs;
@@ -1008,7 +1086,7 @@ __global__ __launch_bounds__(BS) void k_update_huge_place(Params P, int l) {
       }
     }
     if (k == first) {
-      jp_row(P, lane == 0, v, np, ns, nps);
+      jp_row(P, nullptr, lane == 0, v, np, ns, nps);
       l0_append(P, l, (long long)P.n - P.roundN[l], lane == 0 && nps == 0, v);
     }
   }
@@ -1029,6 +1107,8 @@ __global__ __launch_bounds__(BS) void k_part1(Params P) {
   const long long gstride = (long long)gridDim.x * WPB;
   const unsigned lane = lane_id();
   const long long groups = ((long long)P.n + WAVE - 1) / WAVE;
+  BmPool pool = pool_load(P, gw);
+  L0Stage l0s = {0, 0};
   for (long long g = gw; g < groups; g += gstride) {
     long long idx = g * WAVE + lane;
     bool valid = idx < P.n;
@@ -1046,7 +1126,7 @@ __global__ __launch_bounds__(BS) void k_part1(Params P) {
       }
       np = f - b;
     }
-    jp_row(P, small, v, np, (e - b) - np, np);
+    jp_row(P, &pool, small, v, np, (e - b) - np, np);
     l0_append(P, 1, 0, small && np == 0, v);
     uint64_t big = ballot(valid && !small);
     while (big) {
@@ -1067,10 +1147,12 @@ __global__ __launch_bounds__(BS) void k_part1(Params P) {
         fc += __popcll(pm);
         sc += __popcll(sm);
       }
-      jp_row(P, lane == 0, u, fc, sc, fc);
-      l0_append(P, 1, 0, lane == 0 && fc == 0, u);
+      jp_row(P, &pool, lane == 0, u, fc, sc, fc);
+      l0_stage(P, l0s, 1, 0, fc == 0, u);
     }
   }
+  l0_flush(P, l0s, 1, 0);
+  pool_store(P, gw, pool);
 }
 
 // ================================================================ JP Part 2
@@ -2283,11 +2365,25 @@ namespace {
 
 struct Layout {
   size_t ctrl, bcount, boff, bsum, xpart, D, status, UL0, UL1, ORD, roundN, round, dag, npred, nsr, cnt, rec, B,
-      bm_cap, L0, l0n, F0, F1, H0, H1, hub_cap, HL, HC, huge_cap, mhist, total;
+      bm_cap, L0, l0n, F0, F1, H0, H1, hub_cap, HL, HC, huge_cap, mhist, pool, pool_chunk, total;
 };
 
 constexpr int UPD_BLOCKS = 2048;
 constexpr int HUGE_BLOCKS = 1024;
+
+// Colour bitmap words: the rows need sum over v of ceil((bits+2)/32), bits =
+// |pred(v)| for JP (<= nnz/2 in total) or all non-earlier neighbours for
+// DEC-ADG-ITR (<= nnz): at most base = nnz/32 + 33n/32 words.  The
+// wavefront pools (pool_alloc) use at most 8/7 of what they hand out plus
+// one open chunk per wavefront.
+void bm_capacity(int64_t n, int64_t nnz, size_t* cap, size_t* chunk) {
+  const unsigned long long base = (unsigned long long)nnz / 32 + 2ull * (unsigned long long)n + 64;
+  const unsigned long long waves = (unsigned long long)UPD_BLOCKS * WPB;
+  unsigned long long c = base / (8 * waves);
+  c = c < 64 ? 64 : c > 8192 ? 8192 : c;
+  *chunk = (size_t)c;
+  *cap = (size_t)(base + base / 6 + waves * c + 64);
+}
 
 Layout make_layout(int64_t n, int64_t nnz) {
   Layout L{};
@@ -2315,10 +2411,7 @@ Layout make_layout(int64_t n, int64_t nnz) {
   L.nsr = take(4 * nn);
   L.cnt = take(4 * nn);
   L.rec = take(8 * nn);
-  // colour bitmaps: sum over v of ceil((bits+2)/32) words, bits = |pred(v)|
-  // for JP (<= nnz/2 in total), all non-earlier neighbours for DEC-ADG-ITR
-  // (<= nnz): at most nnz/32 + 33n/32 words
-  L.bm_cap = (size_t)nnz / 32 + 2 * nn + 64;
+  bm_capacity(n, nnz, &L.bm_cap, &L.pool_chunk);
   L.B = take(4 * L.bm_cap);
   L.L0 = take(4 * nn);
   L.l0n = take(4 * (nn + 4));
@@ -2334,6 +2427,7 @@ Layout make_layout(int64_t n, int64_t nnz) {
   L.HL = take(8 * L.huge_cap);
   L.HC = take(4 * 8 * L.huge_cap);
   L.mhist = take(4 * MSEL_BINS);
+  L.pool = take(8 * (size_t)UPD_BLOCKS * WPB);
   L.total = off;
   return L;
 }
@@ -2366,7 +2460,9 @@ int check_graph(const adg_csr_t* g) {
   if (g->n > 0 && (!g->row_ptr)) return ADG_ERR_ARG;
   if (g->nnz > 0 && !g->col_idx) return ADG_ERR_ARG;
   // the colour bitmaps are addressed with 32-bit word offsets
-  if ((unsigned long long)g->nnz / 32 + 2ull * (unsigned long long)g->n + 64 >= (1ull << 32)) return ADG_ERR_UNSUPPORTED;
+  size_t cap = 0, chunk = 0;
+  bm_capacity(g->n, g->nnz, &cap, &chunk);
+  if ((unsigned long long)cap + chunk >= (1ull << 32)) return ADG_ERR_UNSUPPORTED;
   return ADG_OK;
 }
 
@@ -2417,6 +2513,8 @@ Params make_params(const adg_csr_t* g, void* ws, uint64_t p, uint64_t q, uint64_
   P.rec = (unsigned long long*)(base + L.rec);
   P.B = (unsigned*)(base + L.B);
   P.bm_cap = L.bm_cap;
+  P.pool = (unsigned long long*)(base + L.pool);
+  P.pool_chunk = (unsigned)L.pool_chunk;
   P.L0 = (unsigned*)(base + L.L0);
   P.l0n = (unsigned*)(base + L.l0n);
   P.F[0] = (unsigned*)(base + L.F0);
