@@ -183,9 +183,13 @@ def dec_itr(row_ptr, col, rho, seed):
     return color[:n], int(k), step[:n], int(st[0])
 
 
-def color_graph_dec(row_ptr, col, eps_num, eps_den, seed):
-    """DEC-ADG-ITR end to end: ADG (Algorithm 1), then dec_itr.  Returns
-    (color, num_colors, round, L, step, iterations)."""
-    rho, L, _ = adg(row_ptr, col, eps_num, eps_den)
+def color_graph_dec(row_ptr, col, eps_num, eps_den, seed, flags=0):
+    """DEC-ADG-ITR end to end: ADG (Algorithm 1; ADG-M's partitions with
+    flags = MEDIAN), then dec_itr.  Returns (color, num_colors, round, L,
+    step, iterations)."""
+    if flags:
+        rho, _, L, _ = adg_ex(row_ptr, col, eps_num, eps_den, seed, flags)
+    else:
+        rho, L, _ = adg(row_ptr, col, eps_num, eps_den)
     color, k, step, it = dec_itr(row_ptr, col, rho, seed)
     return color, k, rho, L, step, it

@@ -43,13 +43,16 @@ def test_alone_and_in_the_mix_give_the_same_result(sv):
     # jobs overlapped in time
     iv = sorted((r["t_start"], r["t_done"]) for r in mix)
     assert any(iv[k + 1][0] < iv[k][1] for k in range(len(iv) - 1))
+    bad = []
     for i, (rp, col) in enumerate(graphs):
         a, m = alone[i], mix[i]
-        assert a["status"] == 0 and m["status"] == 0
-        assert np.array_equal(a["color"], m["color"]), i
-        assert a["num_colors"] == m["num_colors"] and a["num_rounds"] == m["num_rounds"]
         oc, ok, _, oL, _ = oracle.color_graph(rp, col, 1, 10, 5)
-        assert np.array_equal(m["color"], oc) and m["num_colors"] == ok and m["num_rounds"] == oL, i
+        da, dm = int((a["color"] != oc).sum()), int((m["color"] != oc).sum())
+        if a["status"] or m["status"] or da or dm or a["num_rounds"] != oL or m["num_rounds"] != oL:
+            bad.append(dict(request=i, n=rp.size - 1, nnz=col.size, status=(a["status"], m["status"]),
+                            wrong_alone=da, wrong_mix=dm, group=m["group_size"]))
+    print("requests that differ from the oracle:", bad, flush=True)
+    assert not bad
 
 
 @pytest.mark.gpu
