@@ -679,6 +679,11 @@ __device__ __forceinline__ bool is_pred(int cl) { return cl == NB_PRED || cl == 
 // 1 .. np+2 (GetColor's answer is at most np + 1).
 __device__ __forceinline__ unsigned bm_words(int np) { return (unsigned)(np + 2 + 31) / 32; }
 
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_excl_scan(T x, T* total) {
   const unsigned lane = lane_id();
@@ -832,9 +837,18 @@ __device__ void update_small(const Params& P, BmPool* pl, int v, bool valid, int
 
 // Wave-per-vertex UPDATE for longer rows: count pass (with the decrements),
 // then a placing pass.
+// Class masks a wavefront keeps between its count and placing passes: per
+// 64-entry chunk of a row (up to HUGE_DEG entries), the lanes holding
+// predecessors from later rounds, same-round predecessors and same-round
+// successors (the rest are earlier-round successors).
+constexpr int ROW_CHUNKS = HUGE_DEG / WAVE;
+struct RowMasks {
+  uint64_t m[ROW_CHUNKS][3];
+};
+
 template <bool FUSED>
-__device__ void update_big(const Params& P, BmPool* pl, L0Stage& l0s, int v, int l, unsigned char code,
-                           unsigned& x) {
+__device__ void update_big(const Params& P, BmPool* pl, L0Stage& l0s, RowMasks& rm, int v, int l,
+                           unsigned char code, unsigned& x) {
   const long long b = P.rp[v], e = P.rp[v + 1];
   if (e - b > HUGE_DEG) {  // a hub: its chunks are spread over the grid by k_update_huge_*
     if (lane_id() == 0) {
@@ -853,34 +867,41 @@ __device__ void update_big(const Params& P, BmPool* pl, L0Stage& l0s, int v, int
   const unsigned long long hv = same_key(P, v);
   const unsigned lane = lane_id();
   long long nl = 0, nps = 0, ns = 0;
-  // rows of up to 16 chunks keep their classes (2 bits per chunk and lane)
-  constexpr int KEEP = 16;
-  const bool keep = e - b <= (long long)KEEP * WAVE;
-  unsigned cls = 0;
-  for (long long base = b; base < e; base += WAVE) {
+  int ch = 0;
+  for (long long base = b; base < e; base += WAVE, ++ch) {
     long long j = base + lane;
     bool valid = j < e;
     int w = valid ? P.col[j] : 0;
     int cl = valid ? visit3<FUSED>(P, w, l, code, hv, x, !P.pull) : NB_NONE;
     if (FUSED) {
-      nl += __popcll(ballot(cl == NB_PRED));
-      nps += __popcll(ballot(cl == NB_PRED_SAME));
-      ns += __popcll(ballot(cl == NB_SUCC_SAME));
-      if (keep && valid) cls |= (unsigned)cl << (2 * ((base - b) / WAVE));
+      const uint64_t fm = ballot(cl == NB_PRED), gm = ballot(cl == NB_PRED_SAME), sm = ballot(cl == NB_SUCC_SAME);
+      nl += __popcll(fm);
+      nps += __popcll(gm);
+      ns += __popcll(sm);
+      if (lane == 0) {
+        rm.m[ch][0] = fm;
+        rm.m[ch][1] = gm;
+        rm.m[ch][2] = sm;
+      }
     }
   }
   if (!FUSED) return;
+  wave_sync();
   const long long np = nl + nps;
   long long fc = 0, gc = 0, sc = 0, lc = 0;
-  for (long long base = b; base < e; base += WAVE) {
+  ch = 0;
+  for (long long base = b; base < e; base += WAVE, ++ch) {
     long long j = base + lane;
     bool valid = j < e;
     int w = valid ? P.col[j] : 0;
-    int cl = !valid ? NB_NONE
-             : keep ? (int)(cls >> (2 * ((base - b) / WAVE))) & 3
-                    : visit3<FUSED>(P, w, l, code, hv, x, false);
-    uint64_t fm = ballot(cl == NB_PRED), gm = ballot(cl == NB_PRED_SAME), sm = ballot(cl == NB_SUCC_SAME),
-             lm = ballot(cl == NB_SUCC_EARLIER);
+    const uint64_t fm = rm.m[ch][0], gm = rm.m[ch][1], sm = rm.m[ch][2];
+    const uint64_t lm = ballot(valid) & ~(fm | gm | sm);
+    const uint64_t me = 1ull << lane;
+    const int cl = !valid ? NB_NONE
+                   : (fm & me) ? NB_PRED
+                   : (gm & me) ? NB_PRED_SAME
+                   : (sm & me) ? NB_SUCC_SAME
+                               : NB_SUCC_EARLIER;
     if (cl == NB_PRED) P.dag[b + fc + lanes_below(fm)] = w;
     else if (cl == NB_PRED_SAME) P.dag[b + nl + gc + lanes_below(gm)] = w;
     else if (cl == NB_SUCC_SAME) P.dag[b + np + sc + lanes_below(sm)] = w;
@@ -890,6 +911,7 @@ __device__ void update_big(const Params& P, BmPool* pl, L0Stage& l0s, int v, int
     sc += __popcll(sm);
     lc += __popcll(lm);
   }
+  wave_sync();   // the masks are rewritten by the wavefront's next row
   jp_row(P, pl, lane == 0, v, np, ns, nps);
   l0_stage(P, l0s, l, (long long)P.n - P.roundN[l], nps == 0, v);
 }
@@ -909,6 +931,8 @@ __global__ __launch_bounds__(BS) void k_update(Params P, int l) {
   unsigned x = 0;
   BmPool pool = {0, 0};
   L0Stage l0s = {0, 0};
+  __shared__ RowMasks rmask[FUSED ? WPB : 1];
+  RowMasks& rm = rmask[FUSED ? threadIdx.x / WAVE : 0];
   if (FUSED) pool = pool_load(P, gw);
   for (long long it = gw; it < items; it += gstride) {
     if (it < nsg) {
@@ -917,7 +941,7 @@ __global__ __launch_bounds__(BS) void k_update(Params P, int l) {
       int v = valid ? RL[idx] : 0;
       update_small<FUSED>(P, &pool, v, valid, l, code, x);
     } else {
-      update_big<FUSED>(P, &pool, l0s, RL[nRs + (it - nsg)], l, code, x);
+      update_big<FUSED>(P, &pool, l0s, rm, RL[nRs + (it - nsg)], l, code, x);
     }
   }
   if (FUSED) {
@@ -1297,11 +1321,6 @@ struct WaveLds {
   long long pb[WAVE];
   int ffree[WAVE];             // first clear bit found in the lanes' bitmaps
 };
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
 
 __device__ __forceinline__ int wave_owner(const WaveLds& W, int e) {
   int lo = 0, hi = WAVE;  // last k with off[k] <= e
