@@ -2388,6 +2388,10 @@ struct Layout {
 };
 
 constexpr int UPD_BLOCKS = 2048;
+#ifndef ADG_JP_GRID_BLOCKS
+#define ADG_JP_GRID_BLOCKS 1024
+#endif
+constexpr int JP_GRID_BLOCKS = ADG_JP_GRID_BLOCKS;   // launch size of the grid-wide JP steps
 constexpr int HUGE_BLOCKS = 1024;
 
 // Colour bitmap words: the rows need sum over v of ceil((bits+2)/32), bits =
@@ -2698,7 +2702,7 @@ int run_jp(Params& P, hipStream_t s, int rounds) {
       }
       {
         TIMED(KC_JP, s);
-        hipLaunchKernelGGL(k_jp_grid, dim3(P.upd_blocks), dim3(BS), 0, s, P);
+        hipLaunchKernelGGL(k_jp_grid, dim3(JP_GRID_BLOCKS), dim3(BS), 0, s, P);
       }
     }
     pairs += chunk;
