@@ -797,40 +797,88 @@ __device__ __forceinline__ void l0_stage(const Params& P, L0Stage& s, int l, lon
   if (s.cnt == WAVE) l0_flush(P, s, l, base);
 }
 
-// Lane-per-vertex UPDATE for rows of at most SMALL_DEG entries: one pass to
-// count (and decrement), one pass to place the row as [predecessors from
-// later rounds | same-round predecessors | same-round successors |
-// successors from earlier rounds].
+// UPDATE for a wavefront's 64 rows of at most SMALL_DEG entries each (one
+// vertex per lane).  The rows' entries are spread evenly over the lanes --
+// lane i of a pass takes entry p0 + i of the wavefront's concatenated rows,
+// its row found by binary search over the prefix sums -- so a pass has all
+// lanes busy whatever the row lengths.  Count pass: classify (and
+// decrement), keeping each entry's class and the per-row class counts in
+// LDS; placing pass: write the row as [predecessors from later rounds |
+// same-round predecessors | same-round successors | successors from earlier
+// rounds] (the order inside a part is arbitrary).
+struct SmallRows {
+  int off[WAVE + 1];                    // exclusive scan of the row lengths
+  long long b[WAVE];                    // first entry of each row
+  unsigned long long hv[WAVE];          // same-round key of each row's vertex
+  unsigned cnt[WAVE][4];                // entries per class (NB_*) and row
+  unsigned run[WAVE][4];                // entries placed so far
+  unsigned char cls[WAVE * SMALL_DEG];  // class of each entry
+};
+
+__device__ __forceinline__ int small_owner(const SmallRows& S, int pos) {
+  int lo = 0, hi = WAVE;  // the last row k with off[k] <= pos (rows before it may be empty)
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (S.off[mid] <= pos) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 template <bool FUSED>
-__device__ void update_small(const Params& P, BmPool* pl, int v, bool valid, int l, unsigned char code, unsigned& x) {
+__device__ void update_small(const Params& P, BmPool* pl, SmallRows& S, int v, bool valid, int l,
+                             unsigned char code, unsigned& x) {
+  const unsigned lane = lane_id();
   long long b = 0, e = 0;
   if (valid) {
     b = P.rp[v];
     e = P.rp[v + 1];
   }
-  const unsigned long long hv = same_key(P, v);
-  long long nl = 0, nps = 0, ns = 0;
-  unsigned long long cls = 0;   // the row's classes, 2 bits per entry (SMALL_DEG <= 32)
-  for (long long j = b; j < e; ++j) {
-    int cl = visit3<FUSED>(P, P.col[j], l, code, hv, x, !P.pull);
-    nl += cl == NB_PRED;
-    nps += cl == NB_PRED_SAME;
-    ns += cl == NB_SUCC_SAME;
-    cls |= (unsigned long long)cl << (2 * (j - b));
-  }
-  if (!FUSED) return;
-  const long long np = nl + nps;
-  if (valid) {
-    long long f = b, g = b + nl, s = b + np, r = e;
-    for (long long j = b; j < e; ++j) {
-      const int w = P.col[j];
-      const int cl = (int)(cls >> (2 * (j - b))) & 3;
-      if (cl == NB_PRED) P.dag[f++] = w;
-      else if (cl == NB_PRED_SAME) P.dag[g++] = w;
-      else if (cl == NB_SUCC_SAME) P.dag[s++] = w;
-      else P.dag[--r] = w;
+  int T;
+  const int off = wave_excl_scan<int>((int)(e - b), &T);
+  S.off[lane] = off;
+  S.b[lane] = b;
+  S.hv[lane] = same_key(P, v);
+  if (lane == 0) S.off[WAVE] = T;
+  if (FUSED)
+    for (int k = 0; k < 4; ++k) {
+      S.cnt[lane][k] = 0;
+      S.run[lane][k] = 0;
+    }
+  wave_sync();
+  for (int p0 = 0; p0 < T; p0 += WAVE) {
+    const int pos = p0 + (int)lane;
+    if (pos < T) {
+      const int k = small_owner(S, pos);
+      const int cl = visit3<FUSED>(P, P.col[S.b[k] + (pos - S.off[k])], l, code, S.hv[k], x, !P.pull);
+      if (FUSED) {
+        S.cls[pos] = (unsigned char)cl;
+        atomicAdd(&S.cnt[k][cl], 1u);
+      }
     }
   }
+  if (!FUSED) return;
+  wave_sync();
+  const long long nl = S.cnt[lane][NB_PRED], nps = S.cnt[lane][NB_PRED_SAME], ns = S.cnt[lane][NB_SUCC_SAME];
+  const long long np = nl + nps;
+  for (int p0 = 0; p0 < T; p0 += WAVE) {
+    const int pos = p0 + (int)lane;
+    if (pos < T) {
+      const int k = small_owner(S, pos);
+      const long long bk = S.b[k];
+      const int w = P.col[bk + (pos - S.off[k])];
+      const int cl = S.cls[pos];
+      const long long r = atomicAdd(&S.run[k][cl], 1u);
+      const long long nlk = S.cnt[k][NB_PRED], npk = nlk + S.cnt[k][NB_PRED_SAME];
+      long long at;
+      if (cl == NB_PRED) at = bk + r;
+      else if (cl == NB_PRED_SAME) at = bk + nlk + r;
+      else if (cl == NB_SUCC_SAME) at = bk + npk + r;
+      else at = bk + (S.off[k + 1] - S.off[k]) - 1 - r;
+      P.dag[at] = w;
+    }
+  }
+  wave_sync();   // the LDS is rewritten by the wavefront's next group of rows
   jp_row(P, pl, valid, v, np, ns, nps);
   l0_append(P, l, (long long)P.n - P.roundN[l], valid && nps == 0, v);
 }
@@ -931,17 +979,21 @@ __global__ __launch_bounds__(BS) void k_update(Params P, int l) {
   unsigned x = 0;
   BmPool pool = {0, 0};
   L0Stage l0s = {0, 0};
-  __shared__ RowMasks rmask[FUSED ? WPB : 1];
-  RowMasks& rm = rmask[FUSED ? threadIdx.x / WAVE : 0];
+  // per wavefront: the short rows' entry classes, or a long row's masks
+  __shared__ union WaveUpd {
+    SmallRows sr;
+    RowMasks rm;
+  } wu[WPB];
+  WaveUpd& U = wu[threadIdx.x / WAVE];
   if (FUSED) pool = pool_load(P, gw);
   for (long long it = gw; it < items; it += gstride) {
     if (it < nsg) {
       long long idx = it * WAVE + lane_id();
       bool valid = idx < nRs;
       int v = valid ? RL[idx] : 0;
-      update_small<FUSED>(P, &pool, v, valid, l, code, x);
+      update_small<FUSED>(P, &pool, U.sr, v, valid, l, code, x);
     } else {
-      update_big<FUSED>(P, &pool, l0s, rm, RL[nRs + (it - nsg)], l, code, x);
+      update_big<FUSED>(P, &pool, l0s, U.rm, RL[nRs + (it - nsg)], l, code, x);
     }
   }
   if (FUSED) {
