@@ -199,7 +199,8 @@ struct Params {
   int* npred;                  // |pred(v)|
   int* nsr;                    // same-round successors of v (JP levels walk these)
   int* cnt;                    // same-round predecessors of v not yet coloured
-  unsigned long long* rec;     // (colour bitmap offset << 32) | |pred(v)|
+  unsigned long long* rec;     // per vertex two words: (colour bitmap offset << 32) | |pred(v)|, and
+                               // (first same-round successor entry << 24) | same-round successors
   unsigned* B;                 // colour bitmaps (bm_words(|pred|) words per vertex)
   unsigned long long bm_cap;   // words of B
   unsigned long long* pool;    // per-wavefront bitmap pools of k_update / k_part1: (end << 32) | next
@@ -679,6 +680,24 @@ __device__ __forceinline__ bool is_pred(int cl) { return cl == NB_PRED || cl == 
 // 1 .. np+2 (GetColor's answer is at most np + 1).
 __device__ __forceinline__ unsigned bm_words(int np) { return (unsigned)(np + 2 + 31) / 32; }
 
+// A vertex's JP record: its bitmap word, and where its same-round successors
+// are, in one 16-byte read.  Successor counts from 2^24 - 1 up are read from
+// nsr instead.
+struct JpRec {
+  unsigned long long rec, sp;
+};
+constexpr unsigned SP_NS_MAX = (1u << 24) - 1;
+__device__ __forceinline__ unsigned long long rec_of(const Params& P, int v) { return P.rec[2 * (size_t)v]; }
+__device__ __forceinline__ JpRec rec_pair(const Params& P, int v) {
+  const ulonglong2 x = *reinterpret_cast<const ulonglong2*>(P.rec + 2 * (size_t)v);
+  return {x.x, x.y};
+}
+__device__ __forceinline__ long long sp_first(unsigned long long sp) { return (long long)(sp >> 24); }
+__device__ __forceinline__ int sp_count(const Params& P, int v, unsigned long long sp) {
+  const unsigned ns = (unsigned)sp & SP_NS_MAX;
+  return ns < SP_NS_MAX ? (int)ns : P.nsr[v];
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -738,8 +757,8 @@ __device__ __forceinline__ unsigned long long pool_alloc(const Params& P, BmPool
 // to be coloured (cnt = nps), and a cleared colour bitmap from the
 // wavefront's pool (pl) or the bump counter (pl = nullptr);
 // rec[v] = (bitmap offset << 32) | np.
-__device__ __forceinline__ void jp_row(const Params& P, BmPool* pl, bool has, int v, long long np, long long ns,
-                                       long long nps) {
+__device__ __forceinline__ void jp_row(const Params& P, BmPool* pl, bool has, int v, long long b, long long np,
+                                       long long ns, long long nps) {
   // JP: bits for colours 1 .. np+2; DEC-ADG-ITR: also the same-round successors
   const long long nb = P.dec ? np + ns : np;
   const unsigned w = has ? bm_words((int)nb) : 0;
@@ -760,7 +779,9 @@ __device__ __forceinline__ void jp_row(const Params& P, BmPool* pl, bool has, in
   P.npred[v] = (int)np;
   P.nsr[v] = (int)ns;
   P.cnt[v] = (int)nps;
-  P.rec[v] = (off << 32) | (unsigned)(P.dec ? np + ns : np);
+  P.rec[2 * (size_t)v] = (off << 32) | (unsigned)(P.dec ? np + ns : np);
+  P.rec[2 * (size_t)v + 1] =
+      ((unsigned long long)(b + np) << 24) | (ns < (long long)SP_NS_MAX ? (unsigned)ns : SP_NS_MAX);
 }
 
 // Wavefront: append the lanes' vertices with z set to the first JP level of
@@ -879,7 +900,7 @@ __device__ void update_small(const Params& P, BmPool* pl, SmallRows& S, int v, b
     }
   }
   wave_sync();   // the LDS is rewritten by the wavefront's next group of rows
-  jp_row(P, pl, valid, v, np, ns, nps);
+  jp_row(P, pl, valid, v, b, np, ns, nps);
   l0_append(P, l, (long long)P.n - P.roundN[l], valid && nps == 0, v);
 }
 
@@ -960,7 +981,7 @@ __device__ void update_big(const Params& P, BmPool* pl, L0Stage& l0s, RowMasks& 
     lc += __popcll(lm);
   }
   wave_sync();   // the masks are rewritten by the wavefront's next row
-  jp_row(P, pl, lane == 0, v, np, ns, nps);
+  jp_row(P, pl, lane == 0, v, b, np, ns, nps);
   l0_stage(P, l0s, l, (long long)P.n - P.roundN[l], nps == 0, v);
 }
 
@@ -1162,7 +1183,7 @@ __global__ __launch_bounds__(BS) void k_update_huge_place(Params P, int l) {
       }
     }
     if (k == first) {
-      jp_row(P, nullptr, lane == 0, v, np, ns, nps);
+      jp_row(P, nullptr, lane == 0, v, b, np, ns, nps);
       l0_append(P, l, (long long)P.n - P.roundN[l], lane == 0 && nps == 0, v);
     }
   }
@@ -1202,7 +1223,7 @@ __global__ __launch_bounds__(BS) void k_part1(Params P) {
       }
       np = f - b;
     }
-    jp_row(P, &pool, small, v, np, (e - b) - np, np);
+    jp_row(P, &pool, small, v, b, np, (e - b) - np, np);
     l0_append(P, 1, 0, small && np == 0, v);
     uint64_t big = ballot(valid && !small);
     while (big) {
@@ -1223,7 +1244,7 @@ __global__ __launch_bounds__(BS) void k_part1(Params P) {
         fc += __popcll(pm);
         sc += __popcll(sm);
       }
-      jp_row(P, &pool, lane == 0, u, fc, sc, fc);
+      jp_row(P, &pool, lane == 0, u, ub, fc, sc, fc);
       l0_stage(P, l0s, 1, 0, fc == 0, u);
     }
   }
@@ -1484,7 +1505,7 @@ __device__ void jp_xpull_items(const Params& P, WaveLds& W, int r, long long gw,
     if (ok) {
       const int v = P.ORD[b + i];
       x = P.npred[v] - P.cnt[v];   // predecessors from later rounds (cnt is untouched until the round starts)
-      W.rec[lane] = P.rec[v];
+      W.rec[lane] = rec_of(P, v);
       W.pb[lane] = P.rp[v];
     }
     int tot;
@@ -1540,7 +1561,7 @@ __device__ __forceinline__ void jp_push_range(const Params& P, JpStage& st, int 
       u[t] = ok[t] ? P.dag[j] : 0;
     }
 #pragma unroll
-    for (int t = 0; t < JP_UNROLL; ++t) rc[t] = ok[t] ? P.rec[u[t]] : 0;
+    for (int t = 0; t < JP_UNROLL; ++t) rc[t] = ok[t] ? rec_of(P, u[t]) : 0;
     bool rdy[JP_UNROLL];
 #pragma unroll
     for (int t = 0; t < JP_UNROLL; ++t) rdy[t] = ok[t] && jp_push<SC_AGENT>(P, u[t], rc[t], cc);
@@ -1568,9 +1589,10 @@ __device__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, 
       unsigned long long rec = 0;
       long long s0 = 0, s1 = 0;
       if (act) {
-        rec = P.rec[v];
-        s0 = P.rp[v] + (int)(unsigned)rec;
-        s1 = s0 + P.nsr[v];
+        const JpRec pr = rec_pair(P, v);
+        rec = pr.rec;
+        s0 = sp_first(pr.sp);
+        s1 = s0 + sp_count(P, v, pr.sp);
       }
       const int col = wave_colour(P, W, act, rec);
       if (act) sti<SC_AGENT>(&P.color[v], col);
@@ -1584,7 +1606,7 @@ __device__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, 
           u[t] = ok[t] ? P.dag[j + t] : 0;
         }
 #pragma unroll
-        for (int t = 0; t < JP_UNROLL; ++t) rc[t] = ok[t] ? P.rec[u[t]] : 0;
+        for (int t = 0; t < JP_UNROLL; ++t) rc[t] = ok[t] ? rec_of(P, u[t]) : 0;
         bool rdy[JP_UNROLL];
 #pragma unroll
         for (int t = 0; t < JP_UNROLL; ++t) rdy[t] = ok[t] && jp_push<SC_AGENT>(P, u[t], rc[t], col);
@@ -1596,7 +1618,8 @@ __device__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, 
       const unsigned long long ent = fan_entry<SC_AGENT>(Hl, nh, k, hlds);
       const int v = (int)(unsigned)ent;
       const unsigned first = (unsigned)(ent >> 32);
-      const unsigned long long rec = P.rec[v];
+      const JpRec pr = rec_pair(P, v);
+      const unsigned long long rec = pr.rec;
       // the whole wavefront reads v's bitmap: first clear bit
       const unsigned nw = bm_words((int)(unsigned)rec);
       int col = 0;
@@ -1616,7 +1639,7 @@ __device__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, 
         col = (int)(unsigned)rec + 1;
       }
       if (k == first && lane == 0) sti<SC_AGENT>(&P.color[v], col);
-      const long long b = P.rp[v] + (int)(unsigned)rec, e = b + P.nsr[v];
+      const long long b = sp_first(pr.sp), e = b + sp_count(P, v, pr.sp);
       const long long s0 = b + (long long)(k - first) * JP_CHUNK;
       const long long s1 = s0 + JP_CHUNK < e ? s0 + JP_CHUNK : e;
       jp_push_range(P, st, l, col, s0, s1);
@@ -1679,7 +1702,8 @@ struct NarrowLds {
 // past its capacity, to the global lists of level l + 1.  One LDS atomic per
 // wavefront.
 __device__ __forceinline__ void narrow_append(const Params& P, NarrowLds& Z, JpStage& st, int nx, int l,
-                                              const bool* rdy, const int* u, const unsigned long long* urec) {
+                                              const bool* rdy, const int* u, const unsigned long long* urec,
+                                              const unsigned long long* usp) {
   uint64_t m[NARROW_UNROLL];
   unsigned tot = 0;
 #pragma unroll
@@ -1691,9 +1715,9 @@ __device__ __forceinline__ void narrow_append(const Params& P, NarrowLds& Z, JpS
   long long pb[NARROW_UNROLL];
   int ns[NARROW_UNROLL];
 #pragma unroll
-  for (int q = 0; q < NARROW_UNROLL; ++q) {
-    pb[q] = rdy[q] ? P.rp[u[q]] : 0;
-    ns[q] = rdy[q] ? P.nsr[u[q]] : 0;
+  for (int q = 0; q < NARROW_UNROLL; ++q) {   // row start and successors from the record
+    pb[q] = rdy[q] ? sp_first(usp[q]) - (long long)(unsigned)urec[q] : 0;
+    ns[q] = rdy[q] ? sp_count(P, u[q], usp[q]) : 0;
   }
   unsigned base = 0;
   if (lane_id() == 0) base = atomicAdd(&Z.cnt[nx], tot);
@@ -1749,20 +1773,22 @@ __device__ void narrow_flush(const Params& P, NarrowLds& Z, JpStage& st, int cur
 __device__ void narrow_load(const Params& P, NarrowLds& Z, int cur, const unsigned* src, unsigned n) {
   for (unsigned i = threadIdx.x; i < n; i += NARROW_BS) {
     const int v = (int)ld32<SC_AGENT>(&src[i]);
+    const JpRec pr = rec_pair(P, v);
     Z.v[cur][i] = v;
-    Z.pb[cur][i] = P.rp[v];
-    Z.rec[cur][i] = P.rec[v];
-    Z.ns[cur][i] = P.nsr[v];
+    Z.pb[cur][i] = sp_first(pr.sp) - (long long)(unsigned)pr.rec;
+    Z.rec[cur][i] = pr.rec;
+    Z.ns[cur][i] = sp_count(P, v, pr.sp);
   }
 }
 __device__ void narrow_load_fan(const Params& P, NarrowLds& Z, int cur, const unsigned long long* src, unsigned n,
                                 unsigned at) {
   for (unsigned i = threadIdx.x; i < n; i += NARROW_BS) {
     const int v = (int)(unsigned)ld64<SC_AGENT>(&src[i]);
+    const JpRec pr = rec_pair(P, v);
     Z.v[cur][at + i] = v;
-    Z.pb[cur][at + i] = P.rp[v];
-    Z.rec[cur][at + i] = P.rec[v];
-    Z.ns[cur][at + i] = P.nsr[v];
+    Z.pb[cur][at + i] = sp_first(pr.sp) - (long long)(unsigned)pr.rec;
+    Z.rec[cur][at + i] = pr.rec;
+    Z.ns[cur][at + i] = sp_count(P, v, pr.sp);
   }
 }
 
@@ -1834,7 +1860,7 @@ __device__ bool narrow_level(const Params& P, NarrowLds& Z, JpStage& st, int cur
   // pass fetched meanwhile
   int su[NARROW_UNROLL];
   unsigned sk[NARROW_UNROLL];
-  unsigned long long sr[NARROW_UNROLL];
+  unsigned long long sr[NARROW_UNROLL], ssp[NARROW_UNROLL];
 #pragma unroll
   for (int q = 0; q < NARROW_UNROLL; ++q) {
     const unsigned e = q * NARROW_BS + t;
@@ -1866,7 +1892,11 @@ __device__ bool narrow_level(const Params& P, NarrowLds& Z, JpStage& st, int cur
       }
   }
 #pragma unroll
-  for (int q = 0; q < NARROW_UNROLL; ++q) sr[q] = su[q] >= 0 ? P.rec[su[q]] : 0;
+  for (int q = 0; q < NARROW_UNROLL; ++q) {
+    const JpRec pr = su[q] >= 0 ? rec_pair(P, su[q]) : JpRec{0, 0};
+    sr[q] = pr.rec;
+    ssp[q] = pr.sp;
+  }
   __syncthreads();
   // GetColor
   if (t < nv) {
@@ -1896,12 +1926,16 @@ __device__ bool narrow_level(const Params& P, NarrowLds& Z, JpStage& st, int cur
         }
       }
 #pragma unroll
-      for (int q = 0; q < NARROW_UNROLL; ++q) sr[q] = su[q] >= 0 ? P.rec[su[q]] : 0;
+      for (int q = 0; q < NARROW_UNROLL; ++q) {
+        const JpRec pr = su[q] >= 0 ? rec_pair(P, su[q]) : JpRec{0, 0};
+        sr[q] = pr.rec;
+        ssp[q] = pr.sp;
+      }
     }
     bool rdy[NARROW_UNROLL];
 #pragma unroll
     for (int q = 0; q < NARROW_UNROLL; ++q) rdy[q] = su[q] >= 0 && jp_push<SC_WG>(P, su[q], sr[q], Z.col[sk[q]]);
-    narrow_append(P, Z, st, nx, l, rdy, su, sr);
+    narrow_append(P, Z, st, nx, l, rdy, su, sr, ssp);
   }
   order_point();
   __syncthreads();
@@ -2153,7 +2187,7 @@ __global__ __launch_bounds__(BS) void k_dec_pull(Params P) {
     if (has) {
       b = P.rp[v];
       e = b + (P.npred[v] - P.cnt[v]);
-      rec = P.rec[v];
+      rec = rec_of(P, v);
     }
     // the wavefront walks long rows together; each entry marks in its row's bitmap
     const bool longrow = has && e - b > WAVE;
@@ -2178,7 +2212,7 @@ __global__ __launch_bounds__(BS) void k_dec_pick(Params P) {
   const int* U = dec_list(P, d);
   for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < d.ucnt; i += (long long)gridDim.x * BS) {
     const int v = U[i];
-    const unsigned long long rec = P.rec[v];
+    const unsigned long long rec = rec_of(P, v);
     const unsigned nw = bm_words((int)(unsigned)rec);
     unsigned c = 0;
     for (unsigned w = 0; w < nw; ++w) {
@@ -2244,14 +2278,14 @@ __global__ __launch_bounds__(BS) void k_dec_resolve(Params P) {
     const long long pb = keep ? b : 0, pe = keep ? e2 : 0;
     const bool longpush = keep && pe - pb > WAVE;
     if (keep && !longpush)
-      for (long long j = pb; j < pe; ++j) bm_mark<SC_AGENT>(P, P.rec[P.dag[j]], (int)tv);
+      for (long long j = pb; j < pe; ++j) bm_mark<SC_AGENT>(P, rec_of(P, P.dag[j]), (int)tv);
     m = ballot(longpush);
     while (m) {
       const int src = __ffsll((long long)m) - 1;
       m &= m - 1;
       const long long bb = readlane_i64(pb, src), ee = readlane_i64(pe, src);
       const int ts = (int)readlane_u(tv, src);
-      for (long long j = bb + lane_id(); j < ee; j += WAVE) bm_mark<SC_AGENT>(P, P.rec[P.dag[j]], ts);
+      for (long long j = bb + lane_id(); j < ee; j += WAVE) bm_mark<SC_AGENT>(P, rec_of(P, P.dag[j]), ts);
     }
     // the others form the next U
     const uint64_t lm = ballot(has && lose);
@@ -2485,7 +2519,7 @@ Layout make_layout(int64_t n, int64_t nnz) {
   L.npred = take(4 * nn);
   L.nsr = take(4 * nn);
   L.cnt = take(4 * nn);
-  L.rec = take(8 * nn);
+  L.rec = take(16 * nn);
   bm_capacity(n, nnz, &L.bm_cap, &L.pool_chunk);
   L.B = take(4 * L.bm_cap);
   L.L0 = take(4 * nn);
