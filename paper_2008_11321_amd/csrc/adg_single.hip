@@ -119,15 +119,16 @@ struct JpState {
   unsigned long long ssum[3];  // same-round successors summed over each level's vertices
 };
 
-// DEC-ADG-ITR progress (between kernels).
+// DEC-ADG-ITR progress (between kernels), double-buffered by iteration
+// parity: the kernels of iteration k read dec[k & 1] and the last block of
+// its resolve step writes dec[(k + 1) & 1], so a launch's state never
+// changes while its blocks may still be starting.
 struct DecState {
   int round;                   // partition being coloured (L .. 1)
   int first;                   // its first iteration: U is the partition's ORD slot
   int pull;                    // the partition still has to pull its later-round colours
   int cur;                     // U of later iterations: UL[cur]
   unsigned ucnt;               // |U|
-  unsigned unext;              // vertices that gave up their colour (the next U)
-  unsigned blocks;             // blocks of k_dec_resolve done (last-block hand-off)
   int done;
   long long iters;             // iterations run, all partitions
 };
@@ -164,7 +165,9 @@ struct Ctrl {
   unsigned int msel_blocks;    // blocks of the current pass that have added their histogram
   int msel_found;
   JpState js;
-  DecState dec;
+  DecState dec[2];
+  unsigned dec_unext;          // vertices that gave up their colour (the next U)
+  unsigned dec_blocks;         // working blocks of k_dec_resolve done (last-block hand-off)
 };
 
 struct Params {
@@ -284,10 +287,12 @@ __global__ void k_init(Params P) {
   c->msel_prefix = c->msel_mask = c->msel_k = 0;
   c->msel_blocks = 0;
   c->msel_found = 0;
-  c->dec.done = 0;
-  c->dec.iters = 0;
-  c->dec.blocks = 0;
-  c->dec.unext = 0;
+  for (int k = 0; k < 2; ++k) {
+    c->dec[k].done = 0;
+    c->dec[k].iters = 0;
+  }
+  c->dec_blocks = 0;
+  c->dec_unext = 0;
   JpState& j = c->js;
   j.round = 0;
   j.level = 0;
@@ -2159,22 +2164,30 @@ __device__ __forceinline__ const int* dec_list(const Params& P, const DecState& 
 
 __global__ void k_dec_start(Params P, int rounds) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  DecState& d = P.ctrl->dec;
+  DecState& d = P.ctrl->dec[0];
   d.round = rounds;
   d.first = 1;
   d.pull = 1;
   d.cur = 0;
   d.ucnt = rounds > 0 ? P.roundN[rounds] - P.roundN[rounds + 1] : 0;
-  d.unext = 0;
-  d.blocks = 0;
   d.done = rounds == 0;
   d.iters = 0;
+  P.ctrl->dec[1] = d;
+  P.ctrl->dec_unext = 0;
+  P.ctrl->dec_blocks = 0;
+}
+
+// Blocks of a DEC step with items to take (the others leave at once).
+__device__ __forceinline__ long long dec_active(unsigned ucnt) {
+  long long a = ((long long)ucnt + BS - 1) / BS;
+  if (a < 1) a = 1;
+  return a < (long long)gridDim.x ? a : (long long)gridDim.x;
 }
 
 // Before a partition's first iteration: OR the colours of every neighbour in
 // a later round (all final) into the vertex's bitmap.
-__global__ __launch_bounds__(BS) void k_dec_pull(Params P) {
-  const DecState d = P.ctrl->dec;
+__global__ __launch_bounds__(BS) void k_dec_pull(Params P, int p) {
+  const DecState d = P.ctrl->dec[p];
   if (d.done || !d.pull) return;
   const int* U = dec_list(P, d);
   const long long stride = (long long)gridDim.x * BS;
@@ -2205,10 +2218,10 @@ __global__ __launch_bounds__(BS) void k_dec_pull(Params P) {
 }
 
 // Part 1: every vertex of U tries the smallest colour not in its bitmap.
-__global__ __launch_bounds__(BS) void k_dec_pick(Params P) {
-  const DecState d = P.ctrl->dec;
+__global__ __launch_bounds__(BS) void k_dec_pick(Params P, int p) {
+  const DecState d = P.ctrl->dec[p];
   if (d.done) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) P.ctrl->dec.pull = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) P.ctrl->dec[p].pull = 0;
   const int* U = dec_list(P, d);
   for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < d.ucnt; i += (long long)gridDim.x * BS) {
     const int v = U[i];
@@ -2235,10 +2248,15 @@ __global__ __launch_bounds__(BS) void k_dec_pick(Params P) {
 // (a same-round neighbour with a larger hash) tried the same one; kept
 // colours go into the bitmaps of the same-round neighbours, the others form
 // the next U.  The last block moves to the next iteration or partition.
-__global__ __launch_bounds__(BS) void k_dec_resolve(Params P) {
+__global__ __launch_bounds__(BS) void k_dec_resolve(Params P, int p) {
   Ctrl* c = P.ctrl;
-  const DecState d = c->dec;
-  if (d.done) return;
+  const DecState d = c->dec[p];
+  if (d.done) {   // carry the end forward to the other parity
+    if (blockIdx.x == 0 && threadIdx.x == 0) c->dec[p ^ 1].done = 1;
+    return;
+  }
+  const long long active = dec_active(d.ucnt);
+  if ((long long)blockIdx.x >= active) return;
   const int* U = dec_list(P, d);
   int* Unext = P.UL[d.cur ^ 1];
   __shared__ int last;
@@ -2292,7 +2310,7 @@ __global__ __launch_bounds__(BS) void k_dec_resolve(Params P) {
     if (lm) {
       const int leader = __ffsll((long long)lm) - 1;
       unsigned at = 0;
-      if (lane_id() == (unsigned)leader) at = atomicAdd(&c->dec.unext, (unsigned)__popcll(lm));
+      if (lane_id() == (unsigned)leader) at = atomicAdd(&c->dec_unext, (unsigned)__popcll(lm));
       at = readlane_u(at, leader);
       if (has && lose) Unext[at + lanes_below(lm)] = v;
     }
@@ -2300,15 +2318,16 @@ __global__ __launch_bounds__(BS) void k_dec_resolve(Params P) {
   __threadfence();
   __syncthreads();
   if (threadIdx.x == 0)
-    last = __hip_atomic_fetch_add(&c->dec.blocks, 1u, __ATOMIC_ACQ_REL, SC_AGENT) == gridDim.x - 1;
+    last = __hip_atomic_fetch_add(&c->dec_blocks, 1u, __ATOMIC_ACQ_REL, SC_AGENT) == (unsigned)(active - 1);
   __syncthreads();
   if (!last || threadIdx.x != 0) return;
   __threadfence();
-  DecState& g = c->dec;
-  g.blocks = 0;
+  DecState g = d;
+  g.pull = c->dec[p].pull;
   g.iters += 1;
-  const unsigned nx = __hip_atomic_load(&g.unext, __ATOMIC_RELAXED, SC_AGENT);
-  g.unext = 0;
+  const unsigned nx = __hip_atomic_load(&c->dec_unext, __ATOMIC_RELAXED, SC_AGENT);
+  c->dec_unext = 0;
+  c->dec_blocks = 0;
   if (nx > 0) {
     g.ucnt = nx;
     g.cur ^= 1;
@@ -2321,6 +2340,7 @@ __global__ __launch_bounds__(BS) void k_dec_resolve(Params P) {
   } else {
     g.done = 1;
   }
+  c->dec[p ^ 1] = g;
 }
 
 __global__ __launch_bounds__(BS) void k_max_color(Params P) {
@@ -2827,13 +2847,15 @@ int run_dec(Params& P, hipStream_t s, int rounds) {
   while (true) {
     for (int k = 0; k < chunk; ++k) {
       TIMED(KC_DEC, s);
-      hipLaunchKernelGGL(k_dec_pull, dim3(P.upd_blocks), dim3(BS), 0, s, P);
-      hipLaunchKernelGGL(k_dec_pick, dim3(P.upd_blocks), dim3(BS), 0, s, P);
-      hipLaunchKernelGGL(k_dec_resolve, dim3(P.upd_blocks), dim3(BS), 0, s, P);
+      const int p = (int)((triples + k) & 1);
+      hipLaunchKernelGGL(k_dec_pull, dim3(P.upd_blocks), dim3(BS), 0, s, P, p);
+      hipLaunchKernelGGL(k_dec_pick, dim3(P.upd_blocks), dim3(BS), 0, s, P, p);
+      hipLaunchKernelGGL(k_dec_resolve, dim3(P.upd_blocks), dim3(BS), 0, s, P, p);
     }
     triples += chunk;
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(&h[0], &P.ctrl->dec.done, sizeof(int), hipMemcpyDeviceToHost, s));
+    // the state the next triple reads (triples is even here, chunks being even)
+    HIPCHK(hipMemcpyAsync(&h[0], &P.ctrl->dec[triples & 1].done, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(&h[1], &P.ctrl->error, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (h[1]) return h[1];
@@ -2995,7 +3017,7 @@ int adg_get_stats(const void* workspace, size_t ws_bytes, adg_stats_t* out, void
   out->sum_active = (int64_t)h.sum_active;
   out->cut_edges = (int64_t)h.cut_edges;
   out->frontier = (int64_t)h.js.F;
-  out->jp_levels = h.js.levels + h.dec.iters;
+  out->jp_levels = h.js.levels + std::max(h.dec[0].iters, h.dec[1].iters);
   out->error = h.error;
   return ADG_OK;
 }
