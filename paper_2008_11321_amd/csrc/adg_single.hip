@@ -458,6 +458,12 @@ __global__ __launch_bounds__(BS) void k_msel(Params P, int l, int pass) {
   const unsigned width = pass == MSEL_PASSES - 1 ? 9 : 11;
   const unsigned long long dmask = ((1ull << width) - 1) << shift;
   const unsigned long long N = c->N, mask = c->msel_mask, prefix = c->msel_prefix;
+  // blocks with keys to count; the others leave at once (N does not change
+  // during the selection, so every block counts them alike)
+  long long active = ((long long)N + BS - 1) / BS;
+  if (active < 1) active = 1;
+  if (active > (long long)gridDim.x) active = gridDim.x;
+  if ((long long)blockIdx.x >= active) return;
   const int* Uin = P.UL[(l + 1) & 1];
   for (int k = threadIdx.x; k < MSEL_BINS; k += BS) hist[k] = 0;
   __syncthreads();
@@ -473,7 +479,7 @@ __global__ __launch_bounds__(BS) void k_msel(Params P, int l, int pass) {
   __threadfence();
   __syncthreads();
   if (threadIdx.x == 0)
-    last = __hip_atomic_fetch_add(&c->msel_blocks, 1u, __ATOMIC_ACQ_REL, SC_AGENT) == gridDim.x - 1;
+    last = __hip_atomic_fetch_add(&c->msel_blocks, 1u, __ATOMIC_ACQ_REL, SC_AGENT) == (unsigned)(active - 1);
   __syncthreads();
   if (!last) return;
   __threadfence();
