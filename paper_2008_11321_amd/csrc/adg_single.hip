@@ -154,7 +154,6 @@ struct Ctrl {
   unsigned long long huge_ctr; // rows of the round cut into chunks (low 32 bits) and their chunks (high)
   unsigned long long xhuge;    // decrements done by the chunked rows
   int grid_op;                 // OP_* the grid kernel has to run next
-  int grid_ran;                // the grid kernel has run grid_op
   int num_colors;
   int pad_jp;
   // ADG-M radix selection of round l: keys whose masked bits are below
@@ -279,7 +278,6 @@ __global__ void k_init(Params P) {
   c->error = 0;
   c->stats_round = 0;
   c->grid_op = OP_NONE;
-  c->grid_ran = 0;
   c->num_colors = 0;
   c->bm_next = 0;
   c->huge_ctr = 0;
@@ -1965,9 +1963,10 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_narrow(Params P, int max_steps
   if (threadIdx.x == 0) {
     S = c->js;
     have = 0;
-    if (!S.done && c->grid_ran) {
+    // launches alternate (single-block, grid): the op posted by the previous
+    // single-block launch has been run by the grid launch between them
+    if (!S.done) {
       const int op = c->grid_op;
-      c->grid_ran = 0;
       c->grid_op = OP_NONE;
       if (op == OP_XPULL) S.xpull = 0;
       else if (op == OP_SPLIT) S.split = 0;
@@ -2100,8 +2099,10 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_narrow(Params P, int max_steps
 // Grid-wide: the step the single-block kernel handed over.
 __global__ __launch_bounds__(BS) void k_jp_grid(Params P) {
   Ctrl* c = P.ctrl;
+  // Every block decides from state no block of this launch changes: blocks
+  // may start after others have finished (other streams' kernels hold CUs).
   const int op = c->grid_op;
-  if (c->js.done || op == OP_NONE || c->grid_ran) return;
+  if (c->js.done || op == OP_NONE) return;
   {
     // blocks past the step's work leave at once (block 0 stays: it reports)
     const int r = c->js.round, l = c->js.level;
@@ -2139,14 +2140,12 @@ __global__ __launch_bounds__(BS) void k_jp_grid(Params P) {
     jp_level_items(P, st, W, l, c->js.fcnt[l % 3], hc, gw, gstride, hl);
     jp_stage_flush<SC_AGENT>(P, st, l);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) c->grid_ran = 1;
 }
 
 __global__ void k_jp_start(Params P, int rounds) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   Ctrl* c = P.ctrl;
   c->grid_op = OP_NONE;
-  c->grid_ran = 0;
   JpState& j = c->js;
   j.done = 0;
   j.levels = 0;
