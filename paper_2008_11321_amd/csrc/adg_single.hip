@@ -1555,30 +1555,6 @@ __device__ void jp_split_items(const Params& P, JpStage& st, int r, long long gw
   }
 }
 
-// Whole wavefront: push colour cc to the same-round successors dag[s0 .. s1).
-__device__ __forceinline__ void jp_push_range(const Params& P, JpStage& st, int l, int cc, long long s0,
-                                              long long s1) {
-  const unsigned lane = lane_id();
-  for (long long base = s0; base < s1; base += WAVE * JP_UNROLL) {
-    int u[JP_UNROLL];
-    bool ok[JP_UNROLL];
-    unsigned long long rc[JP_UNROLL];
-#pragma unroll
-    for (int t = 0; t < JP_UNROLL; ++t) {
-      const long long j = base + t * WAVE + lane;
-      ok[t] = j < s1;
-      u[t] = ok[t] ? P.dag[j] : 0;
-    }
-#pragma unroll
-    for (int t = 0; t < JP_UNROLL; ++t) rc[t] = ok[t] ? rec_of(P, u[t]) : 0;
-    bool rdy[JP_UNROLL];
-#pragma unroll
-    for (int t = 0; t < JP_UNROLL; ++t) rdy[t] = ok[t] && jp_push<SC_AGENT>(P, u[t], rc[t], cc);
-#pragma unroll
-    for (int t = 0; t < JP_UNROLL; ++t) jp_append<SC_AGENT>(P, st, l, rdy[t], u[t]);
-  }
-}
-
 // The work items of wide level l: groups of 64 plain vertices (colour and
 // successors a lane each), then the fan-out chunks (each chunk reads its
 // vertex's bitmap; the one that starts the range stores the colour).
@@ -1603,16 +1579,24 @@ __device__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, 
         s0 = sp_first(pr.sp);
         s1 = s0 + sp_count(P, v, pr.sp);
       }
+      // the first successors are fetched together with the bitmap words
+      int u[JP_UNROLL];
+      bool ok[JP_UNROLL];
+#pragma unroll
+      for (int t = 0; t < JP_UNROLL; ++t) {
+        ok[t] = act && s0 + t < s1;
+        u[t] = ok[t] ? P.dag[s0 + t] : 0;
+      }
       const int col = wave_colour(P, W, act, rec);
       if (act) sti<SC_AGENT>(&P.color[v], col);
       for (long long j = s0; ballot(act && j < s1); j += JP_UNROLL) {
-        int u[JP_UNROLL];
-        bool ok[JP_UNROLL];
         unsigned long long rc[JP_UNROLL];
+        if (j != s0) {
 #pragma unroll
-        for (int t = 0; t < JP_UNROLL; ++t) {
-          ok[t] = act && j + t < s1;
-          u[t] = ok[t] ? P.dag[j + t] : 0;
+          for (int t = 0; t < JP_UNROLL; ++t) {
+            ok[t] = act && j + t < s1;
+            u[t] = ok[t] ? P.dag[j + t] : 0;
+          }
         }
 #pragma unroll
         for (int t = 0; t < JP_UNROLL; ++t) rc[t] = ok[t] ? rec_of(P, u[t]) : 0;
@@ -1629,6 +1613,19 @@ __device__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, 
       const unsigned first = (unsigned)(ent >> 32);
       const JpRec pr = rec_pair(P, v);
       const unsigned long long rec = pr.rec;
+      // the chunk's successors (one wavefront step) are fetched together
+      // with the bitmap words
+      const long long b = sp_first(pr.sp), e = b + sp_count(P, v, pr.sp);
+      const long long s0 = b + (long long)(k - first) * JP_CHUNK;
+      const long long s1 = s0 + JP_CHUNK < e ? s0 + JP_CHUNK : e;
+      int u[JP_UNROLL];
+      bool ok[JP_UNROLL];
+#pragma unroll
+      for (int t = 0; t < JP_UNROLL; ++t) {
+        const long long j = s0 + t * WAVE + lane;
+        ok[t] = j < s1;
+        u[t] = ok[t] ? P.dag[j] : 0;
+      }
       // the whole wavefront reads v's bitmap: first clear bit
       const unsigned nw = bm_words((int)(unsigned)rec);
       int col = 0;
@@ -1648,10 +1645,14 @@ __device__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, 
         col = (int)(unsigned)rec + 1;
       }
       if (k == first && lane == 0) sti<SC_AGENT>(&P.color[v], col);
-      const long long b = sp_first(pr.sp), e = b + sp_count(P, v, pr.sp);
-      const long long s0 = b + (long long)(k - first) * JP_CHUNK;
-      const long long s1 = s0 + JP_CHUNK < e ? s0 + JP_CHUNK : e;
-      jp_push_range(P, st, l, col, s0, s1);
+      unsigned long long rc[JP_UNROLL];
+#pragma unroll
+      for (int t = 0; t < JP_UNROLL; ++t) rc[t] = ok[t] ? rec_of(P, u[t]) : 0;
+      bool rdy[JP_UNROLL];
+#pragma unroll
+      for (int t = 0; t < JP_UNROLL; ++t) rdy[t] = ok[t] && jp_push<SC_AGENT>(P, u[t], rc[t], col);
+#pragma unroll
+      for (int t = 0; t < JP_UNROLL; ++t) jp_append<SC_AGENT>(P, st, l, rdy[t], u[t]);
     }
   }
 }
