@@ -712,17 +712,28 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Inclusive prefix sum over the 64 lanes with DPP moves (no LDS round trip):
+// sums of 4 lanes, then 8 and 16 inside each row of 16, then the rows' totals
+// carried forward by the row broadcasts of lanes 15 and 31.  Lanes whose DPP
+// source is outside the row or masked off add 0.
+__device__ __forceinline__ unsigned wave_incl_scan_u32(unsigned x) {
+  int v = (int)x;
+  v += __builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false) +   // row_shr:1
+       __builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false) +   // row_shr:2
+       __builtin_amdgcn_update_dpp(0, (int)x, 0x113, 0xf, 0xf, false);    // row_shr:3
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xe, false);          // row_shr:4, lanes 4-15 of a row
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xc, false);          // row_shr:8, lanes 8-15 of a row
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);          // row_bcast:15 into rows 1 and 3
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);          // row_bcast:31 into rows 2 and 3
+  return (unsigned)v;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_excl_scan(T x, T* total) {
-  const unsigned lane = lane_id();
-  T incl = x;
-#pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) {
-    const T t = __shfl_up(incl, o, WAVE);
-    if ((int)lane >= o) incl += t;
-  }
-  *total = __shfl(incl, WAVE - 1, WAVE);
-  return incl - x;
+  static_assert(sizeof(T) == 4, "32-bit scan");
+  const unsigned incl = wave_incl_scan_u32((unsigned)x);
+  *total = (T)(unsigned)__builtin_amdgcn_readlane((int)incl, WAVE - 1);
+  return (T)(incl - (unsigned)x);
 }
 
 // Colour bitmap words come from one bump counter (bm_next).  A counter that
@@ -1806,15 +1817,7 @@ __device__ void narrow_load_fan(const Params& P, NarrowLds& Z, int cur, const un
 __device__ void narrow_scan2(NarrowLds& Z, unsigned a0, unsigned a1, unsigned nv) {
   const unsigned lane = lane_id();
   const int w = threadIdx.x / WAVE;
-  unsigned i0 = a0, i1 = a1;
-#pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) {
-    const unsigned t0 = __shfl_up(i0, o, WAVE), t1 = __shfl_up(i1, o, WAVE);
-    if ((int)lane >= o) {
-      i0 += t0;
-      i1 += t1;
-    }
-  }
+  const unsigned i0 = wave_incl_scan_u32(a0), i1 = wave_incl_scan_u32(a1);
   if (lane == WAVE - 1) {
     Z.wsum[0][w] = i0;
     Z.wsum[1][w] = i1;
