@@ -121,12 +121,7 @@ __device__ __forceinline__ long long block_scan(long long x, long long* red, lon
   constexpr int NW = BB / WAVE;
   const unsigned lane = lane_id();
   const int w = threadIdx.x / WAVE;
-  long long incl = x;
-#pragma unroll
-  for (int off = 1; off < WAVE; off <<= 1) {
-    long long o = __shfl_up(incl, off, WAVE);
-    if ((int)lane >= off) incl += o;
-  }
+  const long long incl = wave_incl_scan<false>(x, OpAdd());
   if (lane == WAVE - 1) red[w] = incl;
   __syncthreads();
   long long pre = 0, tot = 0;

@@ -33,21 +33,69 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int lane) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
-  return v;
-}
-template <typename T>
-__device__ __forceinline__ T wave_max(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    T o = __shfl_xor(v, off, WAVE);
-    v = o > v ? o : v;
+// DPP move of a 32- or 64-bit value from the lane that CTRL selects (row and
+// bank masks as in the DPP encoding); a lane whose source lies outside its
+// row of 16, or is masked off, gets `old`.
+template <int CTRL, int ROW, int BANK, typename T>
+__device__ __forceinline__ T dpp_move(T v, T old) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old), __builtin_bit_cast(int, v),
+                                                             CTRL, ROW, BANK, false));
+  } else {
+    const uint64_t x = __builtin_bit_cast(uint64_t, v), o = __builtin_bit_cast(uint64_t, old);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)o, (int)(unsigned)x, CTRL, ROW, BANK, false);
+    const unsigned hi =
+        (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(o >> 32), (int)(unsigned)(x >> 32), CTRL, ROW, BANK, false);
+    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
   }
+}
+
+// Inclusive scan over the 64 lanes with the associative operation `op`, by
+// DPP moves (no LDS round trip): each lane combines lanes i-3 .. i of its row
+// of 16, then i-7 .. i and i-15 .. i (row shifts by 4 and 8), then rows 1
+// and 3 take the total of the row before them (row broadcast of lane 15) and
+// rows 2 and 3 the total of rows 0-1 (row broadcast of lane 31).  Lanes with
+// no source take `id`: the operation's identity for sums, or the lane's own
+// value when op(v, v) == v (max, min).
+template <bool IDEMPOTENT, typename T, typename Op>
+__device__ __forceinline__ T wave_incl_scan(T x, Op op) {
+  const T z = IDEMPOTENT ? x : T(0);
+  T v = op(op(x, dpp_move<0x111, 0xf, 0xf>(x, z)), op(dpp_move<0x112, 0xf, 0xf>(x, z), dpp_move<0x113, 0xf, 0xf>(x, z)));
+  v = op(v, dpp_move<0x114, 0xf, 0xe>(v, IDEMPOTENT ? v : T(0)));   // row_shr:4, lanes 4-15 of a row
+  v = op(v, dpp_move<0x118, 0xf, 0xc>(v, IDEMPOTENT ? v : T(0)));   // row_shr:8, lanes 8-15 of a row
+  v = op(v, dpp_move<0x142, 0xa, 0xf>(v, IDEMPOTENT ? v : T(0)));   // row_bcast:15 into rows 1 and 3
+  v = op(v, dpp_move<0x143, 0xc, 0xf>(v, IDEMPOTENT ? v : T(0)));   // row_bcast:31 into rows 2 and 3
   return v;
 }
+template <typename T>
+__device__ __forceinline__ T wave_lane63(T v) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), WAVE - 1));
+  } else {
+    return __builtin_bit_cast(T, readlane_u64(__builtin_bit_cast(uint64_t, v), WAVE - 1));
+  }
+}
+struct OpAdd {
+  template <typename T>
+  __device__ T operator()(T a, T b) const { return a + b; }
+};
+struct OpMax {
+  template <typename T>
+  __device__ T operator()(T a, T b) const { return a > b ? a : b; }
+};
+struct OpMin {
+  template <typename T>
+  __device__ T operator()(T a, T b) const { return a < b ? a : b; }
+};
+__device__ __forceinline__ unsigned wave_incl_scan_u32(unsigned x) { return wave_incl_scan<false>(x, OpAdd()); }
+// Wave-wide sum, max and min (every lane receives the result).
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) { return wave_lane63(wave_incl_scan<false>(v, OpAdd())); }
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) { return wave_lane63(wave_incl_scan<true>(v, OpMax())); }
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) { return wave_lane63(wave_incl_scan<true>(v, OpMin())); }
 
 // rho_R, the random tie-break inside an ADG round: MurmurHash3's 32-bit
 // finaliser applied to (v XOR key).  Each step is invertible modulo 2^32, so

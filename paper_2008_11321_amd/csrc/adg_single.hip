@@ -712,22 +712,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Inclusive prefix sum over the 64 lanes with DPP moves (no LDS round trip):
-// sums of 4 lanes, then 8 and 16 inside each row of 16, then the rows' totals
-// carried forward by the row broadcasts of lanes 15 and 31.  Lanes whose DPP
-// source is outside the row or masked off add 0.
-__device__ __forceinline__ unsigned wave_incl_scan_u32(unsigned x) {
-  int v = (int)x;
-  v += __builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false) +   // row_shr:1
-       __builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false) +   // row_shr:2
-       __builtin_amdgcn_update_dpp(0, (int)x, 0x113, 0xf, 0xf, false);    // row_shr:3
-  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xe, false);          // row_shr:4, lanes 4-15 of a row
-  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xc, false);          // row_shr:8, lanes 8-15 of a row
-  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);          // row_bcast:15 into rows 1 and 3
-  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);          // row_bcast:31 into rows 2 and 3
-  return (unsigned)v;
-}
-
 template <typename T>
 __device__ __forceinline__ T wave_excl_scan(T x, T* total) {
   static_assert(sizeof(T) == 4, "32-bit scan");
@@ -1304,14 +1288,13 @@ struct JpStage {
   unsigned long long* acc;      // LDS [2]: this block's share of psum and ssum (null: sums not kept)
 };
 
-// Append u (ready) to the global lists of level l + 1.
+// Append u (ready; JP record ur) to the global lists of level l + 1.
 template <int S>
-__device__ __forceinline__ void jp_append(const Params& P, JpStage& st, int l, bool rdy, int u) {
-  long long ns = 0;
-  if (rdy) ns = P.nsr[u];
+__device__ __forceinline__ void jp_append(const Params& P, JpStage& st, int l, bool rdy, int u, const JpRec& ur) {
+  const long long ns = rdy ? sp_count(P, u, ur.sp) : 0;
   if (st.acc && ballot(rdy)) {
     const unsigned long long es = wave_sum((unsigned long long)ns);
-    const unsigned long long ps = wave_sum((unsigned long long)(rdy ? bm_words(P.npred[u]) : 0));
+    const unsigned long long ps = wave_sum((unsigned long long)(rdy ? bm_words((int)(unsigned)ur.rec) : 0));
     if (lane_id() == 0) {
       atomicAdd(&st.acc[0], ps);
       atomicAdd(&st.acc[1], es);
@@ -1562,7 +1545,7 @@ __device__ void jp_split_items(const Params& P, JpStage& st, int r, long long gw
     const long long i = g * WAVE + lane;
     const bool ok = i < sz;
     const int v = ok ? (int)P.L0[b + i] : 0;
-    jp_append<SC_AGENT>(P, st, -1, ok, v);
+    jp_append<SC_AGENT>(P, st, -1, ok, v, ok ? rec_pair(P, v) : JpRec{0, 0});
   }
 }
 
@@ -1601,7 +1584,7 @@ __device__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, 
       const int col = wave_colour(P, W, act, rec);
       if (act) sti<SC_AGENT>(&P.color[v], col);
       for (long long j = s0; ballot(act && j < s1); j += JP_UNROLL) {
-        unsigned long long rc[JP_UNROLL];
+        JpRec rc[JP_UNROLL];
         if (j != s0) {
 #pragma unroll
           for (int t = 0; t < JP_UNROLL; ++t) {
@@ -1610,12 +1593,12 @@ __device__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, 
           }
         }
 #pragma unroll
-        for (int t = 0; t < JP_UNROLL; ++t) rc[t] = ok[t] ? rec_of(P, u[t]) : 0;
+        for (int t = 0; t < JP_UNROLL; ++t) rc[t] = ok[t] ? rec_pair(P, u[t]) : JpRec{0, 0};
         bool rdy[JP_UNROLL];
 #pragma unroll
-        for (int t = 0; t < JP_UNROLL; ++t) rdy[t] = ok[t] && jp_push<SC_AGENT>(P, u[t], rc[t], col);
+        for (int t = 0; t < JP_UNROLL; ++t) rdy[t] = ok[t] && jp_push<SC_AGENT>(P, u[t], rc[t].rec, col);
 #pragma unroll
-        for (int t = 0; t < JP_UNROLL; ++t) jp_append<SC_AGENT>(P, st, l, rdy[t], u[t]);
+        for (int t = 0; t < JP_UNROLL; ++t) jp_append<SC_AGENT>(P, st, l, rdy[t], u[t], rc[t]);
       }
     } else {
       const unsigned k = (unsigned)(it - groups);
@@ -1643,12 +1626,7 @@ __device__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, 
       for (unsigned w0 = 0; w0 < nw && !col; w0 += WAVE) {
         const unsigned w = w0 + lane;
         const unsigned wd = w < nw ? bm_load(P, (rec >> 32) + w) : ~0u;
-        int f = ~wd ? (int)(w * 32) + __ffs((int)~wd) - 1 : 0x7fffffff;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-          const int g = __shfl_xor(f, o, WAVE);
-          f = g < f ? g : f;
-        }
+        const int f = wave_min(~wd ? (int)(w * 32) + __ffs((int)~wd) - 1 : 0x7fffffff);
         if (f != 0x7fffffff) col = f + 1;
       }
       if (!col) {
@@ -1656,14 +1634,14 @@ __device__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, 
         col = (int)(unsigned)rec + 1;
       }
       if (k == first && lane == 0) sti<SC_AGENT>(&P.color[v], col);
-      unsigned long long rc[JP_UNROLL];
+      JpRec rc[JP_UNROLL];
 #pragma unroll
-      for (int t = 0; t < JP_UNROLL; ++t) rc[t] = ok[t] ? rec_of(P, u[t]) : 0;
+      for (int t = 0; t < JP_UNROLL; ++t) rc[t] = ok[t] ? rec_pair(P, u[t]) : JpRec{0, 0};
       bool rdy[JP_UNROLL];
 #pragma unroll
-      for (int t = 0; t < JP_UNROLL; ++t) rdy[t] = ok[t] && jp_push<SC_AGENT>(P, u[t], rc[t], col);
+      for (int t = 0; t < JP_UNROLL; ++t) rdy[t] = ok[t] && jp_push<SC_AGENT>(P, u[t], rc[t].rec, col);
 #pragma unroll
-      for (int t = 0; t < JP_UNROLL; ++t) jp_append<SC_AGENT>(P, st, l, rdy[t], u[t]);
+      for (int t = 0; t < JP_UNROLL; ++t) jp_append<SC_AGENT>(P, st, l, rdy[t], u[t], rc[t]);
     }
   }
 }
@@ -1759,7 +1737,7 @@ __device__ __forceinline__ void narrow_append(const Params& P, NarrowLds& Z, JpS
   }
   if (base + tot > (unsigned)NARROW_MAX) {
 #pragma unroll
-    for (int q = 0; q < NARROW_UNROLL; ++q) jp_append<SC_WG>(P, st, l, over[q], u[q]);
+    for (int q = 0; q < NARROW_UNROLL; ++q) jp_append<SC_WG>(P, st, l, over[q], u[q], JpRec{urec[q], usp[q]});
   }
 }
 
