@@ -261,7 +261,12 @@ def run_single(args, w):
     torch.cuda.synchronize()
     log("warm-up done")
     adg.profile_read()  # drop anything recorded so far
-    adg.profile_enable(["update", "update_huge", "update_pull", "jp", "jp_narrow", "dec_itr"])
+    # Kernel time, on the launch stream, during the timed steps: HIP events
+    # around every UPDATE launch, and one pair around each call's JP (or
+    # DEC-ADG-ITR) loop counted as the launches issued in it.  (An event pair
+    # around each of JP's thousands of short launches would cost host time
+    # and slow the very steps being timed.)
+    adg.profile_enable(["update", "update_huge", "update_pull", "jp_phase", "dec_phase"])
     torch.cuda.synchronize()
     times = []
     t0 = time.perf_counter()
@@ -280,8 +285,8 @@ def run_single(args, w):
     # single-block steps (jp_narrow) and grid-wide steps (jp); its algorithmic
     # bytes are charged to the two together.
     # (DEC-ADG-ITR's triples of pull, pick and resolve take JP's place)
-    jp_ms = prof.get("jp", (0, 0))[0] + prof.get("jp_narrow", (0, 0))[0] + prof.get("dec_itr", (0, 0))[0]
-    jp_launches = prof.get("jp", (0, 0))[1] + prof.get("jp_narrow", (0, 0))[1] + prof.get("dec_itr", (0, 0))[1]
+    jp_ms = prof.get("jp_phase", (0, 0))[0] + prof.get("dec_phase", (0, 0))[0]
+    jp_launches = prof.get("jp_phase", (0, 0))[1] + prof.get("dec_phase", (0, 0))[1]
     upd_ms = prof.get("update", (0.0, 0))[0] + prof.get("update_huge", (0.0, 0))[0] + \
         prof.get("update_pull", (0.0, 0))[0]
     upd_launches = prof.get("update", (0.0, 0))[1]
@@ -293,7 +298,9 @@ def run_single(args, w):
     roofline = roofline_record(dom, tot_ms, launches, args.steps, algorithmic_bytes(dom, n, nnz, st), kname,
                                args.workload,
                                {"phase_ms_per_step": {"update": round(upd_ms / args.steps, 3),
-                                                      "jp": round(jp_ms / args.steps, 3)}})
+                                                      "jp": round(jp_ms / args.steps, 3)},
+                                "timing": "HIP events on the launch stream in the timed steps: a pair around "
+                                          "each UPDATE launch, one around each call's JP loop"})
     if args.breakdown:
         adg.profile_enable(adg.KERNEL_CLASSES)
         step()

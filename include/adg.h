@@ -327,8 +327,13 @@ int adg_validate_csr(const adg_csr_t* g, void* workspace, size_t ws_bytes, void*
  * 9 finish, 10 batched, 11 jp_narrow (single-block JP steps), 12 update_huge
  * (UPDATE of rows longer than 16384 entries, cut into chunks), 13
  * median_select (ADG-M), 14 order_sort (adg_order_ex's pos), 15 dec_itr
- * (DEC-ADG-ITR triples), 16 update_pull)
- * record a pair of HIP events on its launch stream; 0 disables it.
+ * (DEC-ADG-ITR triples), 16 update_pull, 17 jp_phase, 18 dec_phase)
+ * record a pair of HIP events on its launch stream; 0 disables it.  The two
+ * phase classes put one pair around a call's whole JP (or DEC-ADG-ITR) loop,
+ * host round trips between its chunks included, and count it as the number
+ * of kernel launches issued in the loop: two events per call instead of two
+ * per launch, whose host cost would slow a loop of thousands of short
+ * launches.
  * adg_profile_read waits for the recorded events, adds up the elapsed time
  * and launch count per class into *out and forgets the records.  Process-wide,
  * guarded by a mutex. */

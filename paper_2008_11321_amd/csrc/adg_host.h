@@ -12,21 +12,24 @@ namespace adg {
 
 enum KClass {
   KC_INIT, KC_STATS, KC_COUNT, KC_SCAN, KC_SCATTER, KC_UPDATE, KC_PART1, KC_JP_PREP, KC_JP, KC_FINISH,
-  KC_BATCH, KC_JP_NARROW, KC_UPDATE_HUGE, KC_MSEL, KC_ORDER, KC_DEC, KC_UPDATE_PULL, KC_NUM
+  KC_BATCH, KC_JP_NARROW, KC_UPDATE_HUGE, KC_MSEL, KC_ORDER, KC_DEC, KC_UPDATE_PULL, KC_JP_PHASE, KC_DEC_PHASE,
+  KC_NUM
 };
 
-// Event pair around one launch of class `cls`, recorded only while that
-// class is enabled by adg_profile_enable.
+// Event pair around one launch of class `cls` (or around a loop of
+// `units` launches), recorded only while that class is enabled by
+// adg_profile_enable.
 hipEvent_t prof_begin(int cls, hipStream_t s);
-void prof_end(int cls, hipStream_t s, hipEvent_t a);
+void prof_end(int cls, hipStream_t s, hipEvent_t a, long long units);
 
 struct ProfScope {
   int cls;
   hipStream_t s;
   hipEvent_t a;
+  long long units = 1;   // launches the pair stands for
   ProfScope(int c, hipStream_t st) : cls(c), s(st), a(prof_begin(c, st)) {}
   ~ProfScope() {
-    if (a) prof_end(cls, s, a);
+    if (a) prof_end(cls, s, a, units);
   }
 };
 #define ADG_TIMED_CAT2(a, b) a##b

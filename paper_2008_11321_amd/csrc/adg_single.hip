@@ -2426,11 +2426,13 @@ namespace adg {
 namespace {
 const char* kclass_names[KC_NUM] = {"init", "stats", "count", "scan", "scatter", "update", "part1",
                                     "jp_prep", "jp", "finish", "batched", "jp_narrow", "update_huge",
-                                    "median_select", "order_sort", "dec_itr", "update_pull"};
+                                    "median_select", "order_sort", "dec_itr", "update_pull", "jp_phase",
+                                    "dec_phase"};
 static_assert(KC_NUM <= ADG_PROFILE_CLASSES, "profile classes do not fit adg_profile_t");
 struct ProfRec {
   int cls;
   hipEvent_t a, b;
+  long long units;
 };
 std::mutex g_prof_mu;
 unsigned g_prof_mask = 0;
@@ -2460,7 +2462,7 @@ hipEvent_t prof_begin(int cls, hipStream_t s) {
   return a;
 }
 
-void prof_end(int cls, hipStream_t s, hipEvent_t a) {
+void prof_end(int cls, hipStream_t s, hipEvent_t a, long long units) {
   std::lock_guard<std::mutex> g(g_prof_mu);
   hipEvent_t b = prof_event();
   if (!b || hipEventRecord(b, s) != hipSuccess) {
@@ -2468,7 +2470,7 @@ void prof_end(int cls, hipStream_t s, hipEvent_t a) {
     if (b) g_pool.push_back(b);
     return;
   }
-  g_prof.push_back({cls, a, b});
+  g_prof.push_back({cls, a, b, units});
 }
 
 }  // namespace adg
@@ -2787,24 +2789,30 @@ int run_jp(Params& P, hipStream_t s, int rounds) {
   // steps of one single-block launch: every step processes a level, loads
   // one or starts a round
   const int max_steps = (int)std::min<long long>(0x7fffffff, 3LL * ((long long)P.n + rounds) + 16);
-  while (true) {
-    for (int k = 0; k < chunk; ++k) {
-      {
-        TIMED(KC_JP_NARROW, s);
-        hipLaunchKernelGGL(k_jp_narrow, dim3(1), dim3(NARROW_BS), 0, s, P, max_steps);
+  // one event pair around the whole loop (host round trips between chunks
+  // included), standing for the launches issued in it
+  {
+    ProfScope phase(KC_JP_PHASE, s);
+    while (true) {
+      for (int k = 0; k < chunk; ++k) {
+        {
+          TIMED(KC_JP_NARROW, s);
+          hipLaunchKernelGGL(k_jp_narrow, dim3(1), dim3(NARROW_BS), 0, s, P, max_steps);
+        }
+        {
+          TIMED(KC_JP, s);
+          hipLaunchKernelGGL(k_jp_grid, dim3(JP_GRID_BLOCKS), dim3(BS), 0, s, P);
+        }
       }
-      {
-        TIMED(KC_JP, s);
-        hipLaunchKernelGGL(k_jp_grid, dim3(JP_GRID_BLOCKS), dim3(BS), 0, s, P);
-      }
+      pairs += chunk;
+      phase.units = 2 * pairs;
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(h, &P.ctrl->js.done, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (h[0]) break;
+      if (pairs > max_pairs) return ADG_ERR_INTERNAL;
+      chunk = std::min(chunk * 2, 256);
     }
-    pairs += chunk;
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(h, &P.ctrl->js.done, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (h[0]) break;
-    if (pairs > max_pairs) return ADG_ERR_INTERNAL;
-    chunk = std::min(chunk * 2, 256);
   }
   {
     TIMED(KC_FINISH, s);
@@ -2831,24 +2839,28 @@ int run_dec(Params& P, hipStream_t s, int rounds) {
   int chunk = 4;
   long long triples = 0;
   const long long max_triples = (long long)P.n + rounds + 8;
-  while (true) {
-    for (int k = 0; k < chunk; ++k) {
-      TIMED(KC_DEC, s);
-      const int p = (int)((triples + k) & 1);
-      hipLaunchKernelGGL(k_dec_pull, dim3(P.upd_blocks), dim3(BS), 0, s, P, p);
-      hipLaunchKernelGGL(k_dec_pick, dim3(P.upd_blocks), dim3(BS), 0, s, P, p);
-      hipLaunchKernelGGL(k_dec_resolve, dim3(P.upd_blocks), dim3(BS), 0, s, P, p);
+  {
+    ProfScope phase(KC_DEC_PHASE, s);   // as in run_jp
+    while (true) {
+      for (int k = 0; k < chunk; ++k) {
+        TIMED(KC_DEC, s);
+        const int p = (int)((triples + k) & 1);
+        hipLaunchKernelGGL(k_dec_pull, dim3(P.upd_blocks), dim3(BS), 0, s, P, p);
+        hipLaunchKernelGGL(k_dec_pick, dim3(P.upd_blocks), dim3(BS), 0, s, P, p);
+        hipLaunchKernelGGL(k_dec_resolve, dim3(P.upd_blocks), dim3(BS), 0, s, P, p);
+      }
+      triples += chunk;
+      phase.units = 3 * triples;
+      HIPCHK(hipGetLastError());
+      // the state the next triple reads (triples is even here, chunks being even)
+      HIPCHK(hipMemcpyAsync(&h[0], &P.ctrl->dec[triples & 1].done, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(&h[1], &P.ctrl->error, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (h[1]) return h[1];
+      if (h[0]) break;
+      if (triples > max_triples) return ADG_ERR_INTERNAL;
+      chunk = std::min(chunk * 2, 256);
     }
-    triples += chunk;
-    HIPCHK(hipGetLastError());
-    // the state the next triple reads (triples is even here, chunks being even)
-    HIPCHK(hipMemcpyAsync(&h[0], &P.ctrl->dec[triples & 1].done, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(&h[1], &P.ctrl->error, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (h[1]) return h[1];
-    if (h[0]) break;
-    if (triples > max_triples) return ADG_ERR_INTERNAL;
-    chunk = std::min(chunk * 2, 256);
   }
   {
     TIMED(KC_FINISH, s);
@@ -3043,7 +3055,7 @@ int adg_profile_read(adg_profile_t* out) {
     if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) rc = ADG_ERR_HIP;
     if (r.cls >= 0 && r.cls < ADG_PROFILE_CLASSES) {
       out->ms[r.cls] += ms;
-      out->launches[r.cls] += 1;
+      out->launches[r.cls] += r.units;
     }
     g_pool.push_back(r.a);
     g_pool.push_back(r.b);

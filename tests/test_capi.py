@@ -103,3 +103,15 @@ def test_variant_entry_points_reject_bad_arguments_without_gpu():
     # a pos output needs the larger workspace
     assert L.adg_order_ex(ctypes.byref(csr), 1, 10, 0, 1, fake, fake, None, fake, ws, None) == -2
     assert L.adg_order_ex(None, 1, 10, 0, 1, fake, fake, None, fake, ws, None) == -1
+
+
+def test_profile_class_names_match_the_binding():
+    """The Python class list and the library's class names agree index by
+    index (adg_profile_enable takes bits by these indices)."""
+    L = pkg.lib()
+    L.adg_kernel_class_name.restype = ctypes.c_char_p
+    L.adg_kernel_class_name.argtypes = [ctypes.c_int]
+    for i, name in enumerate(pkg.KERNEL_CLASSES):
+        assert L.adg_kernel_class_name(i).decode() == name, i
+    assert L.adg_kernel_class_name(len(pkg.KERNEL_CLASSES)).decode() == ""
+    assert len(pkg.KERNEL_CLASSES) <= 32
