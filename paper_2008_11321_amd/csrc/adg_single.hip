@@ -2483,6 +2483,26 @@ struct Layout {
 };
 
 constexpr int UPD_BLOCKS = 2048;
+
+// Blocks of the UPDATE-sized launches (k_update, k_part1, the pull and DEC
+// kernels): as many as the device keeps resident at once, at most
+// UPD_BLOCKS.  Each block strides over its share of the rows, so blocks
+// beyond what fits would only start once the first ones had finished their
+// whole share, and then run with most of the chip idle.  k_update's LDS and
+// registers allow 6 blocks per CU on gfx950.  Computed once per process
+// (every GPU here is the same device type).
+int upd_launch_blocks() {
+  static const int blocks = [] {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_update<true>, BS, 0) != hipSuccess || cus <= 0 ||
+        per <= 0)
+      return UPD_BLOCKS;
+    return std::min(UPD_BLOCKS, cus * per);
+  }();
+  return blocks;
+}
 #ifndef ADG_JP_GRID_BLOCKS
 #define ADG_JP_GRID_BLOCKS 1024
 #endif
@@ -2623,7 +2643,7 @@ Params make_params(const adg_csr_t* g, void* ws, uint64_t p, uint64_t q, uint64_
   P.boff = (unsigned long long*)(base + L.boff);
   P.bsum = (unsigned long long*)(base + L.bsum);
   P.xpart = (unsigned long long*)(base + L.xpart);
-  P.upd_blocks = UPD_BLOCKS;
+  P.upd_blocks = upd_launch_blocks();
   P.dag = (int*)(base + L.dag);
   P.npred = (int*)(base + L.npred);
   P.nsr = (int*)(base + L.nsr);
