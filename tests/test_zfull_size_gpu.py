@@ -124,6 +124,78 @@ def check_definition(torch, rp, col_d, rnd, color, p, q, seed, device, median=Fa
     return sum_active
 
 
+def check_adg_by_removal(torch, rp, col_d, rnd, p, q, device):
+    """Algorithm 1's selection rule for every round, with deg_U kept by
+    definition as it shrinks: it starts as the degree, and once round l is
+    checked every edge from a vertex of R_l to a vertex still in U takes one
+    off that vertex's count.  Each row is read once in all, so this suits
+    runs with many rounds (small eps).  Returns sum |U_l|."""
+    n = rp.size - 1
+    L = int(rnd.max())
+    rnd = rnd.to(torch.int64)
+    rpd = torch.as_tensor(rp, device=device)
+    deg = rpd[1:] - rpd[:-1]
+    degU = deg.clone()
+    order = torch.argsort(rnd, stable=True)
+    starts = [0] + torch.cumsum(torch.bincount(rnd, minlength=L + 1)[1:], 0).tolist()
+    sum_active = 0
+    for l in range(1, L + 1):
+        inU = rnd >= l
+        size_u = n - starts[l - 1]
+        assert size_u == int(inU.sum())
+        cnt = int(degU[inU].sum())
+        sel = (q * size_u) * degU <= (q + p) * cnt
+        assert torch.equal(sel[inU], (rnd == l)[inU]), "round %d" % l
+        sum_active += size_u
+        # remove R_l: its edges to U_{l+1}
+        verts = order[starts[l - 1]:starts[l]]
+        dv = deg[verts]
+        csum = torch.cumsum(dv, 0)
+        b0 = 0
+        while b0 < verts.numel():
+            base = int(csum[b0 - 1]) if b0 else 0
+            b1 = int(torch.searchsorted(csum, base + CHUNK, right=True))
+            b1 = max(b1, b0 + 1)
+            vv, dd = verts[b0:b1], dv[b0:b1]
+            tot = int(dd.sum())
+            if tot:
+                first = torch.repeat_interleave(rpd[vv], dd)
+                within = torch.arange(tot, device=device) - torch.repeat_interleave(torch.cumsum(dd, 0) - dd, dd)
+                c = col_d[first + within].to(torch.int64)
+                keep = rnd[c] > l
+                degU.index_add_(0, c[keep], torch.full((int(keep.sum()),), -1, dtype=torch.int64, device=device))
+                del first, within, c, keep
+            b0 = b1
+        if l % 16 == 0 or l == L:
+            print("round", l, "|U|", size_u, "removed", starts[l] - starts[l - 1], flush=True)
+    return sum_active
+
+
+def check_jp(torch, rp, col_d, rnd, color, seed, device):
+    """JP (Algorithm 3) under <round, rho_R(seed)>: proper, GetColor at every
+    vertex."""
+    n = rp.size - 1
+    K = int(color.max())
+    assert int(color.min()) >= 1
+    rnd = rnd.to(torch.int64)
+    color = color.to(torch.int64)
+    rpd = torch.as_tensor(rp, device=device)
+    deg = rpd[1:] - rpd[:-1]
+    key = (rnd << 32) | _tiebreak_torch(torch, seed, torch.arange(n, device=device))
+    width = K + 2
+    for v0, v1 in _chunks(rp, n):
+        e0, e1 = int(rp[v0]), int(rp[v1])
+        src = torch.repeat_interleave(torch.arange(v0, v1, device=device), deg[v0:v1])
+        c = col_d[e0:e1].to(torch.int64)
+        assert not bool((color[src] == color[c]).any()), "improper in [%d, %d)" % (v0, v1)
+        pred = key[c] > key[src]
+        used = torch.zeros((v1 - v0, width), dtype=torch.bool, device=device)
+        used[src[pred] - v0, color[c[pred]]] = True
+        first_missing = (~used[:, 1:]).to(torch.uint8).argmax(dim=1) + 1
+        assert torch.equal(first_missing, color[v0:v1]), "GetColor in [%d, %d)" % (v0, v1)
+        del src, c, pred, used
+
+
 @pytest.fixture(scope="module")
 def rmat26():
     import torch
@@ -173,3 +245,24 @@ def test_rmat26_sorted_and_median_at_full_size(rmat26):
     assert int(nr.item()) == g.n.bit_length()
     check_definition(torch, rp, g.col_idx, rnd, color, p, q, seed, "cuda", median=True)
     print("rmat26 variants checked", flush=True)
+
+
+@pytest.mark.parametrize("p,q", [(1, 100), (1, 2)])
+def test_rmat26_other_eps_at_full_size(rmat26, p, q):
+    """The other eps of the RMAT-26 configuration (the bench's rmat26_e001 and
+    rmat26_e05 workloads): eps = 1/100 takes many rounds."""
+    import torch
+    pkg, rp, g = rmat26
+    seed = 3
+    print("case rmat26 eps %d/%d" % (p, q), flush=True)
+    ws = torch.empty(pkg.workspace_bytes(g.n, g.nnz), dtype=torch.uint8, device="cuda")
+    color, nc, rnd, nr = pkg.color_graph(g, p, q, seed, workspace=ws)
+    torch.cuda.synchronize()
+    st = pkg.get_stats(ws)
+    print("coloured: rounds", int(nr.item()), "colours", int(nc.item()), st, flush=True)
+    assert st["error"] == 0
+    assert int(rnd.max()) == int(nr.item()) and int(color.max()) == int(nc.item())
+    del ws
+    assert check_adg_by_removal(torch, rp, g.col_idx, rnd, p, q, "cuda") == st["sum_active"]
+    check_jp(torch, rp, g.col_idx, rnd, color, seed, "cuda")
+    print("rmat26 eps %d/%d checked" % (p, q), flush=True)
