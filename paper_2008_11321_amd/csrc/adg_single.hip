@@ -86,10 +86,10 @@ constexpr int NARROW_MAX = 1024;             // level size the single block take
 // Work of a level the single block takes (it walks larger ones in passes of
 // NARROW_BS * NARROW_UNROLL entries; beyond these sizes the grid is faster).
 #ifndef ADG_NARROW_WORDS
-#define ADG_NARROW_WORDS 4096
+#define ADG_NARROW_WORDS 3072
 #endif
 #ifndef ADG_NARROW_SUCC
-#define ADG_NARROW_SUCC 4096
+#define ADG_NARROW_SUCC 3072
 #endif
 constexpr int NARROW_WORDS = ADG_NARROW_WORDS;  // colour bitmap words of a level
 constexpr int NARROW_SUCC = ADG_NARROW_SUCC;    // same-round successor entries of a level
