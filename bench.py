@@ -230,6 +230,30 @@ def roofline_record(dom, tot_ms, launches, steps, step_bytes, kname, workload, e
     return r
 
 
+def er_single_launch(args, rp, col, p, q, seed, colour_ref):
+    """The same small graph through color_graph_batched as a batch of one:
+    the whole method in one launch instead of several per ADG round.  Reported
+    beside `value`, which stays the per-call color_graph path."""
+    import torch
+
+    import paper_2008_11321_amd.batched as bt
+
+    n, nnz = rp.size - 1, col.size
+    batch = bt.Batch([(rp, col)], device="cuda:0")
+    ws = torch.empty(bt.batched_workspace_bytes(1, n, nnz), dtype=torch.uint8, device="cuda:0")
+    for _ in range(max(args.warmup, 1)):
+        colour = bt.color_graph_batched(batch, p, q, seed, workspace=ws)[0]
+    torch.cuda.synchronize()
+    same = bool(torch.equal(colour, colour_ref))
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bt.color_graph_batched(batch, p, q, seed, workspace=ws)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000 / args.steps
+    return {"ms_per_step": round(ms, 4), "value": (nnz // 2) / (ms / 1000), "unit": "edges/s",
+            "same_colouring_as_color_graph": same}
+
+
 def run_single(args, w):
     import torch
 
@@ -310,6 +334,9 @@ def run_single(args, w):
             log("  %-8s %8.3f ms  %4d launches" % (k, ms, cnt))
         log("  stats", st)
 
+    extra = {"step_ms": step_stats(times)}
+    if w["kind"] == "er" and not variant:
+        extra["single_launch_batched"] = er_single_launch(args, rp, col, p, q, seed, out[0][:n])
     cpu = None if args.no_cpu_baseline else cpu_baseline_graph(w, rp, col, m, variant)
     cfg = {"workload": args.workload, "graph": w["kind"], "n": n, "nnz": nnz, "m": m, "eps": "%d/%d" % (p, q),
            "seed": seed, "rounds": st["num_rounds"], "colors": st["num_colors"]}
@@ -317,7 +344,7 @@ def run_single(args, w):
         cfg["variant"] = args.variant
     if w["kind"] == "rmat":
         cfg.update(scale=w["scale"], edge_factor=w["edge_factor"], abcd=[0.57, 0.19, 0.19, 0.05])
-    return m / (dt / args.steps), dt * 1000 / args.steps, cfg, roofline, cpu, {"step_ms": step_stats(times)}
+    return m / (dt / args.steps), dt * 1000 / args.steps, cfg, roofline, cpu, extra
 
 
 def run_batched(args, w):
