@@ -2504,7 +2504,7 @@ int upd_launch_blocks() {
   return blocks;
 }
 #ifndef ADG_JP_GRID_BLOCKS
-#define ADG_JP_GRID_BLOCKS 1024
+#define ADG_JP_GRID_BLOCKS 1536
 #endif
 constexpr int JP_GRID_BLOCKS = ADG_JP_GRID_BLOCKS;   // launch size of the grid-wide JP steps
 constexpr int HUGE_BLOCKS = 1024;
