@@ -77,9 +77,19 @@ constexpr int SMALL_DEG = 32;           // lane-per-vertex rows up to this lengt
 constexpr int HUGE_DEG = 16384;         // rows longer than this are cut into chunks in UPDATE
 constexpr int HUGE_CHUNK = 4096;        // entries of such a chunk
 constexpr int FB_CAP = 2048;            // per-block staging of level lists (LDS)
-constexpr int JP_SMALL = 4;             // lane-per-vertex successor loops
-constexpr int JP_UNROLL = 4;
-constexpr int JP_CHUNK = WAVE * JP_UNROLL;   // successors per wavefront step / fan-out chunk
+#ifndef ADG_JP_SMALL
+#define ADG_JP_SMALL 4
+#endif
+#ifndef ADG_JP_UNROLL
+#define ADG_JP_UNROLL 1
+#endif
+constexpr int JP_SMALL = ADG_JP_SMALL;    // lane-per-vertex successor loops (more: fan-out chunks)
+constexpr int JP_UNROLL = ADG_JP_UNROLL;  // successors in flight per lane
+#ifndef ADG_JP_CHUNK_UNROLL
+#define ADG_JP_CHUNK_UNROLL ADG_JP_UNROLL
+#endif
+constexpr int JP_CU = ADG_JP_CHUNK_UNROLL;   // successors per lane of a fan-out chunk
+constexpr int JP_CHUNK = WAVE * JP_CU;       // successors per fan-out chunk (one wavefront step)
 constexpr int FAN_LDS = 1024;                // fan-out list entries a grid block stages in LDS
 constexpr int NARROW_BS = 1024;              // threads of the single-block JP kernel
 constexpr int NARROW_MAX = 1024;             // level size the single block takes
@@ -1612,10 +1622,10 @@ __device__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, 
       const long long b = sp_first(pr.sp), e = b + sp_count(P, v, pr.sp);
       const long long s0 = b + (long long)(k - first) * JP_CHUNK;
       const long long s1 = s0 + JP_CHUNK < e ? s0 + JP_CHUNK : e;
-      int u[JP_UNROLL];
-      bool ok[JP_UNROLL];
+      int u[JP_CU];
+      bool ok[JP_CU];
 #pragma unroll
-      for (int t = 0; t < JP_UNROLL; ++t) {
+      for (int t = 0; t < JP_CU; ++t) {
         const long long j = s0 + t * WAVE + lane;
         ok[t] = j < s1;
         u[t] = ok[t] ? P.dag[j] : 0;
@@ -1634,14 +1644,14 @@ __device__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, 
         col = (int)(unsigned)rec + 1;
       }
       if (k == first && lane == 0) sti<SC_AGENT>(&P.color[v], col);
-      JpRec rc[JP_UNROLL];
+      JpRec rc[JP_CU];
 #pragma unroll
-      for (int t = 0; t < JP_UNROLL; ++t) rc[t] = ok[t] ? rec_pair(P, u[t]) : JpRec{0, 0};
-      bool rdy[JP_UNROLL];
+      for (int t = 0; t < JP_CU; ++t) rc[t] = ok[t] ? rec_pair(P, u[t]) : JpRec{0, 0};
+      bool rdy[JP_CU];
 #pragma unroll
-      for (int t = 0; t < JP_UNROLL; ++t) rdy[t] = ok[t] && jp_push<SC_AGENT>(P, u[t], rc[t].rec, col);
+      for (int t = 0; t < JP_CU; ++t) rdy[t] = ok[t] && jp_push<SC_AGENT>(P, u[t], rc[t].rec, col);
 #pragma unroll
-      for (int t = 0; t < JP_UNROLL; ++t) jp_append<SC_AGENT>(P, st, l, rdy[t], u[t], rc[t]);
+      for (int t = 0; t < JP_CU; ++t) jp_append<SC_AGENT>(P, st, l, rdy[t], u[t], rc[t]);
     }
   }
 }
