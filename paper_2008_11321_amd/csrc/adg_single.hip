@@ -73,7 +73,10 @@ namespace adg {
 constexpr int BS = 256;                 // threads per block
 constexpr int WPB = BS / WAVE;          // wavefronts per block
 constexpr int SEL_BLOCKS = 2048;        // fixed grid of the selection kernels
-constexpr int SMALL_DEG = 32;           // lane-per-vertex rows up to this length
+#ifndef ADG_SMALL_DEG
+#define ADG_SMALL_DEG 32
+#endif
+constexpr int SMALL_DEG = ADG_SMALL_DEG;  // lane-per-vertex rows up to this length
 constexpr int HUGE_DEG = 16384;         // rows longer than this are cut into chunks in UPDATE
 constexpr int HUGE_CHUNK = 4096;        // entries of such a chunk
 constexpr int FB_CAP = 2048;            // per-block staging of level lists (LDS)
@@ -104,7 +107,10 @@ constexpr int NARROW_MAX = 1024;             // level size the single block take
 constexpr int NARROW_WORDS = ADG_NARROW_WORDS;  // colour bitmap words of a level
 constexpr int NARROW_SUCC = ADG_NARROW_SUCC;    // same-round successor entries of a level
 constexpr int NARROW_XPULL = 512;            // round size whose later-round colours it pulls in
-constexpr int NARROW_UNROLL = 4;             // edges per thread in flight in a narrow level
+#ifndef ADG_NARROW_UNROLL
+#define ADG_NARROW_UNROLL 4
+#endif
+constexpr int NARROW_UNROLL = ADG_NARROW_UNROLL;  // edges per thread in flight in a narrow level
 constexpr int MSEL_BINS = 2048;              // radix selection: 11-bit digits
 constexpr int MSEL_PASSES = 6;               // 11 x 5 + 9 bits cover a 64-bit key
 constexpr int MSEL_BLOCKS = 512;
