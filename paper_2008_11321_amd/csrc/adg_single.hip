@@ -2825,6 +2825,11 @@ int run_jp(Params& P, hipStream_t s, int rounds) {
   // steps of one single-block launch: every step processes a level, loads
   // one or starts a round
   const int max_steps = (int)std::min<long long>(0x7fffffff, 3LL * ((long long)P.n + rounds) + 16);
+  // grid-wide steps: no more blocks than a step can have work items (a
+  // level's groups of 64 vertices plus its fan-out chunks), so that small
+  // graphs do not dispatch blocks that leave at once
+  const long long items = ((long long)P.n + WAVE - 1) / WAVE + (P.nnz + JP_CHUNK - 1) / JP_CHUNK;
+  const int grid = (int)std::max<long long>(1, std::min<long long>(JP_GRID_BLOCKS, (items + WPB - 1) / WPB));
   // one event pair around the whole loop (host round trips between chunks
   // included), standing for the launches issued in it
   {
@@ -2837,7 +2842,7 @@ int run_jp(Params& P, hipStream_t s, int rounds) {
         }
         {
           TIMED(KC_JP, s);
-          hipLaunchKernelGGL(k_jp_grid, dim3(JP_GRID_BLOCKS), dim3(BS), 0, s, P);
+          hipLaunchKernelGGL(k_jp_grid, dim3(grid), dim3(BS), 0, s, P);
         }
       }
       pairs += chunk;
