@@ -21,17 +21,20 @@
 //   k_update   UPDATE: for v in R_l and w in N(v) still in U, decrement D[w].
 //              With fusion on, the same sweep also builds JP's DAG G_rho (JP
 //              Part 1 inside UPDATE, "Combining JP and ADG"): v's row is
-//              rewritten as [pred | same-round succ | earlier-round succ] and
-//              |pred(v)|, the number of same-round successors and v's JP word
-//              are stored.
+//              rewritten as [preds from later rounds | same-round preds |
+//              same-round succs], and |pred(v)|, the number of same-round
+//              successors and v's JP record are stored.  The rest of the row's
+//              slot (successors from earlier rounds) is left unwritten: no
+//              step reads it.
 // JP (Algorithm 3, Part 2) colours the rounds from L down to 1.  Every edge of
 // G_rho between different rounds points from the higher round to the lower,
 // so once rounds > l are coloured and have pushed their colours to round l,
-// round l only waits on itself.  Per round: its vertices whose predecessors
-// are all coloured form level 0; levels are processed one after the other
-// over same-round successors only; then one bulk kernel pushes the round's
-// colours to its earlier-round successors.  Narrow levels (and whole small
-// rounds) run in a single block with block barriers; wide ones over the grid.
+// round l only waits on itself.  Per round: one bulk step ORs the colours of
+// every predecessor from a later round (all final) into the round's bitmaps;
+// its vertices with no same-round predecessor form level 0; levels follow
+// one after the other over same-round successors only.  Narrow levels (and
+// whole small rounds) run in a single block with block barriers; wide ones
+// over the grid.
 //
 // Variants (flags of the _ex entry points):
 //   ADG-O (the ADG-O listing): R is ordered by D at selection, so JP's order
@@ -904,18 +907,14 @@ __device__ void update_small(const Params& P, BmPool* pl, SmallRows& S, int v, b
   const long long np = nl + nps;
   for (int p0 = 0; p0 < T; p0 += WAVE) {
     const int pos = p0 + (int)lane;
-    if (pos < T) {
+    const int cl = pos < T ? S.cls[pos] : NB_NONE;
+    if (cl != NB_NONE && cl != NB_SUCC_EARLIER) {   // earlier-round successors: never read back
       const int k = small_owner(S, pos);
       const long long bk = S.b[k];
       const int w = P.col[bk + (pos - S.off[k])];
-      const int cl = S.cls[pos];
       const long long r = atomicAdd(&S.run[k][cl], 1u);
       const long long nlk = S.cnt[k][NB_PRED], npk = nlk + S.cnt[k][NB_PRED_SAME];
-      long long at;
-      if (cl == NB_PRED) at = bk + r;
-      else if (cl == NB_PRED_SAME) at = bk + nlk + r;
-      else if (cl == NB_SUCC_SAME) at = bk + npk + r;
-      else at = bk + (S.off[k + 1] - S.off[k]) - 1 - r;
+      const long long at = cl == NB_PRED ? bk + r : cl == NB_PRED_SAME ? bk + nlk + r : bk + npk + r;
       P.dag[at] = w;
     }
   }
@@ -977,28 +976,23 @@ __device__ void update_big(const Params& P, BmPool* pl, L0Stage& l0s, RowMasks& 
   if (!FUSED) return;
   wave_sync();
   const long long np = nl + nps;
-  long long fc = 0, gc = 0, sc = 0, lc = 0;
+  long long fc = 0, gc = 0, sc = 0;
   ch = 0;
   for (long long base = b; base < e; base += WAVE, ++ch) {
-    long long j = base + lane;
-    bool valid = j < e;
-    int w = valid ? P.col[j] : 0;
     const uint64_t fm = rm.m[ch][0], gm = rm.m[ch][1], sm = rm.m[ch][2];
-    const uint64_t lm = ballot(valid) & ~(fm | gm | sm);
+    // earlier-round successors are never read back: a chunk of only those
+    // needs no pass at all
+    if (!(fm | gm | sm)) continue;
     const uint64_t me = 1ull << lane;
-    const int cl = !valid ? NB_NONE
-                   : (fm & me) ? NB_PRED
-                   : (gm & me) ? NB_PRED_SAME
-                   : (sm & me) ? NB_SUCC_SAME
-                               : NB_SUCC_EARLIER;
-    if (cl == NB_PRED) P.dag[b + fc + lanes_below(fm)] = w;
-    else if (cl == NB_PRED_SAME) P.dag[b + nl + gc + lanes_below(gm)] = w;
-    else if (cl == NB_SUCC_SAME) P.dag[b + np + sc + lanes_below(sm)] = w;
-    else if (cl == NB_SUCC_EARLIER) P.dag[e - 1 - lc - lanes_below(lm)] = w;
+    if ((fm | gm | sm) & me) {
+      const int w = P.col[base + lane];
+      if (fm & me) P.dag[b + fc + lanes_below(fm)] = w;
+      else if (gm & me) P.dag[b + nl + gc + lanes_below(gm)] = w;
+      else P.dag[b + np + sc + lanes_below(sm)] = w;
+    }
     fc += __popcll(fm);
     gc += __popcll(gm);
     sc += __popcll(sm);
-    lc += __popcll(lm);
   }
   wave_sync();   // the masks are rewritten by the wavefront's next row
   jp_row(P, pl, lane == 0, v, b, np, ns, nps);
@@ -1184,13 +1178,14 @@ __global__ __launch_bounds__(BS) void k_update_huge_place(Params P, int l) {
     unsigned* C = P.HC + 8 * (size_t)h;
     const long long nl = C[NB_PRED], nps = C[NB_PRED_SAME], ns = C[NB_SUCC_SAME];
     const long long np = nl + nps;
-    const long long start[4] = {b, b + np, 0, b + nl};   // by class; earlier successors fill from the end
+    const long long start[4] = {b, b + np, 0, b + nl};   // by class (earlier successors are not kept)
     for (long long base = c0; base < c1; base += WAVE) {
       const long long j = base + lane;
       const int w = j < c1 ? P.col[j] : 0;
       const int cl = j < c1 ? visit3<true>(P, w, l, code, hv, x, false) : NB_NONE;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
+        if (q == NB_SUCC_EARLIER) continue;   // never read back
         const uint64_t m = ballot(cl == q);
         if (!m) continue;
         unsigned at = 0;
@@ -1198,7 +1193,7 @@ __global__ __launch_bounds__(BS) void k_update_huge_place(Params P, int l) {
         at = readlane_u(at, 0);
         if (cl == q) {
           const long long o = at + lanes_below(m);
-          P.dag[q == NB_SUCC_EARLIER ? e - 1 - o : start[q] + o] = w;
+          P.dag[start[q] + o] = w;
         }
       }
     }
