@@ -69,8 +69,9 @@ def algorithmic_bytes(cls, n, nnz, st):
     """Bytes the method itself must move in one step, per kernel class.
     update: per vertex the R-list entry (4), its row_ptr pair (16), |pred| and
       the JP word (12); per adjacency entry the neighbour id (4), its status
-      byte (1) and the partitioned copy (4); per cut edge a 4-byte D
-      read-modify-write (8).
+      byte (1) and the partitioned copy (4), except that a cut edge's entry
+      at its later-round end (a successor from an earlier round) is not
+      copied (-4); per cut edge a 4-byte D read-modify-write (8).
     jp: per vertex the row_ptr pair (16), |pred| (4), the colour write (4) and
       a queue entry (4); per successor edge (m of them) the partitioned
       neighbour id (4) and the 8-byte word read-modify-write (16).
@@ -84,7 +85,7 @@ def algorithmic_bytes(cls, n, nnz, st):
       read-modify-write (20)."""
     m = nnz // 2
     if cls == "update":
-        return 32 * n + 9 * nnz + 8 * st["cut_edges"]
+        return 32 * n + 9 * nnz + 4 * st["cut_edges"]
     if cls == "jp":
         return 28 * n + 20 * m
     if cls == "batched":
