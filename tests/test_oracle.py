@@ -3,7 +3,11 @@ mathematics fix, never against itself or the GPU path.
 
 * definition-level checks of ADG's selection rule (Algorithm 1) and JP's
   smallest-free-colour rule (Algorithm 3, GetColor) on every labelled graph
-  with up to 6 vertices and on seeded random graphs;
+  with up to 6 vertices at every eps, a seeded sample of the graphs with 7,
+  and seeded random graphs;
+* the ADG counters against closed forms in rho: sum over rounds of |U_l| is
+  the sum of rho, and UPDATE's decrements of vertices staying in U are the
+  edges whose ends leave in different rounds;
 * closed forms worked out by hand from Algorithm 1 and 3 (edgeless graph,
   K_n, star, complete bipartite, path, very large eps = JP-R);
 * exact degeneracy by brute force over vertex subsets (definition in
@@ -91,7 +95,7 @@ def test_tiebreak_is_bijection():
 def test_degeneracy_matches_brute_force():
     rng = np.random.default_rng(3)
     for trial in range(120):
-        n = int(rng.integers(1, 10))
+        n = int(rng.integers(1, 11))
         p = float(rng.uniform(0.1, 0.9))
         edges = [(u, v) for u in range(n) for v in range(u + 1, n) if rng.random() < p]
         rp, col = edges_to_csr(n, edges)
@@ -135,6 +139,21 @@ def _bounds_hold(rp, col, p, q, rho, L, color, k, seed):
     assert k <= (deg.max() + 1 if n else 0)
 
 
+def _counters_hold(rp, col, rho, st):
+    """The oracle's ADG counters against their closed forms.  A vertex of
+    round r belongs to U_1 .. U_r, so sum over rounds of |U_l| = sum of rho.
+    UPDATE decrements D[u] for every edge between R_l and U_l \\ R_l: each
+    undirected edge whose endpoints leave in different rounds is counted
+    once (when its lower-round end is removed), an edge inside one round
+    never (both ends leave together)."""
+    n = rp.size - 1
+    rho = np.asarray(rho, dtype=np.int64)
+    assert st["sum_active"] == int(rho.sum())
+    src = np.repeat(np.arange(n), np.diff(rp))
+    cut = int(np.count_nonzero(rho[src] != rho[col])) // 2 if n else 0
+    assert st["cut_edges"] == cut
+
+
 # ---------------------------------------------------------------- exhaustive small graphs
 
 @pytest.mark.parametrize("n", [0, 1, 2, 3, 4, 5])
@@ -144,23 +163,42 @@ def test_all_graphs_up_to_5_vertices(n):
         edges = [pairs[i] for i in range(len(pairs)) if mask >> i & 1]
         rp, col = edges_to_csr(n, edges)
         for (p, q) in EPS:
-            color, k, rho, L, _ = oracle.color_graph(rp, col, p, q, seed=mask)
+            color, k, rho, L, st = oracle.color_graph(rp, col, p, q, seed=mask)
             _bounds_hold(rp, col, p, q, rho, L, color, k, mask)
+            _counters_hold(rp, col, rho, st)
 
 
-def test_all_graphs_with_6_vertices_two_eps():
+@pytest.mark.parametrize("eps", EPS)
+def test_all_graphs_with_6_vertices(eps):
     n = 6
+    p, q = eps
     pairs = [(u, v) for u in range(n) for v in range(u + 1, n)]
-    rng = np.random.default_rng(11)
-    masks = range(1 << len(pairs))
-    for mask in masks:
+    for mask in range(1 << len(pairs)):
         edges = [pairs[i] for i in range(len(pairs)) if mask >> i & 1]
         rp, col = edges_to_csr(n, edges)
-        p, q = EPS[int(rng.integers(0, len(EPS)))]
-        rho, L, _ = oracle.adg(rp, col, p, q)
+        rho, L, st = oracle.adg(rp, col, p, q)
         check_adg(rp, col, p, q, rho, L)
+        _counters_hold(rp, col, rho, st)
         color, k = oracle.jp(rp, col, rho, mask)
         check_jp(rp, col, rho, mask, color)
+
+
+def test_sampled_graphs_with_7_vertices():
+    # 2^21 labelled graphs on 7 vertices: a seeded sample of 3000 masks, at
+    # every eps
+    n = 7
+    pairs = [(u, v) for u in range(n) for v in range(u + 1, n)]
+    rng = np.random.default_rng(12)
+    for mask in rng.integers(0, 1 << len(pairs), 3000):
+        mask = int(mask)
+        edges = [pairs[i] for i in range(len(pairs)) if mask >> i & 1]
+        rp, col = edges_to_csr(n, edges)
+        for (p, q) in EPS:
+            rho, L, st = oracle.adg(rp, col, p, q)
+            check_adg(rp, col, p, q, rho, L)
+            _counters_hold(rp, col, rho, st)
+            color, k = oracle.jp(rp, col, rho, mask)
+            check_jp(rp, col, rho, mask, color)
 
 
 @pytest.mark.parametrize("seed", range(6))
@@ -178,7 +216,7 @@ def test_random_graphs_medium(seed):
         for (p, q) in [(0, 1), (1, 100), (1, 10), (1, 2)]:
             color, k, rho, L, st = oracle.color_graph(rp, col, p, q, seed=trial)
             _bounds_hold(rp, col, p, q, rho, L, color, k, trial)
-            assert st["sum_active"] >= rp.size - 1
+            _counters_hold(rp, col, rho, st)
 
 
 # ---------------------------------------------------------------- closed forms
