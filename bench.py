@@ -1,25 +1,32 @@
 #!/usr/bin/env python3
 """Benchmark: edges coloured per second by JP-ADG (ADG + JP) on one MI355X.
 
-Default workload: R-MAT scale 22, edge factor 16, (a, b, c) = (0.57, 0.19,
-0.19), symmetrised and deduplicated, eps = 1/10, seed 2 -- the single-graph
-configuration the headline metric is quoted on.  One step = one color_graph
-call (all of ADG and JP) on the graph already resident in HBM.
+Default workload: R-MAT scale 26 (2^26 vertices, edge factor 16, (a, b, c) =
+(0.57, 0.19, 0.19), symmetrised and deduplicated), eps = 1/10, seed 3 -- the
+single-graph configuration on which the HBM roofline fraction is measured.
+One step = one color_graph call (all of ADG and JP) on the graph already
+resident in HBM.  The same resident graph is also timed at eps = 1/100 and
+1/2 (the sweep of that configuration), and the batched and served workloads
+are run small beside it, each against plain per-graph calls.
 
-Other workloads (--workload): R-MAT scale 26 at eps 1/100, 1/10, 1/2 (seed 3),
-the Erdos-Renyi parity graph, and the batched workload (4096 Chung-Lu graphs
-in one color_graph_batched launch, compared with 4096 plain color_graph
-calls on the same GPU).
+Other workloads (--workload): R-MAT scale 22 (eps 1/10, seed 2), R-MAT scale
+26 at eps 1/100 or 1/2 as the main line, the Erdos-Renyi parity graph, the
+batched workload (4096 Chung-Lu graphs in one color_graph_batched launch,
+against 4096 plain color_graph calls on the same GPU) and the scaled-down
+serving stream.
 
 Prints one JSON line.  Extra fields:
-  roofline      the dominant kernel's algorithmic bytes per launch over its
+  roofline      the dominant kernel (class) with the method's algorithmic
+                bytes per launch (per undirected edge, vertex and
+                vertex-round, as the design notes derive them) over its
                 average launch time, measured with HIP events on the launch
                 stream during the timed steps, against the 8 TB/s HBM peak;
                 `traffic` is the HBM bytes per launch from the committed
                 profiler counters when they were taken on the current kernel
-                sources, else null;
-  cpu_baseline  the CPU oracle (serial C) on the same workload, or on the
-                bounded sample named in `sample`.
+                sources, else null; `phases` gives the same fraction for the
+                whole step, for ADG and for JP;
+  cpu_baseline  the CPU oracle (serial C, one core) on the same graph, its
+                result compared with the GPU's (`oracle_parity`).
 """
 import argparse
 import hashlib
@@ -36,9 +43,9 @@ METRIC = "edges colored/sec (ADG+JP) + HBM GB/s; batched/served vs plain per-gra
 
 WORKLOADS = {
     "rmat22": dict(kind="rmat", scale=22, edge_factor=16, eps=(1, 10), seed=2),
-    "rmat26": dict(kind="rmat", scale=26, edge_factor=16, eps=(1, 10), seed=3, cpu_sample_scale=24),
-    "rmat26_e001": dict(kind="rmat", scale=26, edge_factor=16, eps=(1, 100), seed=3, cpu_sample_scale=24),
-    "rmat26_e05": dict(kind="rmat", scale=26, edge_factor=16, eps=(1, 2), seed=3, cpu_sample_scale=24),
+    "rmat26": dict(kind="rmat", scale=26, edge_factor=16, eps=(1, 10), seed=3, sweep=[(1, 100), (1, 2)]),
+    "rmat26_e001": dict(kind="rmat", scale=26, edge_factor=16, eps=(1, 100), seed=3),
+    "rmat26_e05": dict(kind="rmat", scale=26, edge_factor=16, eps=(1, 2), seed=3),
     "er": dict(kind="er", n=10_000, mean_deg=10.0, eps=(1, 100), seed=1),
     "batched": dict(kind="batched", num_graphs=4096, eps=(1, 10), seed=4),
     "serving": dict(kind="serving", requests=240, eps=(1, 10), seed=5, load=0.75, scale_down=False),
@@ -91,6 +98,23 @@ def algorithmic_bytes(cls, n, nnz, st):
     if cls == "batched":
         return 16 * st["sum_active"] + 80 * n + 12 * nnz + 8 * st["cut_edges"] + 20 * m
     return None
+
+
+def phase_bytes(n, nnz, st):
+    """Algorithmic bytes of one step by phase, per the method's own traffic
+    (no caching assumed): ADG moves 8(n+1) of row_ptr and 8n of D and round
+    initialisation, 12 per active vertex per round (its id, its D, its R or
+    U' entry), per vertex its round write (4), its row_ptr pair (16) and
+    |pred| (4), 8 per adjacency entry (the id and its round) and 8 per cut
+    edge (the D read-modify-write); JP moves per vertex its row_ptr pair
+    (16), frontier entries in and out and its colour (12) and |pred| (4),
+    8 per adjacency entry (id and round) and per undirected edge the
+    predecessor's colour (4) and the successor's count read-modify-write
+    (8).  Whole step: 22 nnz + 8 X + 72 n + 12 sum|U_l|."""
+    m = nnz // 2
+    adg_b = 40 * n + 8 + 12 * st["sum_active"] + 8 * nnz + 8 * st["cut_edges"]
+    jp_b = 32 * n + 8 * nnz + 12 * m
+    return adg_b, jp_b
 
 
 def source_digest(kernel):
@@ -148,16 +172,12 @@ def host_description():
 
 
 def cpu_baseline_graph(w, rp, col, m, variant=0):
-    """The oracle on the workload's graph (for RMAT-26, on the same generator
-    at a smaller scale: a bounded sample of about 10-30 s of CPU work), serial
-    and pinned to one core, ADG and the colouring timed apart, repeated."""
+    """The oracle on the workload's whole graph, serial and pinned to one
+    core, ADG and the colouring timed apart, repeated while the sample stays
+    within about 15 s (one run at R-MAT scale 26, about a minute).  Returns
+    the record and the last run's (rounds, colours)."""
     import oracle
     sample = "whole graph"
-    if "cpu_sample_scale" in w:
-        import graphgen
-        rp, col = graphgen.rmat_config(w["cpu_sample_scale"], seed=w["seed"], edge_factor=w["edge_factor"])
-        m = col.size // 2
-        sample = "R-MAT scale %d, same generator parameters and seed (m = %d)" % (w["cpu_sample_scale"], m)
     p, q, seed = w["eps"][0], w["eps"][1], w["seed"]
     variant &= 7   # pull UPDATE has the same output; the oracle pushes
     if variant & 4:
@@ -185,7 +205,7 @@ def cpu_baseline_graph(w, rp, col, m, variant=0):
             t0 = time.perf_counter()
             o = order()
             t1 = time.perf_counter()
-            colour(o)
+            res = colour(o)
             t2 = time.perf_counter()
             t_ord.append(t1 - t0)
             t_col.append(t2 - t1)
@@ -201,7 +221,7 @@ def cpu_baseline_graph(w, rp, col, m, variant=0):
                      (sample, what, len(t_ord), core, a, c),
            "runs": len(t_ord), "order_s": round(a, 4), "colour_s": round(c, 4), "pinned_cpu": core}
     rec.update(host_description())
-    return rec
+    return rec, (o, res[0])
 
 
 def calibration_copy(mib):
@@ -217,7 +237,7 @@ def calibration_copy(mib):
     del ca, cb
 
 
-def roofline_record(dom, tot_ms, launches, steps, step_bytes, kname, workload, extra=None):
+def roofline_record(tot_ms, launches, steps, step_bytes, kname, workload, extra=None):
     per_launch_ms = tot_ms / launches
     launches_per_step = launches / steps
     bytes_per_launch = step_bytes / launches_per_step
@@ -255,7 +275,30 @@ def er_single_launch(args, rp, col, p, q, seed, colour_ref):
             "same_colouring_as_color_graph": same}
 
 
+def time_steps(step, steps):
+    """Per-step wall times of `steps` calls (each synchronised), and the total."""
+    import torch
+    times = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
+    return times, time.perf_counter() - t0
+
+
+def phase_record(name, nbytes, ms_per_step, launches_per_step=None):
+    achieved = nbytes / (ms_per_step * 1e-3) / 1e9 if ms_per_step > 0 else 0.0
+    r = {"algorithmic_bytes": int(nbytes), "ms": round(ms_per_step, 3), "achieved": round(achieved, 1),
+         "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    if launches_per_step is not None:
+        r["launches"] = launches_per_step
+    return r
+
+
 def run_single(args, w):
+    import numpy as np
     import torch
 
     import paper_2008_11321_amd as adg
@@ -274,12 +317,15 @@ def run_single(args, w):
 
     variant = VARIANTS[args.variant]
 
-    def step():
-        if variant:
-            adg.color_graph_ex(g, p, q, seed, variant, workspace=ws)
-        else:
-            adg.color_graph(g, p, q, seed, workspace=ws, out=out)
+    def make_step(pp, qq):
+        def step():
+            if variant:
+                adg.color_graph_ex(g, pp, qq, seed, variant, workspace=ws, out=out)
+            else:
+                adg.color_graph(g, pp, qq, seed, workspace=ws, out=out)
+        return step
 
+    step = make_step(p, q)
     calibration_copy(args.calib_mib)
     for _ in range(args.warmup):
         step()
@@ -287,45 +333,48 @@ def run_single(args, w):
     log("warm-up done")
     adg.profile_read()  # drop anything recorded so far
     # Kernel time, on the launch stream, during the timed steps: HIP events
-    # around every UPDATE launch, and one pair around each call's JP (or
-    # DEC-ADG-ITR) loop counted as the launches issued in it.  (An event pair
-    # around each of JP's thousands of short launches would cost host time
-    # and slow the very steps being timed.)
-    adg.profile_enable(["update", "update_huge", "update_pull", "jp_phase", "dec_phase"])
+    # around every UPDATE launch, and one pair around each call's ADG round
+    # loop and JP (or DEC-ADG-ITR) loop, counted as the launches issued in
+    # it.  (An event pair around each of JP's thousands of short launches
+    # would cost host time and slow the very steps being timed.)
+    adg.profile_enable(["update", "update_huge", "update_pull", "adg_phase", "jp_phase", "dec_phase"])
     torch.cuda.synchronize()
-    times = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        step()
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - ts)
-    dt = time.perf_counter() - t0
+    times, dt = time_steps(step, args.steps)
     adg.profile_enable([])
     prof = adg.profile_read()
     st = adg.get_stats(ws)
-    log("timed steps done: %.3f ms/step" % (dt * 1000 / args.steps))
+    assert st["error"] == 0, st
+    gpu_colour = out[0][:n].cpu().numpy()
+    gpu_round = out[1][:n].cpu().numpy() if not variant or variant & 4 else None
+    ms_step = dt * 1000 / args.steps
+    log("timed steps done: %.3f ms/step" % ms_step)
 
-    # dominant kernel class: largest share of the timed region.  JP runs as
-    # single-block steps (jp_narrow) and grid-wide steps (jp); its algorithmic
-    # bytes are charged to the two together.
-    # (DEC-ADG-ITR's triples of pull, pick and resolve take JP's place)
-    jp_ms = prof.get("jp_phase", (0, 0))[0] + prof.get("dec_phase", (0, 0))[0]
-    jp_launches = prof.get("jp_phase", (0, 0))[1] + prof.get("dec_phase", (0, 0))[1]
-    upd_ms = prof.get("update", (0.0, 0))[0] + prof.get("update_huge", (0.0, 0))[0] + \
-        prof.get("update_pull", (0.0, 0))[0]
-    upd_launches = prof.get("update", (0.0, 0))[1]
-    if jp_ms >= upd_ms:
-        dom, tot_ms, launches, kname = "jp", jp_ms, jp_launches, (
-            "k_dec_pull+k_dec_pick+k_dec_resolve" if variant & 4 else "k_jp_narrow+k_jp_grid")
+    # phases: ADG (all round kernels) and JP (single-block and grid steps;
+    # DEC-ADG-ITR's pull, pick and resolve take its place)
+    P = lambda k: prof.get(k, (0.0, 0))
+    jp_ms = (P("jp_phase")[0] + P("dec_phase")[0]) / args.steps
+    jp_launches = (P("jp_phase")[1] + P("dec_phase")[1]) / args.steps
+    adg_ms = P("adg_phase")[0] / args.steps
+    upd_ms = (P("update")[0] + P("update_huge")[0] + P("update_pull")[0]) / args.steps
+    upd_launches = P("update")[1] / args.steps
+    adg_b, jp_b = phase_bytes(n, nnz, st)
+    phases = {"step": phase_record("step", adg_b + jp_b, ms_step),
+              "adg": phase_record("adg", adg_b, adg_ms),
+              "jp": phase_record("jp", jp_b, jp_ms, jp_launches),
+              "update": dict(phase_record("update", algorithmic_bytes("update", n, nnz, st), upd_ms,
+                                          upd_launches), model="UPDATE's own traffic (see algorithmic_bytes)")}
+    # the dominant kernel class: the larger share of the step
+    if jp_ms >= adg_ms:
+        kname = "k_dec_pull+k_dec_pick+k_dec_resolve" if variant & 4 else "k_jp_narrow+k_jp_grid"
+        dom_bytes, dom_ms, dom_launches = jp_b, jp_ms, jp_launches
     else:
-        dom, tot_ms, launches, kname = "update", upd_ms, upd_launches, "k_update"
-    roofline = roofline_record(dom, tot_ms, launches, args.steps, algorithmic_bytes(dom, n, nnz, st), kname,
+        kname, dom_bytes, dom_ms, dom_launches = "k_update", algorithmic_bytes("update", n, nnz, st), upd_ms, \
+            upd_launches
+    roofline = roofline_record(dom_ms * args.steps, dom_launches * args.steps, args.steps, dom_bytes, kname,
                                args.workload,
-                               {"phase_ms_per_step": {"update": round(upd_ms / args.steps, 3),
-                                                      "jp": round(jp_ms / args.steps, 3)},
+                               {"phases": phases,
                                 "timing": "HIP events on the launch stream in the timed steps: a pair around "
-                                          "each UPDATE launch, one around each call's JP loop"})
+                                          "each UPDATE launch, one around each call's ADG loop and JP loop"})
     if args.breakdown:
         adg.profile_enable(adg.KERNEL_CLASSES)
         step()
@@ -336,16 +385,49 @@ def run_single(args, w):
         log("  stats", st)
 
     extra = {"step_ms": step_stats(times)}
+    # the other eps of the configuration, on the same resident graph
+    if w.get("sweep") and not variant and not args.no_sweep:
+        sweep = {}
+        for pp, qq in w["sweep"]:
+            sp = make_step(pp, qq)
+            sp()
+            torch.cuda.synchronize()
+            adg.profile_read()
+            adg.profile_enable(["adg_phase", "jp_phase"])
+            tt, dd = time_steps(sp, args.steps)
+            adg.profile_enable([])
+            pr = adg.profile_read()
+            s2 = adg.get_stats(ws)
+            a2, j2 = phase_bytes(n, nnz, s2)
+            ms2 = dd * 1000 / args.steps
+            sweep["%d/%d" % (pp, qq)] = {
+                "value": m / (dd / args.steps), "ms_per_step": round(ms2, 3), "step_ms": step_stats(tt),
+                "rounds": s2["num_rounds"], "colors": s2["num_colors"],
+                "adg_ms": round(pr.get("adg_phase", (0.0, 0))[0] / args.steps, 3),
+                "jp_ms": round(pr.get("jp_phase", (0.0, 0))[0] / args.steps, 3),
+                "frac_step": phase_record("step", a2 + j2, ms2)["frac"]}
+            log("eps %d/%d: %.3f ms/step" % (pp, qq, ms2))
+        extra["eps_sweep"] = sweep
+        step()   # leave the main eps's result in the outputs
+        torch.cuda.synchronize()
     if w["kind"] == "er" and not variant:
         extra["single_launch_batched"] = er_single_launch(args, rp, col, p, q, seed, out[0][:n])
-    cpu = None if args.no_cpu_baseline else cpu_baseline_graph(w, rp, col, m, variant)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu, (o_round, o_colour) = cpu_baseline_graph(w, rp, col, m, variant)
+        par = {"colours_equal": bool(np.array_equal(o_colour, gpu_colour)),
+               "num_colors": [int(st["num_colors"]), int(o_colour.max()) if n else 0]}
+        if gpu_round is not None:
+            par["rounds_equal"] = bool(np.array_equal(o_round, gpu_round))
+        extra["oracle_parity"] = par
+        log("oracle parity:", par)
     cfg = {"workload": args.workload, "graph": w["kind"], "n": n, "nnz": nnz, "m": m, "eps": "%d/%d" % (p, q),
            "seed": seed, "rounds": st["num_rounds"], "colors": st["num_colors"]}
     if variant:
         cfg["variant"] = args.variant
     if w["kind"] == "rmat":
         cfg.update(scale=w["scale"], edge_factor=w["edge_factor"], abcd=[0.57, 0.19, 0.19, 0.05])
-    return m / (dt / args.steps), dt * 1000 / args.steps, cfg, roofline, cpu, extra
+    return m / (dt / args.steps), ms_step, cfg, roofline, cpu, extra
 
 
 def run_batched(args, w):
@@ -393,7 +475,7 @@ def run_batched(args, w):
     assert st["error"] == 0, st
     log("timed steps done: %.3f ms/step" % (dt * 1000 / args.steps))
     b_ms, b_launches = prof["batched"]
-    roofline = roofline_record("batched", b_ms, b_launches, args.steps,
+    roofline = roofline_record(b_ms, b_launches, args.steps,
                                algorithmic_bytes("batched", batch.total_n, batch.total_nnz, st), "k_batched",
                                args.workload)
 
@@ -533,6 +615,38 @@ def run_serving(args, w):
     return served["edges_per_s"], served["span_s"] * 1000, cfg, roofline, cpu, extra
 
 
+def side_runs(args):
+    """Batched and served against plain per-graph calls, run small beside the
+    single-graph line: the full batched workload (4096 Chung-Lu graphs, one
+    launch) with 10 timed launches, and the scaled-down serving stream.  No
+    CPU baselines here."""
+    import gc
+
+    import torch
+    gc.collect()
+    torch.cuda.empty_cache()
+    out = {}
+    a = argparse.Namespace(**vars(args))
+    a.no_cpu_baseline, a.steps, a.warmup, a.calib_mib = True, 10, 2, 0
+    t0 = time.time()
+    value, ms, cfg, roof, _, extra = run_batched(a, WORKLOADS["batched"])
+    out["batched_vs_plain"] = {"workload": "batched", "value": value, "unit": "edges/s", "ms_per_launch": ms,
+                               "plain_per_graph": extra["plain_per_graph"],
+                               "speedup_vs_plain": extra["speedup_vs_plain"], "roofline_frac": roof["frac"],
+                               "launch_shape": cfg["launch_shape"], "wall_s": round(time.time() - t0, 1)}
+    gc.collect()
+    torch.cuda.empty_cache()
+    t0 = time.time()
+    value, ms, cfg, roof, _, extra = run_serving(a, WORKLOADS["serving_small"])
+    out["served_vs_plain"] = {"workload": "serving_small", "value": value, "unit": "edges/s",
+                              "requests": cfg["requests"], "offered_qps": cfg["offered_qps"],
+                              "latency_ms": extra["latency_ms"], "saturation": extra["saturation"],
+                              "plain_per_graph": extra["plain_per_graph"],
+                              "speedup_vs_plain_saturated": extra["speedup_vs_plain_saturated"],
+                              "wall_s": round(time.time() - t0, 1)}
+    return out
+
+
 # ADG variant bits of color_graph_ex (0 = Algorithm 1)
 VARIANTS = {"adg": 0, "sorted": 1, "median": 2, "sorted_median": 3, "dec": 4, "dec_median": 6, "pull": 8}
 
@@ -543,8 +657,11 @@ def main():
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default: 30 for single graphs, 5 at R-MAT scale 26, 20 batched)")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="rmat26", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the other eps of the R-MAT scale 26 configuration")
+    ap.add_argument("--no-side", action="store_true",
+                    help="skip the small batched and served runs beside the single-graph line")
     ap.add_argument("--variant", default="adg", choices=sorted(VARIANTS),
                     help="single-graph workloads: adg = JP-ADG (default), sorted = JP-ADG-O, median = JP-ADG-M, dec = DEC-ADG-ITR, pull = JP-ADG with pull UPDATE")
     ap.add_argument("--breakdown", action="store_true", help="print per-kernel-class times to stderr")
@@ -566,6 +683,8 @@ def main():
         args.steps, args.warmup = 1, 1   # one timed stream after one warm-up pass
     else:
         value, ms_per_step, cfg, roofline, cpu, extra = run_single(args, w)
+        if args.workload == "rmat26" and args.variant == "adg" and not args.no_side:
+            extra.update(side_runs(args))
     rec = {"metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "int32", "data": "synthetic", "config": cfg, "roofline": roofline,

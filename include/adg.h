@@ -39,11 +39,18 @@
  *     caller-provided workspace of at least *_workspace_bytes() bytes,
  *     256-byte aligned; its contents on entry are ignored.
  *   - Calls are issued on `stream` (a hipStream_t; NULL = default stream).
- *     adg_order and color_graph wait on the stream a few times to learn when
- *     the round loop has ended (the number of rounds is data dependent), so
- *     they return only after the ADG phase has finished on the device; the
- *     JP phase and jp_color are fully asynchronous.  Outputs are valid once
- *     the stream is synchronised.
+ *     The single-graph calls (adg_order, jp_color, color_graph and their _ex
+ *     forms) cannot know in advance how many ADG rounds or JP levels a graph
+ *     needs, so they read a finish flag from the device between chunks of
+ *     launches: they block the calling thread on hipStreamSynchronize(stream)
+ *     several times (ADG: after 8 rounds, then after chunks of 16, 32, 64;
+ *     JP: after chunks of 2, 4, ..., 256 kernel pairs; jp_color also once
+ *     after building the DAG) and return once those loops have ended on the
+ *     device.  The last kernels (num_colors, the scalar outputs, the pos
+ *     sort) are still queued when they return: outputs are valid once the
+ *     stream is synchronised.  Because of the waits these calls cannot be
+ *     recorded into a HIP graph.  color_graph_batched never waits and can
+ *     be captured; adg_get_stats and adg_validate_csr are synchronous.
  *   - Return value: ADG_OK (0) or a negative ADG_ERR_* code; no exception
  *     crosses the ABI.  adg_error_string() names a code.
  */

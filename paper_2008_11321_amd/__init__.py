@@ -48,7 +48,7 @@ class _Profile(ctypes.Structure):
 
 KERNEL_CLASSES = ["init", "stats", "count", "scan", "scatter", "update", "part1", "jp_prep", "jp", "finish",
                   "batched", "jp_narrow", "update_huge", "median_select", "order_sort", "dec_itr", "update_pull",
-                  "jp_phase", "dec_phase"]
+                  "jp_phase", "dec_phase", "adg_phase"]
 
 # ADG variants (bit set): ADG-O's sorted rounds and ADG-M's median selection
 SORTED = 1
@@ -235,16 +235,20 @@ def adg_order_ex(g, eps_num, eps_den, seed, variant, want_pos=True, workspace=No
     return rnd[:g.n], (pos[:g.n] if pos is not None else None), nr
 
 
-def color_graph_ex(g, eps_num, eps_den, seed, variant, workspace=None, stream=None, want_rounds=True):
+def color_graph_ex(g, eps_num, eps_den, seed, variant, workspace=None, stream=None, want_rounds=True, out=None):
     """JP-ADG with a variant (SORTED = JP-ADG-O, MEDIAN = JP-ADG-M; DEC_ITR =
     DEC-ADG-ITR's colouring instead of JP, alone or with MEDIAN).  Returns
-    (color, num_colors, round or None, num_rounds) as GPU tensors."""
+    (color, num_colors, round or None, num_rounds) as GPU tensors.  ``out``
+    may hold preallocated (color, round, num_colors, num_rounds) tensors."""
     torch = _torch()
     ws = _workspace(g, workspace)
-    color = torch.empty(max(g.n, 1), dtype=torch.int32, device=g.device)
-    rnd = torch.empty(max(g.n, 1), dtype=torch.int32, device=g.device) if want_rounds else None
-    nc = torch.zeros(1, dtype=torch.int32, device=g.device)
-    nr = torch.zeros(1, dtype=torch.int32, device=g.device)
+    if out is None:
+        color = torch.empty(max(g.n, 1), dtype=torch.int32, device=g.device)
+        rnd = torch.empty(max(g.n, 1), dtype=torch.int32, device=g.device) if want_rounds else None
+        nc = torch.zeros(1, dtype=torch.int32, device=g.device)
+        nr = torch.zeros(1, dtype=torch.int32, device=g.device)
+    else:
+        color, rnd, nc, nr = out
     csr = g.csr()
     rc = lib().color_graph_ex(ctypes.byref(csr), int(eps_num), int(eps_den), int(seed) & (2**64 - 1), int(variant),
                               _ptr(color), _ptr(rnd) if rnd is not None else ctypes.c_void_p(0), _ptr(nc), _ptr(nr),

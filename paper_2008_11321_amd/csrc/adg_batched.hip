@@ -279,7 +279,7 @@ __device__ int adg_graph(const BParams& P, const GraphCtx& C, Lds<BB>& S, long l
       if (tid == 0) atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
       return l - 1;
     }
-    const unsigned long long T = ((P.q + P.p) * Ssum) / (P.q * N);
+    const unsigned long long T = mul_div_floor_sat(P.q + P.p, Ssum, P.q * N, ~0ull);   // 128-bit product
     *act += (long long)N;
     // ---- selection: U_l -> R_l | U_{l+1}, stable
     long long nr = 0, nu = 0, sstay = 0;

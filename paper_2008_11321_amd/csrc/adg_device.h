@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "adg_intmath.h"
+
 namespace adg {
 
 constexpr int WAVE = 64;

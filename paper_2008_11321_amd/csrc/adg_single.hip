@@ -374,10 +374,11 @@ __global__ void k_stats(Params P, int l) {
     c->num_rounds = l - 1;
     return;
   }
-  unsigned long long T = ((P.q + P.p) * S) / (P.q * N);
+  // (q + p) S can pass 2^64: formed in 128 bits; D never exceeds 2^31 - 1
+  const unsigned long long T = mul_div_floor_sat(P.q + P.p, S, P.q * N, 0x7fffffffull);
   c->N = N;
   c->S = S;
-  c->T = (unsigned)(T > 0x7fffffffull ? 0x7fffffffull : T);
+  c->T = (unsigned)T;
   c->round = l;
   c->sum_active += N;
   if (P.median) {
@@ -1299,6 +1300,47 @@ struct JpStage {
   unsigned long long* acc;      // LDS [2]: this block's share of psum and ssum (null: sums not kept)
 };
 
+// ---- bounds on indices that come from device state
+//
+// The vertex ids, list positions, DAG entries and bitmap words the JP steps
+// use are all derived from what earlier steps stored (level lists, DAG rows,
+// JP records, counters).  They are in range whenever those steps are
+// correct; these checks keep a broken state from becoming an access outside
+// the workspace: the call then reports ADG_ERR_INTERNAL and the work item is
+// dropped.
+__device__ __forceinline__ void raise_internal(const Params& P) { atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL); }
+__device__ __forceinline__ bool vid_ok(const Params& P, int v) {
+  if ((unsigned)v < (unsigned)P.n) return true;
+  raise_internal(P);
+  return false;
+}
+// A same-round successor range [s0, s1) of the DAG rows.
+__device__ __forceinline__ bool range_ok(const Params& P, long long s0, long long s1) {
+  if (s0 >= 0 && s0 <= s1 && s1 <= P.nnz) return true;
+  raise_internal(P);
+  return false;
+}
+// A level-list slot (the lists hold at most n entries).
+__device__ __forceinline__ bool slot_ok(const Params& P, unsigned at) {
+  if (at < (unsigned)P.n) return true;
+  raise_internal(P);
+  return false;
+}
+
+// The sizes of a level's lists, and of round r's first level and slot.
+__device__ __forceinline__ bool level_ok(const Params& P, unsigned nf, unsigned nh) {
+  if (nf <= (unsigned)P.n && nh <= P.hub_cap) return true;
+  raise_internal(P);
+  return false;
+}
+__device__ __forceinline__ bool round_ok(const Params& P, int r) {
+  if (r >= 1 && P.roundN[r] <= (unsigned)P.n && P.roundN[r + 1] <= P.roundN[r] &&
+      P.l0n[r] <= P.roundN[r] - P.roundN[r + 1])
+    return true;
+  raise_internal(P);
+  return false;
+}
+
 // Append u (ready; JP record ur) to the global lists of level l + 1.
 template <int S>
 __device__ __forceinline__ void jp_append(const Params& P, JpStage& st, int l, bool rdy, int u, const JpRec& ur) {
@@ -1336,7 +1378,7 @@ __device__ __forceinline__ void jp_append(const Params& P, JpStage& st, int l, b
     unsigned g = 0;
     if (lane_id() == 0) g = add32<S>(&st.fcnt[(l + 1) % 3], k);
     g = readlane_u(g, 0);
-    if (plain) sti<S>((int*)&P.F[(l + 1) & 1][g + lanes_below(m)], u);
+    if (plain && slot_ok(P, g + lanes_below(m))) sti<S>((int*)&P.F[(l + 1) & 1][g + lanes_below(m)], u);
     return;
   }
   unsigned base = 0;
@@ -1349,7 +1391,8 @@ __device__ __forceinline__ void jp_append(const Params& P, JpStage& st, int l, b
     unsigned g = 0;
     if (lane_id() == 0) g = add32<S>(&st.fcnt[(l + 1) % 3], (unsigned)__popcll(om));
     g = readlane_u(g, 0);
-    if (plain && pos >= (unsigned)FB_CAP) sti<S>((int*)&P.F[(l + 1) & 1][g + lanes_below(om)], u);
+    if (plain && pos >= (unsigned)FB_CAP && slot_ok(P, g + lanes_below(om)))
+      sti<S>((int*)&P.F[(l + 1) & 1][g + lanes_below(om)], u);
   }
 }
 
@@ -1370,7 +1413,7 @@ __device__ __forceinline__ void jp_stage_flush(const Params& P, JpStage& st, int
   }
   __syncthreads();
   for (unsigned i = threadIdx.x; i < k; i += blockDim.x)
-    sti<S>((int*)&P.F[(l + 1) & 1][gbase + i], (int)st.buf[i]);
+    if (slot_ok(P, gbase + i)) sti<S>((int*)&P.F[(l + 1) & 1][gbase + i], (int)st.buf[i]);
   __syncthreads();
   if (threadIdx.x == 0) *st.cnt = 0;
   __syncthreads();
@@ -1381,7 +1424,9 @@ template <int S>
 __device__ __forceinline__ void bm_mark(const Params& P, unsigned long long rec, int c) {
   if (c >= 1 && c <= (int)(unsigned)rec + 2) {
     const unsigned b = (unsigned)(c - 1);
-    __hip_atomic_fetch_or(&P.B[(rec >> 32) + (b >> 5)], 1u << (b & 31), __ATOMIC_RELAXED, S);
+    const unsigned long long at = (rec >> 32) + (b >> 5);
+    if (at < P.bm_cap) __hip_atomic_fetch_or(&P.B[at], 1u << (b & 31), __ATOMIC_RELAXED, S);
+    else raise_internal(P);
   }
 }
 
@@ -1396,7 +1441,9 @@ __device__ __forceinline__ bool jp_push(const Params& P, int u, unsigned long lo
 
 // A bitmap word, read at the device's coherence point (atomics update it).
 __device__ __forceinline__ unsigned bm_load(const Params& P, unsigned long long at) {
-  return agent_load_u32(&P.B[at]);
+  if (at < P.bm_cap) return agent_load_u32(&P.B[at]);
+  raise_internal(P);
+  return ~0u;
 }
 
 // Colour of a finished vertex (also read at the coherence point).
@@ -1518,9 +1565,15 @@ __device__ void jp_xpull_items(const Params& P, WaveLds& W, int r, long long gw,
     int x = 0;
     if (ok) {
       const int v = P.ORD[b + i];
-      x = P.npred[v] - P.cnt[v];   // predecessors from later rounds (cnt is untouched until the round starts)
-      W.rec[lane] = rec_of(P, v);
-      W.pb[lane] = P.rp[v];
+      if (vid_ok(P, v)) {
+        x = P.npred[v] - P.cnt[v];   // predecessors from later rounds (cnt is untouched until the round starts)
+        W.rec[lane] = rec_of(P, v);
+        W.pb[lane] = P.rp[v];
+        if (x < 0 || x > P.rp[v + 1] - W.pb[lane]) {
+          raise_internal(P);
+          x = 0;
+        }
+      }
     }
     int tot;
     W.off[lane] = wave_excl_scan<int>(x, &tot);
@@ -1539,7 +1592,7 @@ __device__ void jp_xpull_items(const Params& P, WaveLds& W, int r, long long gw,
         }
       }
 #pragma unroll
-      for (int t = 0; t < JP_UNROLL; ++t) c[t] = own[t] >= 0 ? done_colour(P, c[t]) : 0;
+      for (int t = 0; t < JP_UNROLL; ++t) c[t] = own[t] >= 0 && vid_ok(P, c[t]) ? done_colour(P, c[t]) : 0;
 #pragma unroll
       for (int t = 0; t < JP_UNROLL; ++t)
         if (own[t] >= 0) bm_mark<S>(P, W.rec[own[t]], c[t]);
@@ -1555,8 +1608,10 @@ __device__ void jp_split_items(const Params& P, JpStage& st, int r, long long gw
   for (long long g = gw; g * WAVE < sz; g += gstride) {
     const long long i = g * WAVE + lane;
     const bool ok = i < sz;
-    const int v = ok ? (int)P.L0[b + i] : 0;
-    jp_append<SC_AGENT>(P, st, -1, ok, v, ok ? rec_pair(P, v) : JpRec{0, 0});
+    int v = ok ? (int)P.L0[b + i] : 0;
+    const bool good = ok && vid_ok(P, v);
+    if (!good) v = 0;
+    jp_append<SC_AGENT>(P, st, -1, good, v, good ? rec_pair(P, v) : JpRec{0, 0});
   }
 }
 
@@ -1567,15 +1622,16 @@ __device__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, 
                                long long gw, long long gstride, const unsigned long long* hlds) {
   const unsigned lane = lane_id();
   const unsigned nh = (unsigned)hc;
-  const unsigned nch = (unsigned)(hc >> 32);
+  const unsigned nch = nh ? (unsigned)(hc >> 32) : 0;   // chunks come with their entries
   const unsigned* Fl = P.F[l & 1];
   const unsigned long long* Hl = P.H[l & 1];
   const long long groups = ((long long)nf + WAVE - 1) / WAVE;
   for (long long it = gw; it < groups + (long long)nch; it += gstride) {
     if (it < groups) {
       const long long idx = it * WAVE + lane;
-      const bool act = idx < nf;
-      const int v = act ? (int)ld32<SC_AGENT>(&Fl[idx]) : 0;
+      int v = idx < nf ? (int)ld32<SC_AGENT>(&Fl[idx]) : 0;
+      const bool act = idx < nf && vid_ok(P, v);
+      if (!act) v = 0;
       unsigned long long rec = 0;
       long long s0 = 0, s1 = 0;
       if (act) {
@@ -1583,6 +1639,7 @@ __device__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, 
         rec = pr.rec;
         s0 = sp_first(pr.sp);
         s1 = s0 + sp_count(P, v, pr.sp);
+        if (!range_ok(P, s0, s1)) s1 = s0;
       }
       // the first successors are fetched together with the bitmap words
       int u[JP_UNROLL];
@@ -1591,6 +1648,7 @@ __device__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, 
       for (int t = 0; t < JP_UNROLL; ++t) {
         ok[t] = act && s0 + t < s1;
         u[t] = ok[t] ? P.dag[s0 + t] : 0;
+        ok[t] = ok[t] && vid_ok(P, u[t]);
       }
       const int col = wave_colour(P, W, act, rec);
       if (act) sti<SC_AGENT>(&P.color[v], col);
@@ -1601,6 +1659,7 @@ __device__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, 
           for (int t = 0; t < JP_UNROLL; ++t) {
             ok[t] = act && j + t < s1;
             u[t] = ok[t] ? P.dag[j + t] : 0;
+            ok[t] = ok[t] && vid_ok(P, u[t]);
           }
         }
 #pragma unroll
@@ -1616,13 +1675,18 @@ __device__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, 
       const unsigned long long ent = fan_entry<SC_AGENT>(Hl, nh, k, hlds);
       const int v = (int)(unsigned)ent;
       const unsigned first = (unsigned)(ent >> 32);
+      if (!vid_ok(P, v) || first > k) {
+        raise_internal(P);
+        continue;
+      }
       const JpRec pr = rec_pair(P, v);
       const unsigned long long rec = pr.rec;
       // the chunk's successors (one wavefront step) are fetched together
       // with the bitmap words
       const long long b = sp_first(pr.sp), e = b + sp_count(P, v, pr.sp);
       const long long s0 = b + (long long)(k - first) * JP_CHUNK;
-      const long long s1 = s0 + JP_CHUNK < e ? s0 + JP_CHUNK : e;
+      long long s1 = s0 + JP_CHUNK < e ? s0 + JP_CHUNK : e;
+      if (!range_ok(P, s0, s1)) s1 = s0;
       int u[JP_CU];
       bool ok[JP_CU];
 #pragma unroll
@@ -1630,6 +1694,7 @@ __device__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, 
         const long long j = s0 + t * WAVE + lane;
         ok[t] = j < s1;
         u[t] = ok[t] ? P.dag[j] : 0;
+        ok[t] = ok[t] && vid_ok(P, u[t]);
       }
       // the whole wavefront reads v's bitmap: first clear bit
       const unsigned nw = bm_words((int)(unsigned)rec);
@@ -1728,6 +1793,7 @@ __device__ __forceinline__ void narrow_append(const Params& P, NarrowLds& Z, JpS
   for (int q = 0; q < NARROW_UNROLL; ++q) {   // row start and successors from the record
     pb[q] = rdy[q] ? sp_first(usp[q]) - (long long)(unsigned)urec[q] : 0;
     ns[q] = rdy[q] ? sp_count(P, u[q], usp[q]) : 0;
+    if (rdy[q] && !range_ok(P, sp_first(usp[q]), sp_first(usp[q]) + ns[q])) ns[q] = 0;
   }
   unsigned base = 0;
   if (lane_id() == 0) base = atomicAdd(&Z.cnt[nx], tot);
@@ -1758,7 +1824,7 @@ __device__ void narrow_flush(const Params& P, NarrowLds& Z, JpStage& st, int cur
   const unsigned n = Z.cnt[cur] < (unsigned)NARROW_MAX ? Z.cnt[cur] : (unsigned)NARROW_MAX;
   for (unsigned b = 0; b < n; b += NARROW_BS) {
     const unsigned i = b + threadIdx.x;
-    const bool ok = i < n;
+    const bool ok = i < n && Z.v[cur][i] >= 0;
     const int v = ok ? Z.v[cur][i] : 0;
     const int ns = ok ? Z.ns[cur][i] : 0;
     const bool fan = ok && ns > JP_SMALL;
@@ -1774,32 +1840,46 @@ __device__ void narrow_flush(const Params& P, NarrowLds& Z, JpStage& st, int cur
       unsigned g = 0;
       if (lane_id() == 0) g = add32<SC_WG>(&st.fcnt[l % 3], (unsigned)__popcll(m));
       g = readlane_u(g, 0);
-      if (ok && !fan) sti<SC_WG>((int*)&P.F[l & 1][g + lanes_below(m)], v);
+      if (ok && !fan && slot_ok(P, g + lanes_below(m))) sti<SC_WG>((int*)&P.F[l & 1][g + lanes_below(m)], v);
     }
   }
 }
 
+// Entry i of an LDS list: vertex v with its row start, JP record and
+// same-round successor count; a vertex id or successor range out of bounds
+// (a broken state) becomes an empty entry (v = -1, no bitmap word beyond the
+// first, no successors).
+__device__ __forceinline__ void narrow_put(const Params& P, NarrowLds& Z, int cur, unsigned i, int v) {
+  long long pb = 0;
+  unsigned long long rec = 0;
+  int ns = 0;
+  if (vid_ok(P, v)) {
+    const JpRec pr = rec_pair(P, v);
+    ns = sp_count(P, v, pr.sp);
+    if (range_ok(P, sp_first(pr.sp), sp_first(pr.sp) + ns)) {
+      pb = sp_first(pr.sp) - (long long)(unsigned)pr.rec;
+      rec = pr.rec;
+    } else {
+      ns = 0;
+      v = -1;
+    }
+  } else {
+    v = -1;
+  }
+  Z.v[cur][i] = v;
+  Z.pb[cur][i] = pb;
+  Z.rec[cur][i] = rec;
+  Z.ns[cur][i] = ns;
+}
+
 // Block-wide: n vertices from a global list into LDS list `cur` at `at`.
 __device__ void narrow_load(const Params& P, NarrowLds& Z, int cur, const unsigned* src, unsigned n) {
-  for (unsigned i = threadIdx.x; i < n; i += NARROW_BS) {
-    const int v = (int)ld32<SC_AGENT>(&src[i]);
-    const JpRec pr = rec_pair(P, v);
-    Z.v[cur][i] = v;
-    Z.pb[cur][i] = sp_first(pr.sp) - (long long)(unsigned)pr.rec;
-    Z.rec[cur][i] = pr.rec;
-    Z.ns[cur][i] = sp_count(P, v, pr.sp);
-  }
+  for (unsigned i = threadIdx.x; i < n; i += NARROW_BS) narrow_put(P, Z, cur, i, (int)ld32<SC_AGENT>(&src[i]));
 }
 __device__ void narrow_load_fan(const Params& P, NarrowLds& Z, int cur, const unsigned long long* src, unsigned n,
                                 unsigned at) {
-  for (unsigned i = threadIdx.x; i < n; i += NARROW_BS) {
-    const int v = (int)(unsigned)ld64<SC_AGENT>(&src[i]);
-    const JpRec pr = rec_pair(P, v);
-    Z.v[cur][at + i] = v;
-    Z.pb[cur][at + i] = sp_first(pr.sp) - (long long)(unsigned)pr.rec;
-    Z.rec[cur][at + i] = pr.rec;
-    Z.ns[cur][at + i] = sp_count(P, v, pr.sp);
-  }
+  for (unsigned i = threadIdx.x; i < n; i += NARROW_BS)
+    narrow_put(P, Z, cur, at + i, (int)(unsigned)ld64<SC_AGENT>(&src[i]));
 }
 
 // Block-wide exclusive scans of two per-thread values (thread t: entry t).
@@ -1871,6 +1951,7 @@ __device__ bool narrow_level(const Params& P, NarrowLds& Z, JpStage& st, int cur
     if (e < stot) {
       sk[q] = owner(Z.soff, nv, e);
       su[q] = P.dag[Z.pb[cur][sk[q]] + (int)(unsigned)Z.rec[cur][sk[q]] + (e - Z.soff[sk[q]])];
+      if (!vid_ok(P, su[q])) su[q] = -1;
     }
   }
   for (unsigned e0 = 0; e0 < wtot; e0 += NARROW_BS * NARROW_UNROLL) {
@@ -1911,7 +1992,7 @@ __device__ bool narrow_level(const Params& P, NarrowLds& Z, JpStage& st, int cur
       c = f + 1;
     }
     Z.col[t] = c;
-    sti<SC_WG>(&P.color[Z.v[cur][t]], c);
+    if (Z.v[cur][t] >= 0) sti<SC_WG>(&P.color[Z.v[cur][t]], c);
   }
   __syncthreads();
   // push the colours to the same-round successors
@@ -1925,6 +2006,7 @@ __device__ bool narrow_level(const Params& P, NarrowLds& Z, JpStage& st, int cur
         if (e < stot) {
           sk[q] = owner(Z.soff, nv, e);
           su[q] = P.dag[Z.pb[cur][sk[q]] + (int)(unsigned)Z.rec[cur][sk[q]] + (e - Z.soff[sk[q]])];
+          if (!vid_ok(P, su[q])) su[q] = -1;
         }
       }
 #pragma unroll
@@ -1956,6 +2038,7 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_narrow(Params P, int max_steps
   if (threadIdx.x == 0) {
     S = c->js;
     have = 0;
+    if (c->error) S.done = 1;   // raised by an earlier step: JP stops
     // launches alternate (single-block, grid): the op posted by the previous
     // single-block launch has been run by the grid launch between them
     if (!S.done) {
@@ -1976,6 +2059,12 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_narrow(Params P, int max_steps
     if (S.done) break;
     const int r = S.round;
     const int l = S.level;
+    if (!round_ok(P, r) || !level_ok(P, S.fcnt[l % 3], (unsigned)S.hctr[l % 3])) {
+      __syncthreads();
+      if (threadIdx.x == 0) S.done = 1;   // a broken state: stop (the error is raised)
+      __syncthreads();
+      break;
+    }
     if (S.xpull) {
       if (seg_size(P, r) > (long long)NARROW_XPULL) {
         handed = OP_XPULL;
@@ -2096,6 +2185,9 @@ __global__ __launch_bounds__(BS) void k_jp_grid(Params P) {
   // may start after others have finished (other streams' kernels hold CUs).
   const int op = c->grid_op;
   if (c->js.done || op == OP_NONE) return;
+  if (!round_ok(P, c->js.round) ||
+      !level_ok(P, c->js.fcnt[c->js.level % 3], (unsigned)c->js.hctr[c->js.level % 3]))
+    return;
   {
     // blocks past the step's work leave at once (block 0 stays: it reports)
     const int r = c->js.round, l = c->js.level;
@@ -2438,7 +2530,7 @@ namespace {
 const char* kclass_names[KC_NUM] = {"init", "stats", "count", "scan", "scatter", "update", "part1",
                                     "jp_prep", "jp", "finish", "batched", "jp_narrow", "update_huge",
                                     "median_select", "order_sort", "dec_itr", "update_pull", "jp_phase",
-                                    "dec_phase"};
+                                    "dec_phase", "adg_phase"};
 static_assert(KC_NUM <= ADG_PROFILE_CLASSES, "profile classes do not fit adg_profile_t");
 struct ProfRec {
   int cls;
@@ -2736,6 +2828,8 @@ int run_adg(Params& P, hipStream_t s, bool fused, int* num_rounds_host) {
   if (!h) return ADG_ERR_HIP;
   int l = 1;
   int chunk = 8;
+  // one event pair around the whole round loop (host round trips included)
+  ProfScope phase(KC_ADG_PHASE, s);
   while (true) {
     for (int k = 0; k < chunk; ++k, ++l) {
       {
@@ -2843,8 +2937,10 @@ int run_jp(Params& P, hipStream_t s, int rounds) {
       pairs += chunk;
       phase.units = 2 * pairs;
       HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(h, &P.ctrl->js.done, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(&h[0], &P.ctrl->js.done, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(&h[1], &P.ctrl->error, sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
+      if (h[1]) return h[1];   // a device-side check failed (JP stops by itself)
       if (h[0]) break;
       if (pairs > max_pairs) return ADG_ERR_INTERNAL;
       chunk = std::min(chunk * 2, 256);

@@ -115,3 +115,41 @@ def test_profile_class_names_match_the_binding():
         assert L.adg_kernel_class_name(i).decode() == name, i
     assert L.adg_kernel_class_name(len(pkg.KERNEL_CLASSES)).decode() == ""
     assert len(pkg.KERNEL_CLASSES) <= 32
+
+
+def test_threshold_product_is_exact_beyond_64_bits(tmp_path):
+    """Algorithm 1's threshold floor((q+p) S / (q N)) as the kernels compute it
+    (the header both paths include, built for the host) against Python's exact
+    integers, also where (q+p) S passes 2^64: p, q up to 2^31 - 1 and S up to
+    2^37 adjacency entries are accepted at the boundary."""
+    import random
+    import subprocess
+    csrc = os.path.join(os.path.dirname(pkg.__file__), "csrc")
+    src = tmp_path / "t.cpp"
+    src.write_text('#include "adg_intmath.h"\n#include <cstdio>\n'
+                   'int main() { unsigned long long a, b, d, c;\n'
+                   '  while (scanf("%llu %llu %llu %llu", &a, &b, &d, &c) == 4)\n'
+                   '    printf("%llu\\n", (unsigned long long)adg::mul_div_floor_sat(a, b, d, c));\n'
+                   '  return 0; }\n')
+    exe = tmp_path / "t"
+    subprocess.run(["hipcc", "-x", "hip", "--cuda-host-only", "-O2", "-std=c++17", "-I", csrc, str(src), "-o",
+                    str(exe)], check=True, capture_output=True)
+    M = 2**64 - 1
+    rng = random.Random(7)
+    cases = [(3, 5, 2, 100), (2**32, 2**37, 1, M), (2**32, 2**37, 2**62, M), (2**32 - 2, 2**37 - 1, 3 * 2**30, M),
+             (2**32, 2**36 + 12345, 2**31 - 1, 2**31 - 1), (1, M, 1, M), (M, M, M, M), (M, M, M - 1, M),
+             (2**33, 2**33, 2**2, M), (2**31 + 5, 2**40 + 3, 2**31 * 7, M), (0, 5, 3, M), (5, 0, 3, M)]
+    for _ in range(3000):
+        q = rng.randrange(1, 2**31)
+        p = rng.randrange(0, 2**31)
+        S = rng.randrange(0, 2**38)
+        N = rng.randrange(1, 2**31)
+        cases.append((q + p, S, q * N, rng.choice([2**31 - 1, M])))
+    for _ in range(1000):
+        a, b, d = rng.randrange(0, 2**64), rng.randrange(0, 2**64), rng.randrange(1, 2**64)
+        cases.append((a, b, d, M))
+    inp = "".join("%d %d %d %d\n" % c for c in cases)
+    out = subprocess.run([str(exe)], input=inp, capture_output=True, text=True, check=True).stdout.split()
+    assert len(out) == len(cases)
+    for (a, b, d, cap), got in zip(cases, out):
+        assert int(got) == min(a * b // d, cap), (a, b, d, cap)

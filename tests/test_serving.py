@@ -48,9 +48,12 @@ def test_alone_and_in_the_mix_give_the_same_result(sv):
         a, m = alone[i], mix[i]
         oc, ok, _, oL, _ = oracle.color_graph(rp, col, 1, 10, 5)
         da, dm = int((a["color"] != oc).sum()), int((m["color"] != oc).sum())
-        if a["status"] or m["status"] or da or dm or a["num_rounds"] != oL or m["num_rounds"] != oL:
+        if (a["status"] or m["status"] or da or dm or a["num_rounds"] != oL or m["num_rounds"] != oL
+                or a["num_colors"] != ok or m["num_colors"] != ok):
             bad.append(dict(request=i, n=rp.size - 1, nnz=col.size, status=(a["status"], m["status"]),
-                            wrong_alone=da, wrong_mix=dm, group=m["group_size"]))
+                            wrong_alone=da, wrong_mix=dm, group=m["group_size"],
+                            colours=(a["num_colors"], m["num_colors"], ok),
+                            rounds=(a["num_rounds"], m["num_rounds"], oL)))
     print("requests that differ from the oracle:", bad, flush=True)
     assert not bad
 
@@ -69,6 +72,7 @@ def test_small_arena_admits_by_footprint(sv):
     for i, (rp, col) in enumerate(graphs):
         oc, ok, _, oL, _ = oracle.color_graph(rp, col, 1, 10, 6)
         assert res[i]["status"] == 0 and np.array_equal(res[i]["color"], oc), i
+        assert res[i]["num_colors"] == ok and res[i]["num_rounds"] == oL, (i, res[i]["num_colors"], ok)
 
 
 @pytest.mark.gpu

@@ -1,7 +1,9 @@
 """The RMAT-26 configuration (n = 2^26, edge factor 16, eps = 1/10, seed 3:
 the bench's rmat26 workload, in the launch configuration bench.py times),
-checked on the GPU output against properties that define the result at any
-size -- the oracle's serial run is too slow for a test at this size:
+compared element by element with the serial CPU oracle at eps = 1/100, 1/10
+and 1/2 (the three oracle runs start on host threads when the graph is made
+and finish while the other tests use the GPU), and checked on the GPU output
+against properties that define the result at any size:
 
 * ADG (Algorithm 1): for every round l, with U_l = {v : round(v) >= l} and
   deg_U recomputed from the graph, exactly the vertices of U_l with
@@ -196,22 +198,34 @@ def check_jp(torch, rp, col_d, rnd, color, seed, device):
         del src, c, pred, used
 
 
+EPS_ALL = [(1, 100), (1, 10), (1, 2)]
+
+
 @pytest.fixture(scope="module")
 def rmat26():
+    """The graph on the GPU, and the serial oracle's JP-ADG at the three eps
+    of the configuration started on host threads (the C oracle runs outside
+    the interpreter lock), so that they run while the GPU tests do."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import torch
 
+    import oracle
     import paper_2008_11321_amd as pkg
     assert torch.cuda.is_available()
     print("case rmat26 full size: generating", flush=True)
     rp, col = graphgen.rmat_config(26, seed=3)
     g = pkg.Graph(rp, col)
     print("n", g.n, "nnz", g.nnz, flush=True)
-    return pkg, rp, g
+    pool = ThreadPoolExecutor(max_workers=len(EPS_ALL))
+    runs = {pq: pool.submit(oracle.color_graph, rp, col, pq[0], pq[1], 3) for pq in EPS_ALL}
+    yield pkg, rp, g, runs
+    pool.shutdown(wait=True, cancel_futures=True)
 
 
 def test_rmat26_at_full_size(rmat26):
     import torch
-    pkg, rp, g = rmat26
+    pkg, rp, g, _ = rmat26
     seed, p, q = 3, 1, 10
     ws = torch.empty(pkg.workspace_bytes(g.n, g.nnz), dtype=torch.uint8, device="cuda")
     color, nc, rnd, nr = pkg.color_graph(g, p, q, seed, workspace=ws)
@@ -229,7 +243,7 @@ def test_rmat26_at_full_size(rmat26):
 def test_rmat26_sorted_and_median_at_full_size(rmat26):
     """JP-ADG-O (colours and the total order) and ADG-M with JP-ADG-M."""
     import torch
-    pkg, rp, g = rmat26
+    pkg, rp, g, _ = rmat26
     seed, p, q = 3, 1, 10
     ws = torch.empty(pkg.order_workspace_bytes(g.n, g.nnz), dtype=torch.uint8, device="cuda")
     color, nc, rnd, nr = pkg.color_graph_ex(g, p, q, seed, pkg.SORTED, workspace=ws)
@@ -252,7 +266,7 @@ def test_rmat26_other_eps_at_full_size(rmat26, p, q):
     """The other eps of the RMAT-26 configuration (the bench's rmat26_e001 and
     rmat26_e05 workloads): eps = 1/100 takes many rounds."""
     import torch
-    pkg, rp, g = rmat26
+    pkg, rp, g, _ = rmat26
     seed = 3
     print("case rmat26 eps %d/%d" % (p, q), flush=True)
     ws = torch.empty(pkg.workspace_bytes(g.n, g.nnz), dtype=torch.uint8, device="cuda")
@@ -266,3 +280,32 @@ def test_rmat26_other_eps_at_full_size(rmat26, p, q):
     assert check_adg_by_removal(torch, rp, g.col_idx, rnd, p, q, "cuda") == st["sum_active"]
     check_jp(torch, rp, g.col_idx, rnd, color, seed, "cuda")
     print("rmat26 eps %d/%d checked" % (p, q), flush=True)
+
+
+@pytest.mark.parametrize("p,q", EPS_ALL)
+def test_rmat26_equals_the_oracle(rmat26, p, q):
+    """Element by element against the serial CPU oracle (Algorithm 1 step by
+    step, then greedy colouring in decreasing <round, rho_R> order) at every
+    eps of the configuration: rounds, colours, L, the colour count and the
+    counters sum |U_l| and cut edges."""
+    import torch
+    pkg, rp, g, runs = rmat26
+    seed = 3
+    print("case rmat26 eps %d/%d vs the oracle" % (p, q), flush=True)
+    ws = torch.empty(pkg.workspace_bytes(g.n, g.nnz), dtype=torch.uint8, device="cuda")
+    color, nc, rnd, nr = pkg.color_graph(g, p, q, seed, workspace=ws)
+    torch.cuda.synchronize()
+    st = pkg.get_stats(ws)
+    del ws
+    colour_h, rnd_h = color.cpu().numpy(), rnd.cpu().numpy()
+    del color, rnd
+    oc, ok, orho, oL, ost = runs[(p, q)].result(timeout=600)
+    print("gpu: rounds", int(nr.item()), "colours", int(nc.item()), "oracle: rounds", oL, "colours", ok, flush=True)
+    assert st["error"] == 0
+    assert int(nr.item()) == oL and st["num_rounds"] == oL
+    assert int(nc.item()) == ok and st["num_colors"] == ok
+    assert st["sum_active"] == ost["sum_active"] and st["cut_edges"] == ost["cut_edges"]
+    bad_r = int((rnd_h != orho).sum())
+    bad_c = int((colour_h != oc).sum())
+    assert bad_r == 0, "%d rounds differ" % bad_r
+    assert bad_c == 0, "%d colours differ" % bad_c
