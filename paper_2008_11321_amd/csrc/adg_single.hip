@@ -2054,16 +2054,22 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_narrow(Params P, int max_steps
   WaveLds& W = Z.wl[threadIdx.x / WAVE];
   int cur = 0;
   int handed = OP_NONE;
+  int checked = 0;          // the round whose sizes have been checked
   bool in_global = false;   // the LDS level is also in the global lists
   for (int step = 0; step < max_steps; ++step) {
     if (S.done) break;
     const int r = S.round;
     const int l = S.level;
-    if (!round_ok(P, r) || !level_ok(P, S.fcnt[l % 3], (unsigned)S.hctr[l % 3])) {
+    if (r != checked || !level_ok(P, S.fcnt[l % 3], (unsigned)S.hctr[l % 3])) {
+      // a round's sizes are checked once, when it starts
+      const bool ok = level_ok(P, S.fcnt[l % 3], (unsigned)S.hctr[l % 3]) && round_ok(P, r);
       __syncthreads();
-      if (threadIdx.x == 0) S.done = 1;   // a broken state: stop (the error is raised)
-      __syncthreads();
-      break;
+      if (!ok) {
+        if (threadIdx.x == 0) S.done = 1;   // a broken state: stop (the error is raised)
+        __syncthreads();
+        break;
+      }
+      checked = r;
     }
     if (S.xpull) {
       if (seg_size(P, r) > (long long)NARROW_XPULL) {
@@ -2185,16 +2191,20 @@ __global__ __launch_bounds__(BS) void k_jp_grid(Params P) {
   // may start after others have finished (other streams' kernels hold CUs).
   const int op = c->grid_op;
   if (c->js.done || op == OP_NONE) return;
-  if (!round_ok(P, c->js.round) ||
-      !level_ok(P, c->js.fcnt[c->js.level % 3], (unsigned)c->js.hctr[c->js.level % 3]))
-    return;
   {
-    // blocks past the step's work leave at once (block 0 stays: it reports)
+    // blocks past the step's work leave at once (block 0 stays: it reports);
+    // the round's sizes were checked by the single-block step that handed
+    // the step over
     const int r = c->js.round, l = c->js.level;
     long long items;
-    if (op == OP_XPULL) items = (seg_size(P, r) + WAVE - 1) / WAVE;
-    else if (op == OP_SPLIT) items = ((long long)P.l0n[r] + WAVE - 1) / WAVE;
-    else items = ((long long)c->js.fcnt[l % 3] + WAVE - 1) / WAVE + (long long)(c->js.hctr[l % 3] >> 32);
+    if (op == OP_XPULL) {
+      items = (seg_size(P, r) + WAVE - 1) / WAVE;
+    } else if (op == OP_SPLIT) {
+      items = ((long long)P.l0n[r] + WAVE - 1) / WAVE;
+    } else {
+      if (!level_ok(P, c->js.fcnt[l % 3], (unsigned)c->js.hctr[l % 3])) return;
+      items = ((long long)c->js.fcnt[l % 3] + WAVE - 1) / WAVE + (long long)(c->js.hctr[l % 3] >> 32);
+    }
     if (blockIdx.x > 0 && (long long)blockIdx.x * WPB >= items) return;
   }
   __shared__ unsigned fbuf[FB_CAP];
