@@ -70,8 +70,10 @@ enum {
   ADG_ERR_WORKSPACE = -2,   /* workspace missing, misaligned or too small */
   ADG_ERR_HIP = -3,         /* a HIP runtime call failed */
   ADG_ERR_INTERNAL = -4,    /* round-count watchdog tripped or device-side check failed */
-  ADG_ERR_UNSUPPORTED = -5  /* input outside the supported range: nnz / 32 + 2 n >= 2^32 for the
+  ADG_ERR_UNSUPPORTED = -5, /* input outside the supported range: nnz / 32 + 2 n >= 2^32 for the
                                single-graph calls; a serving request larger than the arena */
+  ADG_ERR_SCRATCH = -6      /* color_graph_static: the graph needs more workspace than the
+                               library's static scratch (adg_static_scratch_bytes) */
 };
 
 /* CSR view of one graph; all pointers are device pointers. */
@@ -180,6 +182,32 @@ int adg_order_ex(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_t 
 int color_graph_ex(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_t seed, uint32_t variant,
                    int32_t* color_out, int32_t* round_out, int32_t* num_colors_out,
                    int32_t* num_rounds_out, void* workspace, size_t ws_bytes, void* stream);
+
+/* ---- Allocation-free JP-ADG, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).
+ *
+ * Computes exactly what color_graph computes, with the same arguments except
+ * the workspace: the library's own static device array of
+ * adg_static_scratch_bytes() bytes (128 MiB) serves as the workspace.  Each
+ * GPU the library runs on holds one such array from when the library's code
+ * is loaded on it until the process ends.  The call makes no device or host
+ * memory allocation (hipMalloc, hipHostMalloc, or any allocating library
+ * routine), records no profiling events, and reads the loop flags through
+ * pageable memory on the calling thread's stack; it synchronises the stream
+ * as color_graph does.  The caller still owns and passes every output.
+ *
+ * The array keeps the last call's contents; nothing in it is assumed on
+ * entry.  Calls that overlap on one GPU -- from several threads or streams
+ * -- share the array and race: serialise them.  A graph whose workspace
+ * (adg_workspace_bytes(n, nnz)) exceeds the array returns ADG_ERR_SCRATCH
+ * before any device work.  Other errors: as color_graph. */
+int color_graph_static(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_t seed,
+                       int32_t* color_out, int32_t* round_out, int32_t* num_colors_out,
+                       int32_t* num_rounds_out, void* stream);
+
+/* Bytes of color_graph_static's static scratch (the largest workspace it takes). */
+size_t adg_static_scratch_bytes(void);
 
 /* ---- Many independent graphs in one call.
  *

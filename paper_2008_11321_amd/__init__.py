@@ -23,7 +23,7 @@ __all__ = [
 
 ADG_OK = 0
 _ERRS = {-1: "ADG_ERR_ARG", -2: "ADG_ERR_WORKSPACE", -3: "ADG_ERR_HIP", -4: "ADG_ERR_INTERNAL",
-         -5: "ADG_ERR_UNSUPPORTED"}
+         -5: "ADG_ERR_UNSUPPORTED", -6: "ADG_ERR_SCRATCH"}
 
 
 class AdgError(RuntimeError):
@@ -95,6 +95,10 @@ def lib():
     L.adg_profile_read.argtypes = [P(_Profile)]
     L.adg_kernel_class_name.restype = ctypes.c_char_p
     L.adg_kernel_class_name.argtypes = [ctypes.c_int]
+    L.color_graph_static.restype = ctypes.c_int
+    L.color_graph_static.argtypes = [P(_Csr), i32, i32, u64, vp, vp, vp, vp, vp]
+    L.adg_static_scratch_bytes.restype = sz
+    L.adg_static_scratch_bytes.argtypes = []
     _lib = L
     return L
 
@@ -254,6 +258,24 @@ def color_graph_ex(g, eps_num, eps_den, seed, variant, workspace=None, stream=No
                               _ptr(color), _ptr(rnd) if rnd is not None else ctypes.c_void_p(0), _ptr(nc), _ptr(nr),
                               _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "color_graph_ex")
+    return color[:g.n], nc, (rnd[:g.n] if rnd is not None else None), nr
+
+
+def static_scratch_bytes():
+    """Size of the static scratch color_graph_static works in."""
+    return int(lib().adg_static_scratch_bytes())
+
+
+def color_graph_static(g, eps_num, eps_den, seed, out, stream=None):
+    """JP-ADG through the allocation-free entry point: the caller passes
+    every output, preallocated, as ``out`` = (color, round or None,
+    num_colors, num_rounds); the library works in its static scratch."""
+    color, rnd, nc, nr = out
+    csr = g.csr()
+    rc = lib().color_graph_static(ctypes.byref(csr), int(eps_num), int(eps_den), int(seed) & (2**64 - 1),
+                                  _ptr(color), _ptr(rnd) if rnd is not None else ctypes.c_void_p(0), _ptr(nc),
+                                  _ptr(nr), _stream(stream))
+    _check(rc, "color_graph_static")
     return color[:g.n], nc, (rnd[:g.n] if rnd is not None else None), nr
 
 

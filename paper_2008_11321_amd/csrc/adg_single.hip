@@ -2564,7 +2564,12 @@ hipEvent_t prof_event() {
 }
 }  // namespace
 
+// Set while an allocation-free call runs on this thread: no event is
+// recorded and the loop flags are read through the caller's stack.
+thread_local bool t_no_alloc = false;
+
 hipEvent_t prof_begin(int cls, hipStream_t s) {
+  if (t_no_alloc) return nullptr;
   std::lock_guard<std::mutex> g(g_prof_mu);
   if (!(g_prof_mask & (1u << cls))) return nullptr;
   hipEvent_t a = prof_event();
@@ -2804,7 +2809,12 @@ std::vector<int*> g_flag_pool;
 
 struct PinnedFlags {
   int* h = nullptr;
+  int local[4] = {0, 0, 0, 0};   // pageable words for allocation-free calls
   PinnedFlags() {
+    if (t_no_alloc) {
+      h = local;
+      return;
+    }
     {
       std::lock_guard<std::mutex> g(g_flag_mu);
       if (!g_flag_pool.empty()) {
@@ -2816,7 +2826,7 @@ struct PinnedFlags {
     if (hipHostMalloc((void**)&h, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) h = nullptr;
   }
   ~PinnedFlags() {
-    if (!h) return;
+    if (!h || h == local) return;
     std::lock_guard<std::mutex> g(g_flag_mu);
     g_flag_pool.push_back(h);
   }
@@ -3040,6 +3050,41 @@ int run_order(Params& P, hipStream_t s, int rounds, void* ws, int32_t* pos_out) 
   return ADG_OK;
 }
 
+// ---- workspace of the allocation-free entry point (color_graph_static)
+//
+// A file-scope device array: each GPU the library runs on holds one copy
+// from the time the library's code is loaded on it until the process ends.
+// Host code never passes the array's name to a kernel (on the host it only
+// stands for the symbol); it looks up the array's device address once per
+// device with hipGetSymbolAddress and passes that address.
+constexpr size_t STATIC_SCRATCH_BYTES = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// The scratch array's address on the current device.
+int static_scratch(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return ADG_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || ((uintptr_t)p & 255)) return ADG_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return ADG_OK;
+}
+
+struct NoAllocScope {
+  NoAllocScope() { t_no_alloc = true; }
+  ~NoAllocScope() { t_no_alloc = false; }
+};
+
 }  // namespace
 
 extern "C" {
@@ -3146,6 +3191,22 @@ int color_graph_ex(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_
   return ADG_OK;
 }
 
+int color_graph_static(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_t seed, int32_t* color_out,
+                       int32_t* round_out, int32_t* num_colors_out, int32_t* num_rounds_out, void* stream) {
+  int rc = check_graph(g);
+  if (rc) return rc;
+  if (eps_num < 0 || eps_den < 1 || (g->n > 0 && !color_out)) return ADG_ERR_ARG;
+  const size_t need = make_layout(g->n, g->nnz).total;
+  if (need > STATIC_SCRATCH_BYTES) return ADG_ERR_SCRATCH;
+  void* ws = nullptr;
+  if ((rc = static_scratch(&ws))) return rc;
+  NoAllocScope na;
+  return color_graph_ex(g, eps_num, eps_den, seed, 0, color_out, round_out, num_colors_out, num_rounds_out, ws,
+                        STATIC_SCRATCH_BYTES, stream);
+}
+
+size_t adg_static_scratch_bytes(void) { return STATIC_SCRATCH_BYTES; }
+
 int adg_get_stats(const void* workspace, size_t ws_bytes, adg_stats_t* out, void* stream) {
   if (!workspace || !out || ws_bytes < sizeof(Ctrl)) return ADG_ERR_ARG;
   Ctrl h;
@@ -3219,6 +3280,7 @@ const char* adg_error_string(int code) {
     case ADG_ERR_HIP: return "HIP runtime error";
     case ADG_ERR_INTERNAL: return "internal error (watchdog or device-side check)";
     case ADG_ERR_UNSUPPORTED: return "input outside the supported range";
+    case ADG_ERR_SCRATCH: return "graph too large for the allocation-free entry point's static scratch";
     default: return "unknown error";
   }
 }
