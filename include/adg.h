@@ -42,7 +42,8 @@
  *     The single-graph calls (adg_order, jp_color, color_graph and their _ex
  *     forms) cannot know in advance how many ADG rounds or JP levels a graph
  *     needs, so they read a finish flag from the device between chunks of
- *     launches: they block the calling thread on hipStreamSynchronize(stream)
+ *     launches (except color_graph on a graph small enough for the
+ *     one-launch engine, see ADG_VARIANT_MULTI_LAUNCH, which never waits): they block the calling thread on hipStreamSynchronize(stream)
  *     several times (ADG: after 8 rounds, then after chunks of 16, 32, 64;
  *     JP: after chunks of 2, 4, ..., 256 kernel pairs; jp_color also once
  *     after building the DAG) and return once those loops have ended on the
@@ -156,9 +157,20 @@ int color_graph(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_t s
  *       subtracts from its own D the number of its neighbours in R, so no
  *       atomics touch D; the rows of the remaining vertices are read every
  *       round.  The output is identical to pushing.  Combines with all.
+ *   ADG_VARIANT_MULTI_LAUNCH  (color_graph_ex only) color_graph hands a graph
+ *       with at most 2^17 entries and vertices to the one-launch engine of
+ *       color_graph_batched (one workgroup colours it, in one launch and
+ *       without waiting on the stream); this bit keeps such a graph on the
+ *       per-round kernels.  The output is the same either way.
  * SORTED and MEDIAN may be combined.  variant = 0 is Algorithm 1 (adg_order,
  * color_graph).  Other bits or combinations: ADG_ERR_ARG. */
-enum { ADG_VARIANT_SORTED = 1, ADG_VARIANT_MEDIAN = 2, ADG_VARIANT_DEC_ITR = 4, ADG_VARIANT_PULL = 8 };
+enum {
+  ADG_VARIANT_SORTED = 1,
+  ADG_VARIANT_MEDIAN = 2,
+  ADG_VARIANT_DEC_ITR = 4,
+  ADG_VARIANT_PULL = 8,
+  ADG_VARIANT_MULTI_LAUNCH = 16
+};
 
 /* Workspace bytes for adg_order_ex with a pos output (adg_workspace_bytes
  * plus sort buffers of 24 n bytes); 0 for invalid sizes. */

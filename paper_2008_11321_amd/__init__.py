@@ -55,6 +55,7 @@ SORTED = 1
 MEDIAN = 2
 DEC_ITR = 4   # colouring by DEC-ADG-ITR instead of JP (color_graph_ex only)
 PULL = 8      # pull (CREW) UPDATE: same output, no atomics on D
+MULTI_LAUNCH = 16   # keep a small graph on the per-round kernels (color_graph_ex only)
 
 _lib = None
 
@@ -64,9 +65,10 @@ def lib():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_build.LIB):
+    path = os.environ.get("ADG_HIP_LIB") or _build.LIB   # another build of the library (tuning runs)
+    if path == _build.LIB and not os.path.exists(path):
         _build.build()
-    L = ctypes.CDLL(_build.LIB)
+    L = ctypes.CDLL(path)
     vp, i32, i64, u64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
     P = ctypes.POINTER
     L.adg_workspace_bytes.restype = sz

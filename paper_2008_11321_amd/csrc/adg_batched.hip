@@ -52,6 +52,7 @@ constexpr int SMALL_ROW = 32;         // lane-per-vertex rows up to this length
 constexpr int SCHED_BS = 1024;        // threads of the schedule kernel
 constexpr int SCHED_BUCKETS = 64;     // work classes (floor(log2(work)))
 constexpr int WG = __HIP_MEMORY_SCOPE_WORKGROUP;
+constexpr int ONE_GRAPH_THREADS = 512;    // workgroup size when one graph is coloured alone
 
 struct BCtrl {
   unsigned int next;              // queue head: graphs claimed so far
@@ -87,8 +88,11 @@ struct BParams {
   unsigned long long* F1;
   unsigned long long* ext;      // extension words; graph g's region starts at rp[vo[g]] / 64 + g
   int* color;                   // [total_n]
-  int* num_colors;              // [G]
+  int* num_colors;              // [G] (nullable for a single graph)
   int* num_rounds;              // [G] (nullable)
+  long long single_n;           // >= 0: one graph of this many vertices, vo in the workspace (k_sched writes it)
+  long long* vo_ws;             // that vo
+  StatsSink sink;               // single graph: its counters for the caller's control block (num_rounds null: none)
 };
 
 // ---------------------------------------------------------------- helpers
@@ -164,6 +168,10 @@ __global__ __launch_bounds__(SCHED_BS) void k_sched(BParams P, int natural) {
   __shared__ unsigned hist[SCHED_BUCKETS];
   __shared__ unsigned base[SCHED_BUCKETS];
   if (threadIdx.x < SCHED_BUCKETS) hist[threadIdx.x] = 0;
+  if (threadIdx.x == 0 && P.single_n >= 0) {
+    P.vo_ws[0] = 0;
+    P.vo_ws[1] = P.single_n;
+  }
   if (threadIdx.x == 0) {
     P.ctrl->next = 0;
     P.ctrl->error = 0;
@@ -526,8 +534,19 @@ __global__ __launch_bounds__(BB) void k_batched(BParams P) {
       K = jp_graph<BB>(P, C, S, f0, &lev);
     }
     if (tid == 0) {
-      P.num_colors[g] = K;
+      if (P.num_colors) P.num_colors[g] = K;
       if (P.num_rounds) P.num_rounds[g] = L;
+      if (P.sink.num_rounds) {   // a single graph for color_graph: its counters
+        *P.sink.num_rounds = L;
+        *P.sink.num_colors = K;
+        *P.sink.sum_active = (unsigned long long)act;
+        *P.sink.cut_edges = (unsigned long long)cut;
+        *P.sink.frontier = (unsigned long long)f0;
+        *P.sink.levels = (int)lev;
+        *P.sink.error = __hip_atomic_load(&P.ctrl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        *P.sink.zero64[0] = 0;
+        *P.sink.zero64[1] = 0;
+      }
       atomicAdd(&P.ctrl->sum_active, (unsigned long long)act);
       atomicAdd(&P.ctrl->cut_edges, (unsigned long long)cut);
       atomicAdd(&P.ctrl->frontier, (unsigned long long)f0);
@@ -638,6 +657,53 @@ int ceil_log2(long long x) {
 TuneKey tune_key(const adg_batch_t* b) { return {b->num_graphs, ceil_log2(b->total_n), ceil_log2(b->total_nnz)}; }
 
 }  // namespace batched
+
+size_t one_graph_bytes(int64_t n, int64_t nnz) { return 256 + batched::make_layout(1, n, nnz).total; }
+
+int color_one_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx, int32_t eps_num,
+                    int32_t eps_den, uint64_t seed, int32_t* color_out, int32_t* round_out, int32_t* num_colors_out,
+                    int32_t* num_rounds_out, void* ws, size_t ws_bytes, hipStream_t s, const StatsSink& sink) {
+  using namespace batched;
+  if (n <= 0 || ((uintptr_t)ws & 255) || ws_bytes < one_graph_bytes(n, nnz)) return ADG_ERR_WORKSPACE;
+  const BLayout L = make_layout(1, n, nnz);
+  char* base = (char*)ws + 256;   // [vo | the batched layout]
+  BParams P{};
+  P.G = 1;
+  P.vo_ws = (long long*)ws;
+  P.vo = P.vo_ws;
+  P.single_n = n;
+  P.rp = (const long long*)row_ptr;
+  P.col = col_idx;
+  P.p = (unsigned long long)eps_num;
+  P.q = (unsigned long long)eps_den;
+  P.hkey = hash_key_from_seed(seed);
+  P.ctrl = (BCtrl*)(base + L.ctrl);
+  P.sched = (int*)(base + L.sched);
+  P.round = round_out ? round_out : (int*)(base + L.round);
+  P.D = (int*)(base + L.D);
+  P.UL0 = (int*)(base + L.UL0);
+  P.UL1 = (int*)(base + L.UL1);
+  P.RL = (int*)(base + L.RL);
+  P.dag = (int*)(base + L.dag);
+  P.npred = (int*)(base + L.npred);
+  P.eoff = (int*)(base + L.eoff);
+  P.word = (unsigned long long*)(base + L.word);
+  P.F0 = (unsigned long long*)(base + L.F0);
+  P.F1 = (unsigned long long*)(base + L.F1);
+  P.ext = (unsigned long long*)(base + L.ext);
+  P.color = color_out;
+  P.num_colors = num_colors_out;
+  P.num_rounds = num_rounds_out;
+  P.sink = sink;
+  {
+    TIMED(KC_BATCH, s);
+    hipLaunchKernelGGL(k_sched, dim3(1), dim3(SCHED_BS), 0, s, P, 1);
+    hipLaunchKernelGGL(k_batched<ONE_GRAPH_THREADS>, dim3(1), dim3(ONE_GRAPH_THREADS), 0, s, P);
+  }
+  HIPCHK(hipGetLastError());
+  return ADG_OK;
+}
+
 }  // namespace adg
 
 using namespace adg;
@@ -697,6 +763,7 @@ int color_graph_batched(const adg_batch_t* b, int32_t eps_num, int32_t eps_den, 
   P.color = color_out;
   P.num_colors = num_colors_out;
   P.num_rounds = num_rounds_out;
+  P.single_n = -1;
   hipStream_t s = (hipStream_t)stream;
   TIMED(KC_BATCH, s);
   hipLaunchKernelGGL(k_sched, dim3(1), dim3(SCHED_BS), 0, s, P, cfg.schedule == ADG_SCHED_NATURAL ? 1 : 0);

@@ -49,6 +49,28 @@ inline uint32_t hash_key_from_seed(uint64_t seed) {
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Where the one-launch engine leaves a single graph's counters when it
+// serves a color_graph call (device pointers into that call's control
+// block; every field is written).
+struct StatsSink {
+  int* num_rounds;
+  int* num_colors;
+  unsigned long long* sum_active;
+  unsigned long long* cut_edges;
+  unsigned long long* frontier;
+  int* levels;
+  int* error;
+  long long* zero64[2];   // counters of other colourings, cleared
+};
+
+// JP-ADG on one graph by the one-launch engine of color_graph_batched (one
+// workgroup colours it; same result as the single-graph kernels).  ws holds
+// one_graph_bytes(n, nnz), 256-byte aligned.
+size_t one_graph_bytes(int64_t n, int64_t nnz);
+int color_one_graph(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx, int32_t eps_num,
+                    int32_t eps_den, uint64_t seed, int32_t* color_out, int32_t* round_out, int32_t* num_colors_out,
+                    int32_t* num_rounds_out, void* ws, size_t ws_bytes, hipStream_t s, const StatsSink& sink);
+
 #define HIPCHK(x)                              \
   do {                                         \
     if ((x) != hipSuccess) return ADG_ERR_HIP; \

@@ -76,6 +76,10 @@ namespace adg {
 constexpr int BS = 256;                 // threads per block
 constexpr int WPB = BS / WAVE;          // wavefronts per block
 constexpr int SEL_BLOCKS = 2048;        // fixed grid of the selection kernels
+#ifndef ADG_UPDATE_ONE_PASS
+#define ADG_UPDATE_ONE_PASS 1
+#endif
+constexpr bool UPDATE_ONE_PASS = ADG_UPDATE_ONE_PASS;   // JP's row partition in one pass (no DEC-ADG-ITR)
 #ifndef ADG_SMALL_DEG
 #define ADG_SMALL_DEG 32
 #endif
@@ -117,6 +121,9 @@ constexpr int NARROW_UNROLL = ADG_NARROW_UNROLL;  // edges per thread in flight 
 constexpr int MSEL_BINS = 2048;              // radix selection: 11-bit digits
 constexpr int MSEL_PASSES = 6;               // 11 x 5 + 9 bits cover a 64-bit key
 constexpr int MSEL_BLOCKS = 512;
+#ifndef ADG_JP_STEPS
+#define ADG_JP_STEPS 1   // JP's narrow and mid-sized steps in one launch of a leader and helper blocks
+#endif
 
 enum { OP_NONE = 0, OP_SPLIT = 1, OP_LEVEL = 2, OP_XPULL = 3 };
 
@@ -186,6 +193,10 @@ struct Ctrl {
   DecState dec[2];
   unsigned dec_unext;          // vertices that gave up their colour (the next U)
   unsigned dec_blocks;         // working blocks of k_dec_resolve done (last-block hand-off)
+  // JP steps launch (k_jp_steps): registration, leader's command, completions
+  unsigned long long preg;
+  unsigned long long pcmd;
+  unsigned long long pjoin;
 };
 
 struct Params {
@@ -241,12 +252,13 @@ struct Params {
 // so a matching code is confirmed against the full round number.
 __device__ __forceinline__ unsigned char round_code(int l) { return (unsigned char)(1 + ((l - 1) % 255)); }
 
-// Scoped accesses for JP data.  The grid-wide kernels exchange data between
-// workgroups and use agent scope; the single-block kernel is one workgroup
-// and uses workgroup scope, which lets its accesses stay in the L2 instead of
-// going to the device coherence point.
+// Scoped accesses for JP data.  JP's steps exchange data between
+// workgroups that may sit on different XCDs (each with its own L2), inside
+// one launch as well as across launches, so every access to data another
+// workgroup writes or reads in the same launch is at agent scope: loads and
+// stores go to the device's coherence point.  (Read-modify-write atomics are
+// performed there whatever their scope.)
 constexpr int SC_AGENT = __HIP_MEMORY_SCOPE_AGENT;
-constexpr int SC_WG = __HIP_MEMORY_SCOPE_WORKGROUP;
 template <int S>
 __device__ __forceinline__ unsigned long long ld64(const unsigned long long* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, S);
@@ -261,6 +273,10 @@ __device__ __forceinline__ int ldi(const int* p) {
 }
 template <int S>
 __device__ __forceinline__ void st64(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, S);
+}
+template <int S>
+__device__ __forceinline__ void st32(unsigned* p, unsigned v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, S);
 }
 template <int S>
@@ -781,7 +797,7 @@ __device__ __forceinline__ unsigned long long pool_alloc(const Params& P, BmPool
 // to be coloured (cnt = nps), and a cleared colour bitmap from the
 // wavefront's pool (pl) or the bump counter (pl = nullptr);
 // rec[v] = (bitmap offset << 32) | np.
-__device__ __forceinline__ void jp_row(const Params& P, BmPool* pl, bool has, int v, long long b, long long np,
+__device__ __forceinline__ void jp_row(const Params& P, BmPool* pl, bool has, int v, long long first, long long np,
                                        long long ns, long long nps) {
   // JP: bits for colours 1 .. np+2; DEC-ADG-ITR: also the same-round successors
   const long long nb = P.dec ? np + ns : np;
@@ -805,7 +821,7 @@ __device__ __forceinline__ void jp_row(const Params& P, BmPool* pl, bool has, in
   P.cnt[v] = (int)nps;
   P.rec[2 * (size_t)v] = (off << 32) | (unsigned)(P.dec ? np + ns : np);
   P.rec[2 * (size_t)v + 1] =
-      ((unsigned long long)(b + np) << 24) | (ns < (long long)SP_NS_MAX ? (unsigned)ns : SP_NS_MAX);
+      ((unsigned long long)first << 24) | (ns < (long long)SP_NS_MAX ? (unsigned)ns : SP_NS_MAX);
 }
 
 // Wavefront: append the lanes' vertices with z set to the first JP level of
@@ -891,6 +907,34 @@ __device__ void update_small(const Params& P, BmPool* pl, SmallRows& S, int v, b
       S.run[lane][k] = 0;
     }
   wave_sync();
+  if (FUSED && UPDATE_ONE_PASS && !P.dec) {
+    // JP needs the predecessors from later rounds (front of the row) and
+    // the same-round successors (back of the row); same-round predecessors
+    // are only counted.  One pass: each entry goes straight to its place.
+    for (int p0 = 0; p0 < T; p0 += WAVE) {
+      const int pos = p0 + (int)lane;
+      if (pos < T) {
+        const int k = small_owner(S, pos);
+        const long long bk = S.b[k];
+        const int w = P.col[bk + (pos - S.off[k])];
+        const int cl = visit3<true>(P, w, l, code, S.hv[k], x, !P.pull);
+        if (cl == NB_PRED) {
+          P.dag[bk + atomicAdd(&S.run[k][NB_PRED], 1u)] = w;
+        } else if (cl == NB_SUCC_SAME) {
+          const long long ek = bk + (S.off[k + 1] - S.off[k]);
+          P.dag[ek - 1 - atomicAdd(&S.run[k][NB_SUCC_SAME], 1u)] = w;
+        } else if (cl == NB_PRED_SAME) {
+          atomicAdd(&S.run[k][NB_PRED_SAME], 1u);
+        }
+      }
+    }
+    wave_sync();
+    const long long nl = S.run[lane][NB_PRED], nps = S.run[lane][NB_PRED_SAME], ns = S.run[lane][NB_SUCC_SAME];
+    wave_sync();   // the LDS is rewritten by the wavefront's next group of rows
+    jp_row(P, pl, valid, v, e - ns, nl + nps, ns, nps);
+    l0_append(P, l, (long long)P.n - P.roundN[l], valid && nps == 0, v);
+    return;
+  }
   for (int p0 = 0; p0 < T; p0 += WAVE) {
     const int pos = p0 + (int)lane;
     if (pos < T) {
@@ -920,7 +964,7 @@ __device__ void update_small(const Params& P, BmPool* pl, SmallRows& S, int v, b
     }
   }
   wave_sync();   // the LDS is rewritten by the wavefront's next group of rows
-  jp_row(P, pl, valid, v, b, np, ns, nps);
+  jp_row(P, pl, valid, v, b + np, np, ns, nps);
   l0_append(P, l, (long long)P.n - P.roundN[l], valid && nps == 0, v);
 }
 
@@ -956,6 +1000,25 @@ __device__ void update_big(const Params& P, BmPool* pl, L0Stage& l0s, RowMasks& 
   const unsigned long long hv = same_key(P, v);
   const unsigned lane = lane_id();
   long long nl = 0, nps = 0, ns = 0;
+  if (FUSED && UPDATE_ONE_PASS && !P.dec) {
+    // JP: predecessors from later rounds to the front, same-round
+    // successors to the back, same-round predecessors only counted; one pass
+    for (long long base = b; base < e; base += WAVE) {
+      const long long j = base + lane;
+      const bool ok = j < e;
+      const int w = ok ? P.col[j] : 0;
+      const int cl = ok ? visit3<true>(P, w, l, code, hv, x, !P.pull) : NB_NONE;
+      const uint64_t fm = ballot(cl == NB_PRED), gm = ballot(cl == NB_PRED_SAME), sm = ballot(cl == NB_SUCC_SAME);
+      if (cl == NB_PRED) P.dag[b + nl + lanes_below(fm)] = w;
+      else if (cl == NB_SUCC_SAME) P.dag[e - 1 - ns - lanes_below(sm)] = w;
+      nl += __popcll(fm);
+      nps += __popcll(gm);
+      ns += __popcll(sm);
+    }
+    jp_row(P, pl, lane == 0, v, e - ns, nl + nps, ns, nps);
+    l0_stage(P, l0s, l, (long long)P.n - P.roundN[l], nps == 0, v);
+    return;
+  }
   int ch = 0;
   for (long long base = b; base < e; base += WAVE, ++ch) {
     long long j = base + lane;
@@ -996,7 +1059,7 @@ __device__ void update_big(const Params& P, BmPool* pl, L0Stage& l0s, RowMasks& 
     sc += __popcll(sm);
   }
   wave_sync();   // the masks are rewritten by the wavefront's next row
-  jp_row(P, pl, lane == 0, v, b, np, ns, nps);
+  jp_row(P, pl, lane == 0, v, b + np, np, ns, nps);
   l0_stage(P, l0s, l, (long long)P.n - P.roundN[l], nps == 0, v);
 }
 
@@ -1199,7 +1262,7 @@ __global__ __launch_bounds__(BS) void k_update_huge_place(Params P, int l) {
       }
     }
     if (k == first) {
-      jp_row(P, nullptr, lane == 0, v, b, np, ns, nps);
+      jp_row(P, nullptr, lane == 0, v, b + np, np, ns, nps);
       l0_append(P, l, (long long)P.n - P.roundN[l], lane == 0 && nps == 0, v);
     }
   }
@@ -1239,7 +1302,7 @@ __global__ __launch_bounds__(BS) void k_part1(Params P) {
       }
       np = f - b;
     }
-    jp_row(P, &pool, small, v, b, np, (e - b) - np, np);
+    jp_row(P, &pool, small, v, b + np, np, (e - b) - np, np);
     l0_append(P, 1, 0, small && np == 0, v);
     uint64_t big = ballot(valid && !small);
     while (big) {
@@ -1260,7 +1323,7 @@ __global__ __launch_bounds__(BS) void k_part1(Params P) {
         fc += __popcll(pm);
         sc += __popcll(sm);
       }
-      jp_row(P, &pool, lane == 0, u, ub, fc, sc, fc);
+      jp_row(P, &pool, lane == 0, u, ub + fc, fc, sc, fc);
       l0_stage(P, l0s, 1, 0, fc == 0, u);
     }
   }
@@ -1453,8 +1516,20 @@ struct WaveLds {
   int off[WAVE + 1];           // exclusive scan of the lanes' item counts
   unsigned long long rec[WAVE];
   long long pb[WAVE];
-  int ffree[WAVE];             // first clear bit found in the lanes' bitmaps
+  int ffree[WAVE];             // first clear bit found in the lanes' bitmaps (then the lanes' colours)
+  int soff[WAVE + 1];          // exclusive scan of the lanes' same-round successor counts
 };
+
+// Lane k whose range [off[k], off[k+1]) holds position e.
+__device__ __forceinline__ int wave_owner_of(const int* off, int e) {
+  int lo = 0, hi = WAVE;  // last k with off[k] <= e
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= e) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
 
 __device__ __forceinline__ int wave_owner(const WaveLds& W, int e) {
   int lo = 0, hi = WAVE;  // last k with off[k] <= e
@@ -1469,7 +1544,7 @@ __device__ __forceinline__ int wave_owner(const WaveLds& W, int e) {
 // GetColor for every active lane (bitmap rec): the wavefront reads all the
 // lanes' bitmap words, spread evenly over its lanes, and each lane takes the
 // first clear bit of its own.
-__device__ int wave_colour(const Params& P, WaveLds& W, bool act, unsigned long long rec) {
+__device__ __forceinline__ int wave_colour(const Params& P, WaveLds& W, bool act, unsigned long long rec) {
   const unsigned lane = lane_id();
   int tot;
   const int pre = wave_excl_scan<int>(act ? (int)bm_words((int)(unsigned)rec) : 0, &tot);
@@ -1556,7 +1631,7 @@ __device__ __forceinline__ long long seg_size(const Params& P, int r) {
 // later round into the round's bitmaps.  Wavefronts take groups of 64 of the
 // round's vertices and spread each group's entries evenly over their lanes.
 template <int S>
-__device__ void jp_xpull_items(const Params& P, WaveLds& W, int r, long long gw, long long gstride) {
+__device__ __forceinline__ void jp_xpull_items(const Params& P, WaveLds& W, int r, long long gw, long long gstride) {
   const long long b = seg_begin(P, r), sz = seg_size(P, r);
   const unsigned lane = lane_id();
   for (long long g = gw; g * WAVE < sz; g += gstride) {
@@ -1602,7 +1677,7 @@ __device__ void jp_xpull_items(const Params& P, WaveLds& W, int r, long long gw,
 }
 
 // Level 0 of round r as global lists: its L0 vertices split into F and H.
-__device__ void jp_split_items(const Params& P, JpStage& st, int r, long long gw, long long gstride) {
+__device__ __forceinline__ void jp_split_items(const Params& P, JpStage& st, int r, long long gw, long long gstride) {
   const long long b = seg_begin(P, r), sz = P.l0n[r];
   const unsigned lane = lane_id();
   for (long long g = gw; g * WAVE < sz; g += gstride) {
@@ -1618,7 +1693,7 @@ __device__ void jp_split_items(const Params& P, JpStage& st, int r, long long gw
 // The work items of wide level l: groups of 64 plain vertices (colour and
 // successors a lane each), then the fan-out chunks (each chunk reads its
 // vertex's bitmap; the one that starts the range stores the colour).
-__device__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, unsigned nf, unsigned long long hc,
+__device__ __forceinline__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, unsigned nf, unsigned long long hc,
                                long long gw, long long gstride, const unsigned long long* hlds) {
   const unsigned lane = lane_id();
   const unsigned nh = (unsigned)hc;
@@ -1641,35 +1716,46 @@ __device__ void jp_level_items(const Params& P, JpStage& st, WaveLds& W, int l, 
         s1 = s0 + sp_count(P, v, pr.sp);
         if (!range_ok(P, s0, s1)) s1 = s0;
       }
-      // the first successors are fetched together with the bitmap words
-      int u[JP_UNROLL];
-      bool ok[JP_UNROLL];
+      // The group's successors (at most JP_SMALL per vertex) spread over
+      // the lanes: fetched, with their JP records, while GetColor reads
+      // the bitmap words, then pushed all at once.
+      int stot;
+      const int spre = wave_excl_scan<int>((int)(s1 - s0), &stot);
+      if (stot > JP_SMALL * WAVE) {   // plain vertices have at most JP_SMALL: a broken state
+        raise_internal(P);
+        stot = JP_SMALL * WAVE;
+      }
+      W.soff[lane] = spre;
+      W.pb[lane] = s0;
+      if (lane == 0) W.soff[WAVE] = stot;
+      wave_sync();
+      int u[JP_SMALL], own[JP_SMALL];
+      bool ok[JP_SMALL];
+      JpRec rc[JP_SMALL];
 #pragma unroll
-      for (int t = 0; t < JP_UNROLL; ++t) {
-        ok[t] = act && s0 + t < s1;
-        u[t] = ok[t] ? P.dag[s0 + t] : 0;
+      for (int t = 0; t < JP_SMALL; ++t) {
+        const int e = t * WAVE + (int)lane;
+        ok[t] = e < stot;
+        own[t] = 0;
+        u[t] = 0;
+        if (ok[t]) {
+          own[t] = wave_owner_of(W.soff, e);
+          u[t] = P.dag[W.pb[own[t]] + (e - W.soff[own[t]])];
+        }
         ok[t] = ok[t] && vid_ok(P, u[t]);
       }
+#pragma unroll
+      for (int t = 0; t < JP_SMALL; ++t) rc[t] = ok[t] ? rec_pair(P, u[t]) : JpRec{0, 0};
       const int col = wave_colour(P, W, act, rec);
       if (act) sti<SC_AGENT>(&P.color[v], col);
-      for (long long j = s0; ballot(act && j < s1); j += JP_UNROLL) {
-        JpRec rc[JP_UNROLL];
-        if (j != s0) {
+      W.ffree[lane] = col;
+      wave_sync();
+      bool rdy[JP_SMALL];
 #pragma unroll
-          for (int t = 0; t < JP_UNROLL; ++t) {
-            ok[t] = act && j + t < s1;
-            u[t] = ok[t] ? P.dag[j + t] : 0;
-            ok[t] = ok[t] && vid_ok(P, u[t]);
-          }
-        }
+      for (int t = 0; t < JP_SMALL; ++t) rdy[t] = ok[t] && jp_push<SC_AGENT>(P, u[t], rc[t].rec, W.ffree[own[t]]);
 #pragma unroll
-        for (int t = 0; t < JP_UNROLL; ++t) rc[t] = ok[t] ? rec_pair(P, u[t]) : JpRec{0, 0};
-        bool rdy[JP_UNROLL];
-#pragma unroll
-        for (int t = 0; t < JP_UNROLL; ++t) rdy[t] = ok[t] && jp_push<SC_AGENT>(P, u[t], rc[t].rec, col);
-#pragma unroll
-        for (int t = 0; t < JP_UNROLL; ++t) jp_append<SC_AGENT>(P, st, l, rdy[t], u[t], rc[t]);
-      }
+      for (int t = 0; t < JP_SMALL; ++t) jp_append<SC_AGENT>(P, st, l, rdy[t], u[t], rc[t]);
+      wave_sync();   // W is rewritten by the wavefront's next item
     } else {
       const unsigned k = (unsigned)(it - groups);
       const unsigned long long ent = fan_entry<SC_AGENT>(Hl, nh, k, hlds);
@@ -1814,13 +1900,13 @@ __device__ __forceinline__ void narrow_append(const Params& P, NarrowLds& Z, JpS
   }
   if (base + tot > (unsigned)NARROW_MAX) {
 #pragma unroll
-    for (int q = 0; q < NARROW_UNROLL; ++q) jp_append<SC_WG>(P, st, l, over[q], u[q], JpRec{urec[q], usp[q]});
+    for (int q = 0; q < NARROW_UNROLL; ++q) jp_append<SC_AGENT>(P, st, l, over[q], u[q], JpRec{urec[q], usp[q]});
   }
 }
 
 // Block-wide: the LDS entries of list `cur` (level l) to the global lists of
 // level l (the level's sums are set by the caller).
-__device__ void narrow_flush(const Params& P, NarrowLds& Z, JpStage& st, int cur, int l) {
+__device__ __forceinline__ void narrow_flush(const Params& P, NarrowLds& Z, JpStage& st, int cur, int l) {
   const unsigned n = Z.cnt[cur] < (unsigned)NARROW_MAX ? Z.cnt[cur] : (unsigned)NARROW_MAX;
   for (unsigned b = 0; b < n; b += NARROW_BS) {
     const unsigned i = b + threadIdx.x;
@@ -1830,17 +1916,17 @@ __device__ void narrow_flush(const Params& P, NarrowLds& Z, JpStage& st, int cur
     const bool fan = ok && ns > JP_SMALL;
     if (fan) {
       unsigned long long nch = (unsigned long long)((ns + JP_CHUNK - 1) / JP_CHUNK);
-      unsigned long long old = add64<SC_WG>(&st.hctr[l % 3], (nch << 32) | 1ull);
+      unsigned long long old = add64<SC_AGENT>(&st.hctr[l % 3], (nch << 32) | 1ull);
       unsigned pos = (unsigned)old;
-      if (pos < P.hub_cap) st64<SC_WG>(&P.H[l & 1][pos], (old & 0xffffffff00000000ull) | (unsigned)v);
+      if (pos < P.hub_cap) st64<SC_AGENT>(&P.H[l & 1][pos], (old & 0xffffffff00000000ull) | (unsigned)v);
       else atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
     }
     const uint64_t m = ballot(ok && !fan);
     if (m) {
       unsigned g = 0;
-      if (lane_id() == 0) g = add32<SC_WG>(&st.fcnt[l % 3], (unsigned)__popcll(m));
+      if (lane_id() == 0) g = add32<SC_AGENT>(&st.fcnt[l % 3], (unsigned)__popcll(m));
       g = readlane_u(g, 0);
-      if (ok && !fan && slot_ok(P, g + lanes_below(m))) sti<SC_WG>((int*)&P.F[l & 1][g + lanes_below(m)], v);
+      if (ok && !fan && slot_ok(P, g + lanes_below(m))) sti<SC_AGENT>((int*)&P.F[l & 1][g + lanes_below(m)], v);
     }
   }
 }
@@ -1873,10 +1959,10 @@ __device__ __forceinline__ void narrow_put(const Params& P, NarrowLds& Z, int cu
 }
 
 // Block-wide: n vertices from a global list into LDS list `cur` at `at`.
-__device__ void narrow_load(const Params& P, NarrowLds& Z, int cur, const unsigned* src, unsigned n) {
+__device__ __forceinline__ void narrow_load(const Params& P, NarrowLds& Z, int cur, const unsigned* src, unsigned n) {
   for (unsigned i = threadIdx.x; i < n; i += NARROW_BS) narrow_put(P, Z, cur, i, (int)ld32<SC_AGENT>(&src[i]));
 }
-__device__ void narrow_load_fan(const Params& P, NarrowLds& Z, int cur, const unsigned long long* src, unsigned n,
+__device__ __forceinline__ void narrow_load_fan(const Params& P, NarrowLds& Z, int cur, const unsigned long long* src, unsigned n,
                                 unsigned at) {
   for (unsigned i = threadIdx.x; i < n; i += NARROW_BS)
     narrow_put(P, Z, cur, at + i, (int)(unsigned)ld64<SC_AGENT>(&src[i]));
@@ -1929,7 +2015,7 @@ __device__ __forceinline__ unsigned owner(const unsigned* off, unsigned nv, unsi
 // vertex; then push the colours to the same-round successors and append the
 // ready ones to list `nx`.  Returns false, having changed nothing outside
 // LDS, if the level's work exceeds what one block takes.
-__device__ bool narrow_level(const Params& P, NarrowLds& Z, JpStage& st, int cur, int nx, int l) {
+__device__ __forceinline__ bool narrow_level(const Params& P, NarrowLds& Z, JpStage& st, int cur, int nx, int l) {
   const unsigned nv = Z.cnt[cur];
   const unsigned t = threadIdx.x;
   {
@@ -1992,7 +2078,7 @@ __device__ bool narrow_level(const Params& P, NarrowLds& Z, JpStage& st, int cur
       c = f + 1;
     }
     Z.col[t] = c;
-    if (Z.v[cur][t] >= 0) sti<SC_WG>(&P.color[Z.v[cur][t]], c);
+    if (Z.v[cur][t] >= 0) sti<SC_AGENT>(&P.color[Z.v[cur][t]], c);
   }
   __syncthreads();
   // push the colours to the same-round successors
@@ -2018,7 +2104,7 @@ __device__ bool narrow_level(const Params& P, NarrowLds& Z, JpStage& st, int cur
     }
     bool rdy[NARROW_UNROLL];
 #pragma unroll
-    for (int q = 0; q < NARROW_UNROLL; ++q) rdy[q] = su[q] >= 0 && jp_push<SC_WG>(P, su[q], sr[q], Z.col[sk[q]]);
+    for (int q = 0; q < NARROW_UNROLL; ++q) rdy[q] = su[q] >= 0 && jp_push<SC_AGENT>(P, su[q], sr[q], Z.col[sk[q]]);
     narrow_append(P, Z, st, nx, l, rdy, su, sr, ssp);
   }
   order_point();
@@ -2076,7 +2162,7 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_narrow(Params P, int max_steps
         handed = OP_XPULL;
         break;
       }
-      jp_xpull_items<SC_WG>(P, W, r, threadIdx.x / WAVE, NARROW_BS / WAVE);
+      jp_xpull_items<SC_AGENT>(P, W, r, threadIdx.x / WAVE, NARROW_BS / WAVE);
       order_point();
       __syncthreads();
       if (threadIdx.x == 0) S.xpull = 0;
@@ -2184,9 +2270,403 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_narrow(Params P, int max_steps
   }
 }
 
+// ---- JP steps of one launch: a leader block and helper blocks
+//
+// k_jp_steps replaces a launch of the single-block kernel.  Its first block
+// to start leads: it runs the JP state machine and every narrow step itself,
+// exactly as k_jp_narrow does (lists in LDS).  The other blocks that start in
+// time help: they wait for the leader's commands and take their share of
+// steps too wide for one block but far too narrow for a grid launch of their
+// own -- mid-sized levels, later-round colour pulls and first-level splits of
+// mid-sized rounds -- as the grid kernel does, over the blocks that take
+// part; the leader takes its share too and waits until every helper has
+// reported the command done.  Steps wider still go to the grid kernel.
+//
+// Taking part.  Every block registers with one atomic add on a word of the
+// control block, which the grid step launched between two steps launches
+// (or k_jp_start, before the first) clears; the block that finds it empty
+// leads.  The leader closes registration once every block of the launch has
+// started or after a short wait, whichever comes first; blocks that start
+// later leave at once.  No block ever waits for a block that has not
+// registered, so the launch needs no co-residency of all its blocks.
+//
+// Commands are one 64-bit word (sequence << 40 | op << 32 | argument) that
+// the helpers poll; completions are counted in a second word.  The leader
+// ends the launch (and the helpers with it) after a bounded number of narrow
+// steps without a command, so no helper waits long; every wait is bounded
+// and a wait that runs out raises ADG_ERR_INTERNAL.
+
+#ifndef ADG_STEP_BLOCKS
+#define ADG_STEP_BLOCKS 64
+#endif
+#ifndef ADG_MID_LOG
+#define ADG_MID_LOG 20
+#endif
+constexpr int STEP_BLOCKS = ADG_STEP_BLOCKS;    // blocks of a k_jp_steps launch (one per CU)
+constexpr unsigned MID_MAX_V = ADG_MID_LOG ? 1u << 16 : 0;   // vertices of a level the launch's blocks take together
+constexpr unsigned long long MID_MAX_W = ADG_MID_LOG ? 1ull << ADG_MID_LOG : 0;   // its bitmap words
+constexpr unsigned long long MID_MAX_S = ADG_MID_LOG ? 1ull << ADG_MID_LOG : 0;   // its same-round successors
+constexpr long long MID_MAX_XPULL = ADG_MID_LOG ? 1ll << 17 : NARROW_XPULL;   // vertices of a round whose later-round colours they pull in
+constexpr unsigned MID_MAX_SPLIT = ADG_MID_LOG ? 1u << 17 : NARROW_MAX;      // first-level vertices of a round they split
+constexpr int NARROW_RUN = 4096;                // narrow steps without a command before the launch ends
+constexpr unsigned long long REG_CLOSED = 1ull << 32;
+constexpr unsigned long long REG_SEEN = 1ull << 16;
+constexpr unsigned REG_WAIT_TICKS = 2000;       // the leader waits at most 20 us (100 MHz clock) for late blocks
+constexpr unsigned long long POLL_MAX = 1ull << 22;   // polls of a helper's or the leader's wait
+enum { PC_LEVEL = 1, PC_XPULL = 2, PC_SPLIT = 3, PC_EXIT = 4 };
+
+
+// The helpers' share of a command (the leader takes part as participant 0).
+__device__ __forceinline__ void steps_command(const Params& P, JpStage& st, WaveLds& W, int op, int arg, int r, long long gw,
+                              long long gstride, unsigned long long* flds) {
+  Ctrl* c = P.ctrl;
+  if (op == PC_XPULL) {
+    jp_xpull_items<SC_AGENT>(P, W, arg, gw, gstride);
+  } else if (op == PC_SPLIT) {
+    jp_split_items(P, st, arg, gw, gstride);
+    jp_stage_flush<SC_AGENT>(P, st, -1);
+  } else if (op == PC_LEVEL) {
+    const int l = arg;
+    const unsigned nf = ld32<SC_AGENT>(&c->js.fcnt[l % 3]);
+    const unsigned long long hc = ld64<SC_AGENT>(&c->js.hctr[l % 3]);
+    if (level_ok(P, nf, (unsigned)hc)) {
+      const unsigned long long* hl = fan_stage<SC_AGENT>(P.H[l & 1], (unsigned)hc, flds);
+      jp_level_items(P, st, W, l, nf, hc, gw, gstride, hl);
+    }
+    jp_stage_flush<SC_AGENT>(P, st, l);
+  }
+  (void)r;
+}
+
+// The leader's side of one command: publish it, take participant 0's share,
+// wait until every helper has reported its share done.
+__device__ __forceinline__ void steps_lead(const Params& P, JpStage& gst, WaveLds& W, int op, int arg,
+                                           unsigned long long& seq, int nparts, long long gw, long long gstride,
+                                           unsigned long long* flds, unsigned* fcntl, unsigned long long* acc,
+                                           int* stop) {
+  Ctrl* c = P.ctrl;
+  if (threadIdx.x == 0) {
+    order_point();
+    st64<SC_AGENT>(&c->pcmd, ((seq + 1) << 40) | ((unsigned long long)op << 32) | (unsigned)arg);
+    *fcntl = 0;
+    acc[0] = acc[1] = 0;
+  }
+  ++seq;
+  __syncthreads();
+  steps_command(P, gst, W, op, arg, 0, gw, gstride, flds);
+  order_point();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long want = (unsigned long long)(nparts - 1) * seq;
+    unsigned long long k = 0;
+    while (ld64<SC_AGENT>(&c->pjoin) < want && ++k < POLL_MAX) __builtin_amdgcn_s_sleep(1);
+    if (k >= POLL_MAX) {
+      raise_internal(P);
+      *stop = 1;
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(NARROW_BS) void k_jp_steps(Params P, int max_steps) {
+  Ctrl* c = P.ctrl;
+  __shared__ JpState S;
+  __shared__ NarrowLds Z;
+  __shared__ unsigned fbuf[FB_CAP];
+  __shared__ unsigned fcntl;
+  __shared__ unsigned long long flds[FAN_LDS];
+  __shared__ unsigned long long acc[2];
+  __shared__ int have, role, nparts, pidx, cmd_op, cmd_arg, stop;
+  constexpr int NW = NARROW_BS / WAVE;   // wavefronts per block
+  WaveLds& W = Z.wl[threadIdx.x / WAVE];
+  // ---- registration: one atomic per block on a word that the previous
+  // launch of the grid step (or k_jp_start) has cleared
+  if (threadIdx.x == 0) {
+    const unsigned long long old = __hip_atomic_fetch_add(&c->preg, REG_SEEN + 1ull, __ATOMIC_RELAXED, SC_AGENT);
+    role = (old & REG_CLOSED) ? 0 : (old & 0xffff) == 0 ? 1 : 2;   // 0: leave, 1: lead, 2: help
+    pidx = (int)(old & 0xffff);
+    if (role == 1) {
+      // fresh command and completion words, then close registration once
+      // every block has started (or after a short wait)
+      st64<SC_AGENT>(&c->pcmd, 0ull);
+      st64<SC_AGENT>(&c->pjoin, 0ull);
+      order_point();
+      const bool idle = c->js.done || c->error;
+      const unsigned long long t0 = wall_clock64();
+      while (!idle && ((ld64<SC_AGENT>(&c->preg) >> 16) & 0xffff) < gridDim.x &&
+             wall_clock64() - t0 < REG_WAIT_TICKS)
+        __builtin_amdgcn_s_sleep(2);
+      nparts = (int)(__hip_atomic_fetch_or(&c->preg, REG_CLOSED, __ATOMIC_RELAXED, SC_AGENT) & 0xffff);
+    } else if (role == 2) {
+      unsigned long long w = 0;
+      for (unsigned long long k = 0; k < POLL_MAX; ++k) {
+        w = ld64<SC_AGENT>(&c->preg);
+        if (w & REG_CLOSED) break;
+        __builtin_amdgcn_s_sleep(2);
+      }
+      if (!(w & REG_CLOSED)) {
+        raise_internal(P);
+        role = 0;
+      }
+      nparts = (int)(w & 0xffff);
+    }
+  }
+  __syncthreads();
+  if (role == 0) return;
+  JpStage gst{fbuf, &fcntl, c->js.fcnt, c->js.hctr, c->js.psum, c->js.ssum, acc};   // global lists and counters
+  const long long gstride = (long long)nparts * NW;
+  // work items go round-robin over the participants (item k to participant
+  // k mod nparts), so that the heavy items at the front of a level -- the
+  // groups of plain vertices -- spread over all of them
+  const long long gw = (long long)(threadIdx.x / WAVE) * nparts + pidx;
+  unsigned long long seq = 0;
+  if (role == 2) {
+    // ---- helper: take a share of each command until told to leave
+    for (;;) {
+      if (threadIdx.x == 0) {
+        unsigned long long w = 0;
+        bool got = false;
+        for (unsigned long long k = 0; k < POLL_MAX; ++k) {
+          w = ld64<SC_AGENT>(&c->pcmd);
+          if ((w >> 40) == seq + 1) {
+            got = true;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+        if (!got) raise_internal(P);
+        cmd_op = got ? (int)((w >> 32) & 0xff) : PC_EXIT;
+        cmd_arg = (int)(unsigned)w;
+        fcntl = 0;
+        acc[0] = acc[1] = 0;
+      }
+      __syncthreads();
+      const int op = cmd_op, arg = cmd_arg;
+      ++seq;
+      __syncthreads();
+      if (op == PC_EXIT) return;
+      steps_command(P, gst, W, op, arg, 0, gw, gstride, flds);
+      order_point();
+      __syncthreads();
+      if (threadIdx.x == 0) __hip_atomic_fetch_add(&c->pjoin, 1ull, __ATOMIC_RELAXED, SC_AGENT);
+    }
+  }
+  // ---- leader
+  if (threadIdx.x == 0) {
+    S = c->js;
+    have = 0;
+    stop = 0;
+    if (c->error) S.done = 1;   // raised by an earlier step: JP stops
+    // launches alternate (steps, grid): the op posted by the previous steps
+    // launch has been run by the grid launch between them
+    if (!S.done) {
+      const int op = c->grid_op;
+      c->grid_op = OP_NONE;
+      if (op == OP_XPULL) S.xpull = 0;
+      else if (op == OP_SPLIT) S.split = 0;
+      else if (op == OP_LEVEL) jp_next_level(S);
+    }
+  }
+  __syncthreads();
+  JpStage st{nullptr, nullptr, S.fcnt, S.hctr, S.psum, S.ssum, nullptr};   // LDS counters (narrow steps)
+  int cur = 0;
+  int handed = OP_NONE;
+  int checked = 0;          // the round whose sizes have been checked
+  int since_cmd = 0;        // narrow steps since the last command
+  bool in_global = false;   // the LDS level is also in the global lists
+  for (int step = 0; step < max_steps; ++step) {
+    if (S.done || stop) break;
+    const int r = S.round;
+    const int l = S.level;
+    if (r != checked || !level_ok(P, S.fcnt[l % 3], (unsigned)S.hctr[l % 3])) {
+      // a round's sizes are checked once, when it starts
+      const bool ok = level_ok(P, S.fcnt[l % 3], (unsigned)S.hctr[l % 3]) && round_ok(P, r);
+      __syncthreads();
+      if (!ok) {
+        if (threadIdx.x == 0) S.done = 1;   // a broken state: stop (the error is raised)
+        __syncthreads();
+        break;
+      }
+      checked = r;
+    }
+    if (nparts > 1 && since_cmd > NARROW_RUN) {
+      // a long run of narrow steps: end the launch so that no helper waits long
+      if (have && !in_global) narrow_flush(P, Z, st, cur, l);
+      __syncthreads();
+      if (threadIdx.x == 0) have = 0;
+      __syncthreads();
+      break;
+    }
+    if (S.xpull) {
+      const long long sz = seg_size(P, r);
+      if (sz > MID_MAX_XPULL) {
+        handed = OP_XPULL;
+        break;
+      }
+      if (sz > (long long)NARROW_XPULL) {
+        steps_lead(P, gst, W, PC_XPULL, r, seq, nparts, gw, gstride, flds, &fcntl, acc, &stop);
+        since_cmd = 0;
+      } else {
+        jp_xpull_items<SC_AGENT>(P, W, r, threadIdx.x / WAVE, NW);
+        order_point();
+        ++since_cmd;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) S.xpull = 0;
+      __syncthreads();
+      continue;
+    }
+    if (!have) {
+      if (S.split) {
+        // the round's first level, from L0
+        const unsigned n0 = P.l0n[r];
+        if (n0 > MID_MAX_SPLIT) {
+          handed = OP_SPLIT;
+          break;
+        }
+        if (n0 > (unsigned)NARROW_MAX) {
+          // split into the global lists of level 0 by all participants
+          if (threadIdx.x == 0) {
+            st32<SC_AGENT>(&c->js.fcnt[0], 0u);
+            st64<SC_AGENT>(&c->js.hctr[0], 0ull);
+            st64<SC_AGENT>(&c->js.psum[0], 0ull);
+            st64<SC_AGENT>(&c->js.ssum[0], 0ull);
+          }
+          steps_lead(P, gst, W, PC_SPLIT, r, seq, nparts, gw, gstride, flds, &fcntl, acc, &stop);
+          since_cmd = 0;
+          if (threadIdx.x == 0) {
+            S.fcnt[0] = ld32<SC_AGENT>(&c->js.fcnt[0]);
+            S.hctr[0] = ld64<SC_AGENT>(&c->js.hctr[0]);
+            S.psum[0] = ld64<SC_AGENT>(&c->js.psum[0]);
+            S.ssum[0] = ld64<SC_AGENT>(&c->js.ssum[0]);
+            S.split = 0;
+            S.F += n0;
+          }
+          __syncthreads();
+          continue;
+        }
+        narrow_load(P, Z, cur, P.L0 + seg_begin(P, r), n0);
+        in_global = false;
+        if (threadIdx.x == 0) {
+          Z.cnt[cur] = n0;
+          S.split = 0;
+          S.F += n0;
+        }
+      } else {
+        const unsigned nf = S.fcnt[l % 3], nh = (unsigned)S.hctr[l % 3];
+        if (nf + nh == 0) {  // round finished
+          __syncthreads();
+          if (threadIdx.x == 0) jp_begin_round(S, r - 1);
+          __syncthreads();
+          continue;
+        }
+        if (!jp_fits_narrow(nf + nh, S.psum[l % 3], S.ssum[l % 3])) {
+          if (nf + nh > MID_MAX_V || S.psum[l % 3] > MID_MAX_W || S.ssum[l % 3] > MID_MAX_S) {
+            handed = OP_LEVEL;
+            break;
+          }
+          // a mid-sized level in the global lists: all participants
+          if (threadIdx.x == 0) {
+            st32<SC_AGENT>(&c->js.fcnt[l % 3], S.fcnt[l % 3]);
+            st64<SC_AGENT>(&c->js.hctr[l % 3], S.hctr[l % 3]);
+            const int nx = (l + 1) % 3;
+            st32<SC_AGENT>(&c->js.fcnt[nx], 0u);
+            st64<SC_AGENT>(&c->js.hctr[nx], 0ull);
+            st64<SC_AGENT>(&c->js.psum[nx], 0ull);
+            st64<SC_AGENT>(&c->js.ssum[nx], 0ull);
+          }
+          steps_lead(P, gst, W, PC_LEVEL, l, seq, nparts, gw, gstride, flds, &fcntl, acc, &stop);
+          since_cmd = 0;
+          if (threadIdx.x == 0) {
+            const int nx = (l + 1) % 3;
+            S.fcnt[nx] = ld32<SC_AGENT>(&c->js.fcnt[nx]);
+            S.hctr[nx] = ld64<SC_AGENT>(&c->js.hctr[nx]);
+            S.psum[nx] = ld64<SC_AGENT>(&c->js.psum[nx]);
+            S.ssum[nx] = ld64<SC_AGENT>(&c->js.ssum[nx]);
+            jp_next_level(S);
+          }
+          __syncthreads();
+          continue;
+        }
+        narrow_load(P, Z, cur, P.F[l & 1], nf);
+        narrow_load_fan(P, Z, cur, P.H[l & 1], nh, nf);
+        in_global = true;
+        if (threadIdx.x == 0) Z.cnt[cur] = nf + nh;
+      }
+      if (threadIdx.x == 0) have = 1;
+      __syncthreads();
+    }
+    // process level l from LDS list `cur`
+    ++since_cmd;
+    const int nx = cur ^ 1;
+    if (threadIdx.x == 0) Z.cnt[nx] = 0;
+    __syncthreads();
+    if (Z.cnt[cur] == 0) {  // nothing ready: the round is finished
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        jp_begin_round(S, r - 1);
+        have = 0;
+      }
+      __syncthreads();
+      continue;
+    }
+    if (!narrow_level(P, Z, st, cur, nx, l)) {
+      // too much work for one block: the level goes to the global lists
+      // (the next pass of the loop gives it to the participants or the grid)
+      if (!in_global) {
+        narrow_flush(P, Z, st, cur, l);
+        order_point();
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        S.psum[l % 3] = Z.woff[Z.cnt[cur]];
+        S.ssum[l % 3] = Z.soff[Z.cnt[cur]];
+        have = 0;
+      }
+      __syncthreads();
+      continue;
+    }
+    const unsigned nn = Z.cnt[nx];
+    const bool wide = nn > (unsigned)NARROW_MAX;
+    if (wide) {
+      // the next level leaves LDS: its overflow entries are already in the
+      // global lists; add the LDS ones
+      narrow_flush(P, Z, st, nx, l + 1);
+      order_point();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      jp_next_level(S);
+      if (nn == 0) {
+        jp_begin_round(S, r - 1);
+        have = 0;
+      } else if (wide) {
+        have = 0;
+      }
+    }
+    __syncthreads();
+    cur = nx;
+    in_global = false;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (have) {  // step bound reached with a level still in LDS: a broken state
+      atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
+      S.done = 1;
+    }
+    c->js = S;
+    c->grid_op = handed;
+    order_point();
+    if (nparts > 1) st64<SC_AGENT>(&c->pcmd, ((seq + 1) << 40) | ((unsigned long long)PC_EXIT << 32));
+  }
+}
+
 // Grid-wide: the step the single-block kernel handed over.
 __global__ __launch_bounds__(BS) void k_jp_grid(Params P) {
   Ctrl* c = P.ctrl;
+  // launches alternate (steps, grid): every block of the steps launch before
+  // this one has finished, so its registration word can be cleared for the next
+  if (blockIdx.x == 0 && threadIdx.x == 0) st64<SC_AGENT>(&c->preg, 0ull);
   // Every block decides from state no block of this launch changes: blocks
   // may start after others have finished (other streams' kernels hold CUs).
   const int op = c->grid_op;
@@ -2241,6 +2721,9 @@ __global__ void k_jp_start(Params P, int rounds) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   Ctrl* c = P.ctrl;
   c->grid_op = OP_NONE;
+  c->preg = 0;   // the first steps launch registers from zero
+  c->pcmd = 0;
+  c->pjoin = 0;
   JpState& j = c->js;
   j.done = 0;
   j.levels = 0;
@@ -2601,6 +3084,12 @@ struct Layout {
 };
 
 constexpr int UPD_BLOCKS = 2048;
+// color_graph hands graphs up to these sizes to the one-launch engine
+#ifndef ADG_ONE_GRAPH_MAX_NNZ
+#define ADG_ONE_GRAPH_MAX_NNZ (1 << 17)
+#endif
+constexpr int64_t ONE_GRAPH_MAX_NNZ = ADG_ONE_GRAPH_MAX_NNZ;
+constexpr int64_t ONE_GRAPH_MAX_N = 1 << 17;
 
 // Blocks of the UPDATE-sized launches (k_update, k_part1, the pull and DEC
 // kernels): as many as the device keeps resident at once, at most
@@ -2930,7 +3419,7 @@ int run_jp(Params& P, hipStream_t s, int rounds) {
   if (!h) return ADG_ERR_HIP;
   int chunk = 2;
   long long pairs = 0;
-  const long long max_pairs = 4LL * ((long long)P.n + rounds + 4);
+  const long long max_pairs = std::min(4LL * ((long long)P.n + rounds + 4), (1LL << 30));
   // steps of one single-block launch: every step processes a level, loads
   // one or starts a round
   const int max_steps = (int)std::min<long long>(0x7fffffff, 3LL * ((long long)P.n + rounds) + 16);
@@ -2947,7 +3436,11 @@ int run_jp(Params& P, hipStream_t s, int rounds) {
       for (int k = 0; k < chunk; ++k) {
         {
           TIMED(KC_JP_NARROW, s);
+#if ADG_JP_STEPS
+          hipLaunchKernelGGL(k_jp_steps, dim3(STEP_BLOCKS), dim3(NARROW_BS), 0, s, P, max_steps);
+#else
           hipLaunchKernelGGL(k_jp_narrow, dim3(1), dim3(NARROW_BS), 0, s, P, max_steps);
+#endif
         }
         {
           TIMED(KC_JP, s);
@@ -3174,11 +3667,27 @@ int color_graph_ex(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_
   int rc = check_graph(g);
   if (rc) return rc;
   if (eps_num < 0 || eps_den < 1 || (g->n > 0 && !color_out)) return ADG_ERR_ARG;
-  if (variant & ~(uint32_t)(ADG_VARIANT_SORTED | ADG_VARIANT_MEDIAN | ADG_VARIANT_DEC_ITR | ADG_VARIANT_PULL))
+  if (variant & ~(uint32_t)(ADG_VARIANT_SORTED | ADG_VARIANT_MEDIAN | ADG_VARIANT_DEC_ITR | ADG_VARIANT_PULL |
+                            ADG_VARIANT_MULTI_LAUNCH))
     return ADG_ERR_ARG;
+  const bool multi = (variant & ADG_VARIANT_MULTI_LAUNCH) != 0;
+  variant &= ~(uint32_t)ADG_VARIANT_MULTI_LAUNCH;
   if ((variant & ADG_VARIANT_DEC_ITR) && (variant & ADG_VARIANT_SORTED)) return ADG_ERR_ARG;
   if ((rc = check_ws(workspace, ws_bytes, g->n, g->nnz))) return rc;
   hipStream_t s = (hipStream_t)stream;
+  if (variant == 0 && !multi && g->n > 0 && g->n <= ONE_GRAPH_MAX_N && g->nnz <= ONE_GRAPH_MAX_NNZ) {
+    // a small graph: one launch of the one-workgroup engine instead of
+    // several launches per round; the same result, and its counters in
+    // this workspace's control block
+    const Layout L = make_layout(g->n, g->nnz);
+    Ctrl* c = (Ctrl*)((char*)workspace + L.ctrl);
+    const StatsSink sink{&c->num_rounds, &c->num_colors, &c->sum_active, &c->cut_edges, &c->js.F, &c->js.levels,
+                         &c->error, {&c->dec[0].iters, &c->dec[1].iters}};
+    char* rest = (char*)workspace + L.bcount;
+    if (one_graph_bytes(g->n, g->nnz) <= ws_bytes - L.bcount)
+      return color_one_graph(g->n, g->nnz, g->row_ptr, g->col_idx, eps_num, eps_den, seed, color_out, round_out,
+                             num_colors_out, num_rounds_out, rest, ws_bytes - L.bcount, s, sink);
+  }
   Params P = make_params(g, workspace, (uint64_t)eps_num, (uint64_t)eps_den, seed, 1, round_out, color_out, variant);
   int L = 0;
   if ((rc = run_adg(P, s, true, &L))) return rc;

@@ -95,7 +95,7 @@ def test_variant_entry_points_reject_bad_arguments_without_gpu():
     csr = pkg._Csr(5, 8, fake, fake)
     ws = L.adg_workspace_bytes(5, 8)
     # unknown variant bits
-    assert L.color_graph_ex(ctypes.byref(csr), 1, 10, 0, 16, fake, None, None, None, fake, ws, None) == -1
+    assert L.color_graph_ex(ctypes.byref(csr), 1, 10, 0, 32, fake, None, None, None, fake, ws, None) == -1
     assert L.adg_order_ex(ctypes.byref(csr), 1, 10, 0, 16, fake, None, None, fake, ws, None) == -1
     # DEC-ADG-ITR colours only, and not with ADG-O's order
     assert L.color_graph_ex(ctypes.byref(csr), 1, 10, 0, 5, fake, None, None, None, fake, ws, None) == -1

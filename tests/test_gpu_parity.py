@@ -20,27 +20,36 @@ def dev():
     return pkg
 
 
-def _gpu_color(pkg, rp, col, p, q, seed):
+def _gpu_color(pkg, rp, col, p, q, seed, variant=0):
     import torch
     g = pkg.Graph(rp, col)
     ws = torch.empty(pkg.workspace_bytes(g.n, g.nnz), dtype=torch.uint8, device="cuda")
-    color, nc, rnd, nr = pkg.color_graph(g, p, q, seed, workspace=ws)
+    if variant:
+        color, nc, rnd, nr = pkg.color_graph_ex(g, p, q, seed, variant, workspace=ws)
+    else:
+        color, nc, rnd, nr = pkg.color_graph(g, p, q, seed, workspace=ws)
     torch.cuda.synchronize()
     st = pkg.get_stats(ws)
     return color.cpu().numpy(), int(nc.item()), rnd.cpu().numpy(), int(nr.item()), st
 
 
 def _compare(pkg, rp, col, p, q, seed, label=""):
+    """Both routes of color_graph against the oracle: the default one (a
+    graph of at most 2^17 entries goes to the one-launch engine) and the
+    per-round kernels (MULTI_LAUNCH)."""
     print("case", label, "n", rp.size - 1, "nnz", col.size, "eps", p, q, "seed", seed, flush=True)
     color, k, rho, L, st = oracle.color_graph(rp, col, p, q, seed)
-    gc, gk, gr, gL, gst = _gpu_color(pkg, rp, col, p, q, seed)
-    assert gL == L, (label, gL, L)
-    assert np.array_equal(gr, rho), label
-    assert gk == k, (label, gk, k)
-    assert np.array_equal(gc, color), label
-    assert gst["sum_active"] == st["sum_active"]
-    assert gst["cut_edges"] == st["cut_edges"]
-    assert gst["error"] == 0
+    for variant in (0, pkg.MULTI_LAUNCH):
+        gc, gk, gr, gL, gst = _gpu_color(pkg, rp, col, p, q, seed, variant)
+        lab = (label, "route", variant)
+        assert gL == L, (lab, gL, L)
+        assert np.array_equal(gr, rho), lab
+        assert gk == k, (lab, gk, k)
+        assert np.array_equal(gc, color), lab
+        assert gst["sum_active"] == st["sum_active"], lab
+        assert gst["cut_edges"] == st["cut_edges"], lab
+        assert gst["num_rounds"] == L and gst["num_colors"] == k, lab
+        assert gst["error"] == 0, lab
     return gst
 
 
