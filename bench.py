@@ -55,9 +55,9 @@ WORKLOADS = {
 # kernel sources each timed kernel class is built from (for matching
 # committed counter records to the current code)
 KERNEL_SOURCES = {
-    "k_jp_narrow+k_jp_grid": ["adg_single.hip", "adg_device.h"],
-    "k_update": ["adg_single.hip", "adg_device.h"],
-    "k_batched": ["adg_batched.hip", "adg_device.h"],
+    "k_jp_steps+k_jp_grid": ["adg_single.hip", "adg_device.h", "adg_intmath.h"],
+    "k_update": ["adg_single.hip", "adg_device.h", "adg_intmath.h"],
+    "k_batched": ["adg_batched.hip", "adg_device.h", "adg_intmath.h"],
 }
 
 
@@ -365,7 +365,7 @@ def run_single(args, w):
                                           upd_launches), model="UPDATE's own traffic (see algorithmic_bytes)")}
     # the dominant kernel class: the larger share of the step
     if jp_ms >= adg_ms:
-        kname = "k_dec_pull+k_dec_pick+k_dec_resolve" if variant & 4 else "k_jp_narrow+k_jp_grid"
+        kname = "k_dec_pull+k_dec_pick+k_dec_resolve" if variant & 4 else "k_jp_steps+k_jp_grid"
         dom_bytes, dom_ms, dom_launches = jp_b, jp_ms, jp_launches
     else:
         kname, dom_bytes, dom_ms, dom_launches = "k_update", algorithmic_bytes("update", n, nnz, st), upd_ms, \
