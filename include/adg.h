@@ -162,6 +162,20 @@ int color_graph(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_t s
  *       color_graph_batched (one workgroup colours it, in one launch and
  *       without waiting on the stream); this bit keeps such a graph on the
  *       per-round kernels.  The output is the same either way.
+ *   ADG_VARIANT_RELAX_ALL, ADG_VARIANT_LEVELS_ONLY  (color_graph_ex only,
+ *       not with ADG_VARIANT_DEC_ITR, not together; each keeps every graph
+ *       on the per-round kernels) how JP schedules each round.  JP colours a
+ *       round level by level (Algorithm 3's waves inside the round); by
+ *       default, once a round of at least 2048 vertices has run 8 levels
+ *       that colour 3 or more vertices each on average, with a quarter of
+ *       the round still uncoloured, its other vertices are relaxed instead:
+ *       every uncoloured vertex repeatedly takes the smallest colour that
+ *       neither its later-round predecessors nor its current same-round
+ *       predecessors have, until no colour changes.  The same-round DAG is
+ *       acyclic, so these equations have one solution, which is JP's
+ *       colouring: the output is the same under every schedule.
+ *       RELAX_ALL relaxes every round from its start; LEVELS_ONLY never
+ *       relaxes.
  * SORTED and MEDIAN may be combined.  variant = 0 is Algorithm 1 (adg_order,
  * color_graph).  Other bits or combinations: ADG_ERR_ARG. */
 enum {
@@ -169,7 +183,9 @@ enum {
   ADG_VARIANT_MEDIAN = 2,
   ADG_VARIANT_DEC_ITR = 4,
   ADG_VARIANT_PULL = 8,
-  ADG_VARIANT_MULTI_LAUNCH = 16
+  ADG_VARIANT_MULTI_LAUNCH = 16,
+  ADG_VARIANT_RELAX_ALL = 32,
+  ADG_VARIANT_LEVELS_ONLY = 64
 };
 
 /* Workspace bytes for adg_order_ex with a pos output (adg_workspace_bytes

@@ -56,6 +56,8 @@ MEDIAN = 2
 DEC_ITR = 4   # colouring by DEC-ADG-ITR instead of JP (color_graph_ex only)
 PULL = 8      # pull (CREW) UPDATE: same output, no atomics on D
 MULTI_LAUNCH = 16   # keep a small graph on the per-round kernels (color_graph_ex only)
+RELAX_ALL = 32      # JP relaxes every round from its start (color_graph_ex only; same output)
+LEVELS_ONLY = 64    # JP colours every round level by level (color_graph_ex only; same output)
 
 _lib = None
 

@@ -76,10 +76,22 @@ namespace adg {
 constexpr int BS = 256;                 // threads per block
 constexpr int WPB = BS / WAVE;          // wavefronts per block
 constexpr int SEL_BLOCKS = 2048;        // fixed grid of the selection kernels
+#ifndef ADG_JP_STEPS
+#define ADG_JP_STEPS 1   // JP's narrow and mid-sized steps in one launch of a leader and helper blocks
+#endif
+#ifndef ADG_JP_RELAX
+#define ADG_JP_RELAX ADG_JP_STEPS   // deep rounds finished by relaxation (needs the steps launch)
+#endif
+#if ADG_JP_RELAX && !ADG_JP_STEPS
+#error "relaxation runs from the steps launch"
+#endif
+constexpr bool JP_RELAX = ADG_JP_RELAX;
 #ifndef ADG_UPDATE_ONE_PASS
 #define ADG_UPDATE_ONE_PASS 1
 #endif
-constexpr bool UPDATE_ONE_PASS = ADG_UPDATE_ONE_PASS;   // JP's row partition in one pass (no DEC-ADG-ITR)
+// JP's row partition in one pass: no DEC-ADG-ITR, and no relaxation, which
+// reads the same-round predecessors that this partition leaves out
+constexpr bool UPDATE_ONE_PASS = ADG_UPDATE_ONE_PASS && !ADG_JP_RELAX;
 #ifndef ADG_SMALL_DEG
 #define ADG_SMALL_DEG 32
 #endif
@@ -121,11 +133,29 @@ constexpr int NARROW_UNROLL = ADG_NARROW_UNROLL;  // edges per thread in flight 
 constexpr int MSEL_BINS = 2048;              // radix selection: 11-bit digits
 constexpr int MSEL_PASSES = 6;               // 11 x 5 + 9 bits cover a 64-bit key
 constexpr int MSEL_BLOCKS = 512;
-#ifndef ADG_JP_STEPS
-#define ADG_JP_STEPS 1   // JP's narrow and mid-sized steps in one launch of a leader and helper blocks
+#ifndef ADG_RELAX_AFTER
+#define ADG_RELAX_AFTER 8
 #endif
+constexpr int RELAX_AFTER = ADG_RELAX_AFTER;   // levels of a round before its other vertices are relaxed
+#ifndef ADG_RELAX_MIN_V
+#define ADG_RELAX_MIN_V 2048
+#endif
+constexpr unsigned RELAX_MIN_V = ADG_RELAX_MIN_V;   // smaller rounds keep their levels to the end
+#ifndef ADG_RELAX_DENSE
+#define ADG_RELAX_DENSE 3
+#endif
+constexpr unsigned RELAX_DENSE = ADG_RELAX_DENSE;   // vertices per level below which a round keeps its levels
+#ifndef ADG_RELAX_MID
+#define ADG_RELAX_MID 2048
+#endif
+constexpr unsigned RELAX_MID = ADG_RELAX_MID;   // relaxation lists the steps launch takes (larger: the grid)
+constexpr int RELAX_UNROLL = 4;                 // predecessor colours per lane in flight
+constexpr int RELAX_LK = 32;                    // vertices a lane solves alone: same-round predecessors and successors
+constexpr int RELAX_LW = 8;                     // and bitmap words
 
-enum { OP_NONE = 0, OP_SPLIT = 1, OP_LEVEL = 2, OP_XPULL = 3 };
+enum { OP_NONE = 0, OP_SPLIT = 1, OP_LEVEL = 2, OP_XPULL = 3, OP_RELAX = 4 };
+// which rounds JP relaxes: by relax_pays (default), all from their start, none
+enum { RELAX_MODE_RULE = 0, RELAX_MODE_ALL = 1, RELAX_MODE_NONE = 2 };
 
 // JP progress.  Lives in the control block between kernels; the single-block
 // kernel keeps its own copy in LDS while it runs.
@@ -136,8 +166,12 @@ struct JpState {
   int xpull;                   // the round's later-round colours are still to be pulled in
   int top;                     // L (the first round coloured)
   int done;                    // JP finished
-  int levels;                  // levels processed (all rounds)
+  int levels;                  // levels and relaxation steps processed (all rounds)
+  int relax;                   // the rest of the round is being relaxed
+  int rit;                     // its relaxation step (0: list the uncoloured vertices)
+  unsigned rstamp;             // mark stamp of the latest relaxation step (all rounds)
   unsigned long long F;        // vertices that formed a round's first level
+  unsigned long long rv;       // vertices the current round's levels have coloured
   unsigned int fcnt[3];        // plain vertices per level (by level mod 3)
   unsigned int pad3;
   unsigned long long hctr[3];  // fan-out vertices (low 32 bits) and chunks (high 32 bits)
@@ -197,6 +231,8 @@ struct Ctrl {
   unsigned long long preg;
   unsigned long long pcmd;
   unsigned long long pjoin;
+  // relaxation step the steps launch's participants run: round, step, list size, stamp
+  unsigned rx[4];
 };
 
 struct Params {
@@ -213,6 +249,7 @@ struct Params {
   int median;                  // ADG-M: R = the lower half of U by (D, rho_R)
   int dec;                     // DEC-ADG-ITR colours the partitions (bitmaps for all same-round neighbours)
   int pull;                    // UPDATE pulls: survivors lower their own D (k_update_pull)
+  int relax_mode;              // RELAX_MODE_*: which rounds JP relaxes
   unsigned* tent;              // DEC-ADG-ITR: colour each vertex tried in its latest iteration
   unsigned* mhist;             // [MSEL_BINS] radix selection histogram
   Ctrl* ctrl;
@@ -228,7 +265,7 @@ struct Params {
   unsigned long long* xpart;   // [upd_blocks] decrement counts
   int upd_blocks;
   int* dag;                    // [nnz] rows as [pred | same-round succ | earlier succ]
-  int* npred;                  // |pred(v)|
+  int* xpred;                  // predecessors of v from later rounds (|pred(v)| less the same-round ones)
   int* nsr;                    // same-round successors of v (JP levels walk these)
   int* cnt;                    // same-round predecessors of v not yet coloured
   unsigned long long* rec;     // per vertex two words: (colour bitmap offset << 32) | |pred(v)|, and
@@ -246,6 +283,7 @@ struct Params {
   unsigned long long* H[2];    // level lists, fan-out vertices: (first chunk << 32) | vertex
   unsigned hub_cap;
   int* color;
+  unsigned* rmark;             // relaxation: stamp of the step a vertex was last listed for
 };
 
 // Status byte of a vertex removed in round l.  Codes repeat every 255 rounds,
@@ -816,7 +854,7 @@ __device__ __forceinline__ void jp_row(const Params& P, BmPool* pl, bool has, in
   } else {
     for (unsigned k = 0; k < w; ++k) P.B[off + k] = 0;
   }
-  P.npred[v] = (int)np;
+  P.xpred[v] = (int)(np - nps);
   P.nsr[v] = (int)ns;
   P.cnt[v] = (int)nps;
   P.rec[2 * (size_t)v] = (off << 32) | (unsigned)(P.dec ? np + ns : np);
@@ -1641,7 +1679,7 @@ __device__ __forceinline__ void jp_xpull_items(const Params& P, WaveLds& W, int 
     if (ok) {
       const int v = P.ORD[b + i];
       if (vid_ok(P, v)) {
-        x = P.npred[v] - P.cnt[v];   // predecessors from later rounds (cnt is untouched until the round starts)
+        x = P.xpred[v];   // predecessors from later rounds
         W.rec[lane] = rec_of(P, v);
         W.pb[lane] = P.rp[v];
         if (x < 0 || x > P.rp[v + 1] - W.pb[lane]) {
@@ -1808,6 +1846,220 @@ __device__ __forceinline__ void jp_level_items(const Params& P, JpStage& st, Wav
   }
 }
 
+// ---- relaxation of a deep round
+//
+// Colouring a round level by level costs one step per level, and the rounds
+// at the top of a power-law graph hold long same-round chains (thousands of
+// levels).  Their JP colours are also the unique solution of the system
+//   c(v) = smallest colour neither in v's bitmap nor taken by a same-round
+//          predecessor of v,
+// because the same-round DAG is acyclic: going down the DAG, each equation
+// fixes one colour from colours already fixed.  Repeating the equations from
+// any start reaches that solution, and stops changing, in at most (longest
+// chain + 1) sweeps; on these rounds it stops far sooner than the chain is
+// long.  So once a round has run RELAX_AFTER levels, its uncoloured vertices
+// are relaxed instead: step 0 lists them (a colour of 0: JP start clears the
+// colours); step t >= 1 recomputes every vertex of its list and, where the
+// colour changed, lists the same-round successors for step t + 1, each once
+// (the first to raise the successor's mark to step t + 1's stamp lists it).
+// The round ends with an empty list.  The vertices JP already coloured keep
+// their colours: all their predecessors were coloured before them, so their
+// equations hold already, and their colours are in the bitmaps of their
+// successors, as the equations want.  Colours are read while other
+// wavefronts may rewrite them, but every change lists its successors for the
+// next step, so whatever a vertex last read was final once the lists run dry.
+
+// Step 0: the round's uncoloured vertices (lane per vertex) into list 1.
+__device__ __forceinline__ void jp_relax_list(const Params& P, JpStage& st, int r, long long gw, long long gstride) {
+  const long long b = seg_begin(P, r), sz = seg_size(P, r);
+  const unsigned lane = lane_id();
+  for (long long g = gw; g * WAVE < sz; g += gstride) {
+    const long long i = g * WAVE + lane;
+    int v = i < sz ? P.ORD[b + i] : -1;
+    const bool ok = v >= 0 && vid_ok(P, v);
+    const bool open = ok && done_colour(P, v) == 0;
+    jp_append<SC_AGENT>(P, st, 0, open, open ? v : 0, JpRec{0, 0});
+  }
+}
+
+// The colour equation of one vertex v (bitmap rec, np predecessors, the
+// same-round ones at dag[p0, s0)), solved by the whole wavefront: windows of
+// 2048 colours, each filled from v's bitmap words and then from the current
+// colours of its same-round predecessors, until one has a clear bit.
+__device__ __forceinline__ int relax_wave(const Params& P, WaveLds& W, unsigned long long rec, int np, long long p0,
+                                          long long s0) {
+  const unsigned lane = lane_id();
+  unsigned* bits = (unsigned*)W.ffree;
+  const unsigned nw = bm_words(np);
+  const unsigned long long bo = rec >> 32;
+  int col = 0;
+  for (unsigned w0 = 0; w0 < nw && !col; w0 += WAVE) {
+    bits[lane] = w0 + lane < nw ? bm_load(P, bo + w0 + lane) : ~0u;
+    wave_sync();
+    const int lo = (int)(w0 * 32);
+    for (long long j0 = p0; j0 < s0; j0 += WAVE * RELAX_UNROLL) {
+      int u[RELAX_UNROLL];
+#pragma unroll
+      for (int k = 0; k < RELAX_UNROLL; ++k) {
+        const long long j = j0 + k * WAVE + lane;
+        u[k] = j < s0 ? P.dag[j] : -1;
+      }
+#pragma unroll
+      for (int k = 0; k < RELAX_UNROLL; ++k) u[k] = u[k] >= 0 && vid_ok(P, u[k]) ? done_colour(P, u[k]) : 0;
+#pragma unroll
+      for (int k = 0; k < RELAX_UNROLL; ++k) {
+        const int bit = u[k] - 1 - lo;   // colours outside 1 .. np+2 cannot be v's
+        if (u[k] >= 1 && u[k] <= np + 2 && bit >= 0 && bit < WAVE * 32) atomicOr(&bits[bit >> 5], 1u << (bit & 31));
+      }
+    }
+    wave_sync();
+    const unsigned wd = bits[lane];
+    const int f = wave_min(~wd ? (int)(w0 + lane) * 32 + __ffs((int)~wd) - 1 : 0x7fffffff);
+    if (f != 0x7fffffff) col = f + 1;
+    wave_sync();   // the window is rewritten by the next pass
+  }
+  if (!col) {   // unreachable: at most np of the np+2 colours are taken
+    if (lane == 0) raise_internal(P);
+    col = np + 1;
+  }
+  return col;
+}
+
+// The same-round successors [s0, s1) of a vertex whose colour changed, by
+// the whole wavefront, RELAX_UNROLL widths at a time: each is listed for
+// the next step unless a mark at its stamp says it already is (most are:
+// listed by another changed predecessor).  A plain read of the mark, which
+// can only lag behind, spares most of the atomics.
+__device__ __forceinline__ void relax_push_wave(const Params& P, JpStage& ast, int t, unsigned stamp, long long s0,
+                                                long long s1) {
+  const unsigned lane = lane_id();
+  for (long long j0 = s0; j0 < s1; j0 += WAVE * RELAX_UNROLL) {
+    int w[RELAX_UNROLL];
+    bool mk[RELAX_UNROLL];
+#pragma unroll
+    for (int k = 0; k < RELAX_UNROLL; ++k) {
+      const long long j = j0 + k * WAVE + lane;
+      w[k] = j < s1 ? P.dag[j] : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < RELAX_UNROLL; ++k) mk[k] = w[k] >= 0 && vid_ok(P, w[k]) && P.rmark[w[k]] < stamp;
+#pragma unroll
+    for (int k = 0; k < RELAX_UNROLL; ++k)
+      mk[k] = mk[k] && __hip_atomic_fetch_max(&P.rmark[w[k]], stamp, __ATOMIC_RELAXED, SC_AGENT) < stamp;
+#pragma unroll
+    for (int k = 0; k < RELAX_UNROLL; ++k) jp_append<SC_AGENT>(P, ast, t, mk[k], mk[k] ? w[k] : 0, JpRec{0, 0});
+  }
+}
+
+// Step t >= 1 over its list of nl vertices.  A list no longer than
+// 2 gstride goes a wavefront per vertex (relax_wave, relax_push_wave).
+// Longer lists go G entries per wavefront, G spreading the list evenly over
+// the wavefronts (up to 64), with lb the wavefront's LDS area of
+// 64 x RELAX_LW words: a light vertex (at most RELAX_LK same-round
+// predecessors and successors, at most RELAX_LW bitmap words) is solved and
+// pushed by its lane alone, in its own words of lb (word w of lane k at
+// lb[64 w + k]); the others by the whole wavefront, one after the other.
+__device__ __forceinline__ void jp_relax_items(const Params& P, JpStage& st, WaveLds& W, unsigned* lb, int t, unsigned nl,
+                                               unsigned stamp, long long gw, long long gstride) {
+  const unsigned lane = lane_id();
+  const unsigned* Lin = P.F[t & 1];
+  JpStage ast = st;
+  ast.acc = nullptr;   // a relaxation list keeps no work sums
+  if (!lb || (long long)nl <= 2 * gstride) {
+    for (long long i = gw; i < (long long)nl; i += gstride) {
+      const int v = __builtin_amdgcn_readfirstlane((int)ld32<SC_AGENT>(&Lin[i]));
+      if (!vid_ok(P, v)) continue;
+      const JpRec pr = rec_pair(P, v);
+      const int old = __builtin_amdgcn_readfirstlane(done_colour(P, v));
+      const int np = (int)(unsigned)pr.rec;
+      const long long s0 = sp_first(pr.sp);
+      const long long s1 = s0 + sp_count(P, v, pr.sp);
+      const long long p0 = s0 - (np - P.xpred[v]);   // same-round predecessors: [p0, s0)
+      if (!range_ok(P, p0, s0) || !range_ok(P, s0, s1)) continue;
+      const int col = relax_wave(P, W, pr.rec, np, p0, s0);
+      if (col == old) continue;
+      if (lane == 0) sti<SC_AGENT>(&P.color[v], col);
+      relax_push_wave(P, ast, t, stamp, s0, s1);
+    }
+    return;
+  }
+  long long G = ((long long)nl + gstride - 1) / gstride;
+  if (G > WAVE) G = WAVE;
+  for (long long g = gw; g * G < (long long)nl; g += gstride) {
+    const long long i = g * G + lane;
+    const int v = lane < G && i < (long long)nl ? (int)ld32<SC_AGENT>(&Lin[i]) : -1;
+    bool act = v >= 0 && vid_ok(P, v);
+    JpRec pr{0, 0};
+    long long p0 = 0, s0 = 0, s1 = 0;
+    int np = 0, old = 0;
+    if (act) {
+      pr = rec_pair(P, v);
+      old = done_colour(P, v);
+      np = (int)(unsigned)pr.rec;
+      s0 = sp_first(pr.sp);
+      s1 = s0 + sp_count(P, v, pr.sp);
+      p0 = s0 - (np - P.xpred[v]);
+      act = range_ok(P, p0, s0) && range_ok(P, s0, s1);
+    }
+    const int nw = act ? (int)bm_words(np) : 0;
+    const bool lite = act && s0 - p0 <= RELAX_LK && s1 - s0 <= RELAX_LK && nw <= RELAX_LW;
+    int col = 0;
+    // light vertices: a lane each
+    const int kp = lite ? (int)(s0 - p0) : 0;
+    const int kmax = wave_max(kp);
+#pragma unroll
+    for (int w = 0; w < RELAX_LW; ++w)
+      lb[w * WAVE + lane] = lite && w < nw ? bm_load(P, (pr.rec >> 32) + (unsigned)w) : ~0u;
+    for (int j0 = 0; j0 < kmax; j0 += RELAX_UNROLL) {
+      int u[RELAX_UNROLL];
+#pragma unroll
+      for (int k = 0; k < RELAX_UNROLL; ++k) u[k] = j0 + k < kp ? P.dag[p0 + j0 + k] : -1;
+#pragma unroll
+      for (int k = 0; k < RELAX_UNROLL; ++k) u[k] = u[k] >= 0 && vid_ok(P, u[k]) ? done_colour(P, u[k]) : 0;
+#pragma unroll
+      for (int k = 0; k < RELAX_UNROLL; ++k)
+        if (u[k] >= 1 && u[k] <= np + 2) lb[((u[k] - 1) >> 5) * WAVE + lane] |= 1u << ((u[k] - 1) & 31);
+    }
+    if (lite) {
+#pragma unroll
+      for (int w = RELAX_LW - 1; w >= 0; --w) {
+        const unsigned x = lb[w * WAVE + lane];
+        if (w < nw && ~x) col = w * 32 + __ffs((int)~x);
+      }
+      if (!col) {   // unreachable: at most np of the np+2 colours are taken
+        raise_internal(P);
+        col = np + 1;
+      }
+    }
+    const bool lchanged = lite && col != old;
+    if (lchanged) sti<SC_AGENT>(&P.color[v], col);
+    const int ks = lchanged ? (int)(s1 - s0) : 0;
+    const int smax = wave_max(ks);
+    for (int j0 = 0; j0 < smax; j0 += RELAX_UNROLL) {
+      int w[RELAX_UNROLL];
+      bool mk[RELAX_UNROLL];
+#pragma unroll
+      for (int k = 0; k < RELAX_UNROLL; ++k) w[k] = j0 + k < ks ? P.dag[s0 + j0 + k] : -1;
+#pragma unroll
+      for (int k = 0; k < RELAX_UNROLL; ++k) mk[k] = w[k] >= 0 && vid_ok(P, w[k]) && P.rmark[w[k]] < stamp;
+#pragma unroll
+      for (int k = 0; k < RELAX_UNROLL; ++k)
+        mk[k] = mk[k] && __hip_atomic_fetch_max(&P.rmark[w[k]], stamp, __ATOMIC_RELAXED, SC_AGENT) < stamp;
+#pragma unroll
+      for (int k = 0; k < RELAX_UNROLL; ++k) jp_append<SC_AGENT>(P, ast, t, mk[k], mk[k] ? w[k] : 0, JpRec{0, 0});
+    }
+    // the others: the whole wavefront, one after the other
+    for (uint64_t m = ballot(act && !lite); m; m &= m - 1) {
+      const int src = __ffsll((long long)m) - 1;
+      const long long hs0 = readlane_i64(s0, src), hs1 = readlane_i64(s1, src);
+      const int c = relax_wave(P, W, readlane_u64(pr.rec, src), readlane_i(np, src), readlane_i64(p0, src), hs0);
+      if (c == readlane_i(old, src)) continue;
+      if (lane == 0) sti<SC_AGENT>(&P.color[readlane_i(v, src)], c);
+      relax_push_wave(P, ast, t, stamp, hs0, hs1);
+    }
+  }
+}
+
 // ---- JP state machine (plain accesses: the state is in LDS while the
 // single-block kernel runs, in the control block between kernels)
 
@@ -1825,6 +2077,9 @@ __device__ __forceinline__ void jp_begin_round(JpState& j, int r) {
   j.level = 0;
   j.split = 1;
   j.xpull = r < j.top ? 1 : 0;
+  j.relax = 0;
+  j.rit = 0;
+  j.rv = 0;
   for (int k = 0; k < 3; ++k) jp_clear_level(j, k);
   if (r <= 0) j.done = 1;
 }
@@ -1834,6 +2089,18 @@ __device__ __forceinline__ void jp_next_level(JpState& j) {
   j.levels += 1;
   j.level += 1;
   jp_clear_level(j, (j.level + 1) % 3);
+}
+
+// Whether the rest of round r (its levels so far in j) is worth relaxing:
+// a round of at least RELAX_MIN_V vertices whose levels colour RELAX_DENSE
+// or more vertices each on average (a round whose levels take a vertex or
+// two is a dense core: levels cost little there, while relaxation would
+// sweep its edges hundreds of times), with at least a quarter of it still
+// uncoloured (listing the uncoloured vertices reads the whole round).
+__device__ __forceinline__ bool relax_pays(const Params& P, const JpState& j, int r) {
+  const unsigned long long rs = (unsigned long long)seg_size(P, r);
+  return rs >= RELAX_MIN_V && j.rv >= (unsigned long long)RELAX_DENSE * (unsigned long long)j.level &&
+         rs - (j.rv < rs ? j.rv : rs) >= rs / 4;
 }
 
 // Work of a level, as the single block sees it: bitmap words + successors.
@@ -2313,12 +2580,12 @@ constexpr unsigned long long REG_CLOSED = 1ull << 32;
 constexpr unsigned long long REG_SEEN = 1ull << 16;
 constexpr unsigned REG_WAIT_TICKS = 2000;       // the leader waits at most 20 us (100 MHz clock) for late blocks
 constexpr unsigned long long POLL_MAX = 1ull << 22;   // polls of a helper's or the leader's wait
-enum { PC_LEVEL = 1, PC_XPULL = 2, PC_SPLIT = 3, PC_EXIT = 4 };
+enum { PC_LEVEL = 1, PC_XPULL = 2, PC_SPLIT = 3, PC_EXIT = 4, PC_RELAX = 5 };
 
 
 // The helpers' share of a command (the leader takes part as participant 0).
-__device__ __forceinline__ void steps_command(const Params& P, JpStage& st, WaveLds& W, int op, int arg, int r, long long gw,
-                              long long gstride, unsigned long long* flds) {
+__device__ __forceinline__ void steps_command(const Params& P, JpStage& st, WaveLds& W, int op, int arg, long long gw,
+                                              long long gstride, unsigned long long* flds) {
   Ctrl* c = P.ctrl;
   if (op == PC_XPULL) {
     jp_xpull_items<SC_AGENT>(P, W, arg, gw, gstride);
@@ -2334,8 +2601,13 @@ __device__ __forceinline__ void steps_command(const Params& P, JpStage& st, Wave
       jp_level_items(P, st, W, l, nf, hc, gw, gstride, hl);
     }
     jp_stage_flush<SC_AGENT>(P, st, l);
+  } else if (op == PC_RELAX) {
+    const int rr = (int)ld32<SC_AGENT>(&c->rx[0]);
+    const int t = (int)ld32<SC_AGENT>(&c->rx[1]);
+    if (t == 0) jp_relax_list(P, st, rr, gw, gstride);
+    else jp_relax_items(P, st, W, nullptr, t, ld32<SC_AGENT>(&c->rx[2]), ld32<SC_AGENT>(&c->rx[3]), gw, gstride);
+    jp_stage_flush<SC_AGENT>(P, st, t);
   }
-  (void)r;
 }
 
 // The leader's side of one command: publish it, take participant 0's share,
@@ -2353,7 +2625,7 @@ __device__ __forceinline__ void steps_lead(const Params& P, JpStage& gst, WaveLd
   }
   ++seq;
   __syncthreads();
-  steps_command(P, gst, W, op, arg, 0, gw, gstride, flds);
+  steps_command(P, gst, W, op, arg, gw, gstride, flds);
   order_point();
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -2445,7 +2717,7 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_steps(Params P, int max_steps)
       ++seq;
       __syncthreads();
       if (op == PC_EXIT) return;
-      steps_command(P, gst, W, op, arg, 0, gw, gstride, flds);
+      steps_command(P, gst, W, op, arg, gw, gstride, flds);
       order_point();
       __syncthreads();
       if (threadIdx.x == 0) __hip_atomic_fetch_add(&c->pjoin, 1ull, __ATOMIC_RELAXED, SC_AGENT);
@@ -2464,7 +2736,13 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_steps(Params P, int max_steps)
       c->grid_op = OP_NONE;
       if (op == OP_XPULL) S.xpull = 0;
       else if (op == OP_SPLIT) S.split = 0;
-      else if (op == OP_LEVEL) jp_next_level(S);
+      else if (op == OP_LEVEL) {
+        S.rv += S.fcnt[S.level % 3] + (unsigned)S.hctr[S.level % 3];
+        jp_next_level(S);
+      } else if (op == OP_RELAX) {
+        S.rit += 1;
+        S.levels += 1;
+      }
     }
   }
   __syncthreads();
@@ -2513,6 +2791,69 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_steps(Params P, int max_steps)
       }
       __syncthreads();
       if (threadIdx.x == 0) S.xpull = 0;
+      __syncthreads();
+      continue;
+    }
+    if (JP_RELAX && P.relax_mode != RELAX_MODE_NONE && !S.relax && !S.split &&
+        (P.relax_mode == RELAX_MODE_ALL || (S.level >= RELAX_AFTER && relax_pays(P, S, r)))) {
+      // a deep round: its uncoloured vertices are relaxed from here on (a
+      // level still in LDS is dropped; its vertices are uncoloured)
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        S.relax = 1;
+        S.rit = 0;
+        have = 0;
+      }
+      __syncthreads();
+      in_global = false;
+      continue;
+    }
+    if (S.relax) {
+      const int t = S.rit;
+      const long long rs = seg_size(P, r);
+      const unsigned nl = t == 0 ? (unsigned)rs : S.fcnt[t % 3];
+      if (t > 0 && nl == 0) {   // no colour changed: the round is finished
+        __syncthreads();
+        if (threadIdx.x == 0) jp_begin_round(S, r - 1);
+        __syncthreads();
+        continue;
+      }
+      if ((long long)t > rs + 2 || (long long)nl > rs) {   // more steps than the longest chain needs: a broken state
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          raise_internal(P);
+          S.done = 1;
+        }
+        __syncthreads();
+        break;
+      }
+      const int nx = (t + 1) % 3;
+      if (threadIdx.x == 0) {
+        S.rstamp += 1;
+        jp_clear_level(S, nx);
+        st32<SC_AGENT>(&c->js.fcnt[nx], 0u);
+        st64<SC_AGENT>(&c->js.hctr[nx], 0ull);
+        st64<SC_AGENT>(&c->js.psum[nx], 0ull);
+        st64<SC_AGENT>(&c->js.ssum[nx], 0ull);
+      }
+      __syncthreads();
+      if (t == 0 ? rs > (long long)RELAX_MID * WAVE : nl > RELAX_MID) {
+        handed = OP_RELAX;   // the grid takes the step
+        break;
+      }
+      if (threadIdx.x == 0) {
+        st32<SC_AGENT>(&c->rx[0], (unsigned)r);
+        st32<SC_AGENT>(&c->rx[1], (unsigned)t);
+        st32<SC_AGENT>(&c->rx[2], nl);
+        st32<SC_AGENT>(&c->rx[3], S.rstamp);
+      }
+      steps_lead(P, gst, W, PC_RELAX, t, seq, nparts, gw, gstride, flds, &fcntl, acc, &stop);
+      since_cmd = 0;
+      if (threadIdx.x == 0) {
+        S.fcnt[nx] = ld32<SC_AGENT>(&c->js.fcnt[nx]);
+        S.rit = t + 1;
+        S.levels += 1;
+      }
       __syncthreads();
       continue;
     }
@@ -2583,6 +2924,7 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_steps(Params P, int max_steps)
             S.hctr[nx] = ld64<SC_AGENT>(&c->js.hctr[nx]);
             S.psum[nx] = ld64<SC_AGENT>(&c->js.psum[nx]);
             S.ssum[nx] = ld64<SC_AGENT>(&c->js.ssum[nx]);
+            S.rv += S.fcnt[l % 3] + (unsigned)S.hctr[l % 3];
             jp_next_level(S);
           }
           __syncthreads();
@@ -2636,6 +2978,7 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_steps(Params P, int max_steps)
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+      S.rv += Z.cnt[cur];
       jp_next_level(S);
       if (nn == 0) {
         jp_begin_round(S, r - 1);
@@ -2679,6 +3022,16 @@ __global__ __launch_bounds__(BS) void k_jp_grid(Params P) {
     long long items;
     if (op == OP_XPULL) {
       items = (seg_size(P, r) + WAVE - 1) / WAVE;
+    } else if (op == OP_RELAX) {
+      // step 0: groups of 64 of the round's vertices; later steps: a
+      // wavefront per listed vertex
+      const int t = c->js.rit;
+      const unsigned nl = c->js.fcnt[t % 3];
+      if (t > 0 && (long long)nl > seg_size(P, r)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) raise_internal(P);
+        return;
+      }
+      items = t == 0 ? (seg_size(P, r) + WAVE - 1) / WAVE : (long long)nl;
     } else if (op == OP_SPLIT) {
       items = ((long long)P.l0n[r] + WAVE - 1) / WAVE;
     } else {
@@ -2708,6 +3061,15 @@ __global__ __launch_bounds__(BS) void k_jp_grid(Params P) {
     jp_split_items(P, st, r, gw, gstride);
     jp_stage_flush<SC_AGENT>(P, st, -1);
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&c->js.F, (unsigned long long)P.l0n[r]);
+  } else if (op == OP_RELAX) {
+    const int t = c->js.rit;
+    // the fan-out staging area is free: it holds the wavefronts' bits of
+    // lane-solved vertices
+    static_assert(sizeof(flds) >= WPB * WAVE * RELAX_LW * 4, "relaxation buffers");
+    if (t == 0) jp_relax_list(P, st, r, gw, gstride);
+    else jp_relax_items(P, st, W, (unsigned*)flds + (threadIdx.x / WAVE) * WAVE * RELAX_LW, t, c->js.fcnt[t % 3],
+                        c->js.rstamp, gw, gstride);
+    jp_stage_flush<SC_AGENT>(P, st, t);
   } else {
     const int l = c->js.level;
     const unsigned long long hc = c->js.hctr[l % 3];
@@ -2718,6 +3080,13 @@ __global__ __launch_bounds__(BS) void k_jp_grid(Params P) {
 }
 
 __global__ void k_jp_start(Params P, int rounds) {
+  // colours start at 0 (relaxation lists the uncoloured vertices by it),
+  // and so do the relaxation marks
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < P.n; i += stride) {
+    P.color[i] = 0;
+    if (JP_RELAX) P.rmark[i] = 0u;
+  }
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   Ctrl* c = P.ctrl;
   c->grid_op = OP_NONE;
@@ -2727,6 +3096,7 @@ __global__ void k_jp_start(Params P, int rounds) {
   JpState& j = c->js;
   j.done = 0;
   j.levels = 0;
+  j.rstamp = 0;
   j.F = 0;
   j.top = rounds;
   if (P.ord_identity) {
@@ -2782,7 +3152,7 @@ __global__ __launch_bounds__(BS) void k_dec_pull(Params P, int p) {
     unsigned long long rec = 0;
     if (has) {
       b = P.rp[v];
-      e = b + (P.npred[v] - P.cnt[v]);
+      e = b + P.xpred[v];
       rec = rec_of(P, v);
     }
     // the wavefront walks long rows together; each entry marks in its row's bitmap
@@ -2854,7 +3224,7 @@ __global__ __launch_bounds__(BS) void k_dec_resolve(Params P, int p) {
       v = U[i];
       tv = P.tent[v];
       const int nps = P.cnt[v];
-      b = P.rp[v] + (P.npred[v] - nps);   // same-round predecessors: [b, e)
+      b = P.rp[v] + P.xpred[v];   // same-round predecessors: [b, e)
       e = b + nps;
       e2 = e + P.nsr[v];                  // and successors: [e, e2)
     }
@@ -3079,7 +3449,7 @@ void prof_end(int cls, hipStream_t s, hipEvent_t a, long long units) {
 namespace {
 
 struct Layout {
-  size_t ctrl, bcount, boff, bsum, xpart, D, status, UL0, UL1, ORD, roundN, round, dag, npred, nsr, cnt, rec, B,
+  size_t ctrl, bcount, boff, bsum, xpart, D, status, UL0, UL1, ORD, roundN, round, dag, xpred, nsr, cnt, rec, B,
       bm_cap, L0, l0n, F0, F1, H0, H1, hub_cap, HL, HC, huge_cap, mhist, pool, pool_chunk, total;
 };
 
@@ -3152,7 +3522,7 @@ Layout make_layout(int64_t n, int64_t nnz) {
   L.roundN = take(4 * (nn + 4));
   L.round = take(4 * nn);
   L.dag = take(4 * (size_t)nnz);
-  L.npred = take(4 * nn);
+  L.xpred = take(4 * nn);
   L.nsr = take(4 * nn);
   L.cnt = take(4 * nn);
   L.rec = take(16 * nn);
@@ -3252,7 +3622,7 @@ Params make_params(const adg_csr_t* g, void* ws, uint64_t p, uint64_t q, uint64_
   P.xpart = (unsigned long long*)(base + L.xpart);
   P.upd_blocks = upd_launch_blocks();
   P.dag = (int*)(base + L.dag);
-  P.npred = (int*)(base + L.npred);
+  P.xpred = (int*)(base + L.xpred);
   P.nsr = (int*)(base + L.nsr);
   P.cnt = (int*)(base + L.cnt);
   P.rec = (unsigned long long*)(base + L.rec);
@@ -3271,6 +3641,7 @@ Params make_params(const adg_csr_t* g, void* ws, uint64_t p, uint64_t q, uint64_
   P.HC = (unsigned*)(base + L.HC);
   P.huge_cap = (unsigned)L.huge_cap;
   P.color = color;
+  P.rmark = (unsigned*)(base + L.UL0);   // ADG's active lists are free once JP starts
   // Round-count bound from the ADG depth lemma: |U| shrinks by a factor
   // 1/(1+eps) per round, so L <= ceil(log n / log(1+eps)) + 1; +1 margin.
   long long bound = (long long)g->n + 1;
@@ -3411,7 +3782,8 @@ int run_jp(Params& P, hipStream_t s, int rounds) {
   if (P.n == 0) return ADG_OK;
   {
     TIMED(KC_JP_PREP, s);
-    hipLaunchKernelGGL(k_jp_start, dim3(1), dim3(64), 0, s, P, rounds);
+    const int blocks = (int)std::max<long long>(1, std::min<long long>(1024, ((long long)P.n + BS - 1) / BS));
+    hipLaunchKernelGGL(k_jp_start, dim3(blocks), dim3(BS), 0, s, P, rounds);
   }
   HIPCHK(hipGetLastError());
   PinnedFlags pf;
@@ -3668,10 +4040,13 @@ int color_graph_ex(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_
   if (rc) return rc;
   if (eps_num < 0 || eps_den < 1 || (g->n > 0 && !color_out)) return ADG_ERR_ARG;
   if (variant & ~(uint32_t)(ADG_VARIANT_SORTED | ADG_VARIANT_MEDIAN | ADG_VARIANT_DEC_ITR | ADG_VARIANT_PULL |
-                            ADG_VARIANT_MULTI_LAUNCH))
+                            ADG_VARIANT_MULTI_LAUNCH | ADG_VARIANT_RELAX_ALL | ADG_VARIANT_LEVELS_ONLY))
     return ADG_ERR_ARG;
-  const bool multi = (variant & ADG_VARIANT_MULTI_LAUNCH) != 0;
-  variant &= ~(uint32_t)ADG_VARIANT_MULTI_LAUNCH;
+  const uint32_t sched = variant & (uint32_t)(ADG_VARIANT_RELAX_ALL | ADG_VARIANT_LEVELS_ONLY);
+  if (sched == (uint32_t)(ADG_VARIANT_RELAX_ALL | ADG_VARIANT_LEVELS_ONLY) || (sched && (variant & ADG_VARIANT_DEC_ITR)))
+    return ADG_ERR_ARG;
+  const bool multi = (variant & ADG_VARIANT_MULTI_LAUNCH) != 0 || sched != 0;
+  variant &= ~(uint32_t)(ADG_VARIANT_MULTI_LAUNCH | ADG_VARIANT_RELAX_ALL | ADG_VARIANT_LEVELS_ONLY);
   if ((variant & ADG_VARIANT_DEC_ITR) && (variant & ADG_VARIANT_SORTED)) return ADG_ERR_ARG;
   if ((rc = check_ws(workspace, ws_bytes, g->n, g->nnz))) return rc;
   hipStream_t s = (hipStream_t)stream;
@@ -3689,6 +4064,8 @@ int color_graph_ex(const adg_csr_t* g, int32_t eps_num, int32_t eps_den, uint64_
                              num_colors_out, num_rounds_out, rest, ws_bytes - L.bcount, s, sink);
   }
   Params P = make_params(g, workspace, (uint64_t)eps_num, (uint64_t)eps_den, seed, 1, round_out, color_out, variant);
+  P.relax_mode = sched == ADG_VARIANT_RELAX_ALL ? RELAX_MODE_ALL : sched == ADG_VARIANT_LEVELS_ONLY ? RELAX_MODE_NONE
+                                                                                                     : RELAX_MODE_RULE;
   int L = 0;
   if ((rc = run_adg(P, s, true, &L))) return rc;
   if ((rc = P.dec ? run_dec(P, s, L) : run_jp(P, s, L))) return rc;

@@ -95,7 +95,14 @@ def test_variant_entry_points_reject_bad_arguments_without_gpu():
     csr = pkg._Csr(5, 8, fake, fake)
     ws = L.adg_workspace_bytes(5, 8)
     # unknown variant bits
-    assert L.color_graph_ex(ctypes.byref(csr), 1, 10, 0, 32, fake, None, None, None, fake, ws, None) == -1
+    assert L.color_graph_ex(ctypes.byref(csr), 1, 10, 0, 128, fake, None, None, None, fake, ws, None) == -1
+    # JP's schedule bits: not together, not with DEC-ADG-ITR, not for adg_order_ex
+    both = pkg.RELAX_ALL | pkg.LEVELS_ONLY
+    assert L.color_graph_ex(ctypes.byref(csr), 1, 10, 0, both, fake, None, None, None, fake, ws, None) == -1
+    for bit in (pkg.RELAX_ALL, pkg.LEVELS_ONLY):
+        assert L.color_graph_ex(ctypes.byref(csr), 1, 10, 0, bit | pkg.DEC_ITR, fake, None, None, None, fake, ws,
+                                None) == -1
+        assert L.adg_order_ex(ctypes.byref(csr), 1, 10, 0, bit, fake, None, None, fake, ws, None) == -1
     assert L.adg_order_ex(ctypes.byref(csr), 1, 10, 0, 16, fake, None, None, fake, ws, None) == -1
     # DEC-ADG-ITR colours only, and not with ADG-O's order
     assert L.color_graph_ex(ctypes.byref(csr), 1, 10, 0, 5, fake, None, None, None, fake, ws, None) == -1

@@ -34,12 +34,13 @@ def _gpu_color(pkg, rp, col, p, q, seed, variant=0):
 
 
 def _compare(pkg, rp, col, p, q, seed, label=""):
-    """Both routes of color_graph against the oracle: the default one (a
-    graph of at most 2^17 entries goes to the one-launch engine) and the
-    per-round kernels (MULTI_LAUNCH)."""
+    """Every route of color_graph against the oracle: the default one (a
+    graph of at most 2^17 entries goes to the one-launch engine), the
+    per-round kernels (MULTI_LAUNCH), and those with JP relaxing every round
+    (RELAX_ALL) or none (LEVELS_ONLY)."""
     print("case", label, "n", rp.size - 1, "nnz", col.size, "eps", p, q, "seed", seed, flush=True)
     color, k, rho, L, st = oracle.color_graph(rp, col, p, q, seed)
-    for variant in (0, pkg.MULTI_LAUNCH):
+    for variant in (0, pkg.MULTI_LAUNCH, pkg.RELAX_ALL, pkg.LEVELS_ONLY):
         gc, gk, gr, gL, gst = _gpu_color(pkg, rp, col, p, q, seed, variant)
         lab = (label, "route", variant)
         assert gL == L, (lab, gL, L)

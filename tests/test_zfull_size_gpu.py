@@ -287,25 +287,30 @@ def test_rmat26_equals_the_oracle(rmat26, p, q):
     """Element by element against the serial CPU oracle (Algorithm 1 step by
     step, then greedy colouring in decreasing <round, rho_R> order) at every
     eps of the configuration: rounds, colours, L, the colour count and the
-    counters sum |U_l| and cut edges."""
+    counters sum |U_l| and cut edges.  JP runs with each of its schedules:
+    the default (levels, deep rounds relaxed), every round relaxed, and
+    levels only."""
     import torch
     pkg, rp, g, runs = rmat26
     seed = 3
-    print("case rmat26 eps %d/%d vs the oracle" % (p, q), flush=True)
+    oc, ok, orho, oL, ost = None, None, None, None, None
     ws = torch.empty(pkg.workspace_bytes(g.n, g.nnz), dtype=torch.uint8, device="cuda")
-    color, nc, rnd, nr = pkg.color_graph(g, p, q, seed, workspace=ws)
-    torch.cuda.synchronize()
-    st = pkg.get_stats(ws)
+    for variant in (0, pkg.RELAX_ALL, pkg.LEVELS_ONLY):
+        print("case rmat26 eps %d/%d variant %d vs the oracle" % (p, q, variant), flush=True)
+        color, nc, rnd, nr = pkg.color_graph_ex(g, p, q, seed, variant, workspace=ws)
+        torch.cuda.synchronize()
+        st = pkg.get_stats(ws)
+        colour_h, rnd_h = color.cpu().numpy(), rnd.cpu().numpy()
+        del color, rnd
+        if oc is None:
+            oc, ok, orho, oL, ost = runs[(p, q)].result(timeout=600)
+        print("gpu: rounds", int(nr.item()), "colours", int(nc.item()), "oracle: rounds", oL, "colours", ok, flush=True)
+        assert st["error"] == 0
+        assert int(nr.item()) == oL and st["num_rounds"] == oL
+        assert int(nc.item()) == ok and st["num_colors"] == ok
+        assert st["sum_active"] == ost["sum_active"] and st["cut_edges"] == ost["cut_edges"]
+        bad_r = int((rnd_h != orho).sum())
+        bad_c = int((colour_h != oc).sum())
+        assert bad_r == 0, "variant %d: %d rounds differ" % (variant, bad_r)
+        assert bad_c == 0, "variant %d: %d colours differ" % (variant, bad_c)
     del ws
-    colour_h, rnd_h = color.cpu().numpy(), rnd.cpu().numpy()
-    del color, rnd
-    oc, ok, orho, oL, ost = runs[(p, q)].result(timeout=600)
-    print("gpu: rounds", int(nr.item()), "colours", int(nc.item()), "oracle: rounds", oL, "colours", ok, flush=True)
-    assert st["error"] == 0
-    assert int(nr.item()) == oL and st["num_rounds"] == oL
-    assert int(nc.item()) == ok and st["num_colors"] == ok
-    assert st["sum_active"] == ost["sum_active"] and st["cut_edges"] == ost["cut_edges"]
-    bad_r = int((rnd_h != orho).sum())
-    bad_c = int((colour_h != oc).sum())
-    assert bad_r == 0, "%d rounds differ" % bad_r
-    assert bad_c == 0, "%d colours differ" % bad_c
