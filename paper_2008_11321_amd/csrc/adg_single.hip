@@ -76,22 +76,14 @@ namespace adg {
 constexpr int BS = 256;                 // threads per block
 constexpr int WPB = BS / WAVE;          // wavefronts per block
 constexpr int SEL_BLOCKS = 2048;        // fixed grid of the selection kernels
-#ifndef ADG_JP_STEPS
-#define ADG_JP_STEPS 1   // JP's narrow and mid-sized steps in one launch of a leader and helper blocks
-#endif
 #ifndef ADG_JP_RELAX
-#define ADG_JP_RELAX ADG_JP_STEPS   // deep rounds finished by relaxation (needs the steps launch)
-#endif
-#if ADG_JP_RELAX && !ADG_JP_STEPS
-#error "relaxation runs from the steps launch"
+#define ADG_JP_RELAX 1   // deep rounds finished by relaxation
 #endif
 constexpr bool JP_RELAX = ADG_JP_RELAX;
-#ifndef ADG_UPDATE_ONE_PASS
-#define ADG_UPDATE_ONE_PASS 1
+#ifndef ADG_UPD_UNROLL
+#define ADG_UPD_UNROLL 4
 #endif
-// JP's row partition in one pass: no DEC-ADG-ITR, and no relaxation, which
-// reads the same-round predecessors that this partition leaves out
-constexpr bool UPDATE_ONE_PASS = ADG_UPDATE_ONE_PASS && !ADG_JP_RELAX;
+constexpr int UPD_UNROLL = ADG_UPD_UNROLL;   // 64-entry chunks of rows UPDATE reads at a time
 #ifndef ADG_SMALL_DEG
 #define ADG_SMALL_DEG 32
 #endif
@@ -277,8 +269,7 @@ struct Params {
   unsigned long long* HL;      // rows of the round cut into chunks: (first chunk << 32) | vertex
   unsigned* HC;                // per such row: class counts [4] and placed counts [4]
   unsigned huge_cap;
-  unsigned* L0;                // first JP level of each round, in the round's ORD slot range
-  unsigned* l0n;               // its size, per round
+  unsigned* L0;                // first JP level of each round, indexed like the round's ORD slot (~0: not in it)
   unsigned* F[2];              // level lists, plain vertices (by level parity)
   unsigned long long* H[2];    // level lists, fan-out vertices: (first chunk << 32) | vertex
   unsigned hub_cap;
@@ -379,7 +370,6 @@ __global__ void k_init(Params P) {
     j.psum[k] = 0;
     j.ssum[k] = 0;
   }
-  for (int k = 0; k < 3; ++k) P.l0n[k] = 0;
   if (P.median)
     for (int k = 0; k < MSEL_BINS; ++k) P.mhist[k] = 0;
 }
@@ -415,7 +405,6 @@ __global__ void k_stats(Params P, int l) {
   c->huge_ctr = 0;
   if (l <= P.max_rounds + 1) {
     P.roundN[l] = (unsigned)N;
-    P.l0n[l] = 0;
   }
   if (N == 0) {
     c->done = 1;
@@ -757,6 +746,36 @@ __device__ __forceinline__ int visit3(const Params& P, int w, int l, unsigned ch
   return NB_SUCC_EARLIER;
 }
 
+// visit3 for UPD_UNROLL entries at once (ok[u]: entry u exists): the status
+// gathers first, then the round gathers of same-round candidates, then the
+// decisions, so that each kind of gather is in flight for all entries together.
+template <bool FUSED>
+__device__ __forceinline__ void visit_n(const Params& P, const int* w, const bool* ok, int l, unsigned char code,
+                                        const unsigned long long* hv, unsigned& x, bool decrement, int* cl) {
+  unsigned char st[UPD_UNROLL];
+#pragma unroll
+  for (int u = 0; u < UPD_UNROLL; ++u) st[u] = ok[u] ? P.status[w[u]] : 0;
+  int rr[UPD_UNROLL];
+#pragma unroll
+  for (int u = 0; u < UPD_UNROLL; ++u) rr[u] = FUSED && ok[u] && st[u] == code ? P.round[w[u]] : 0;
+#pragma unroll
+  for (int u = 0; u < UPD_UNROLL; ++u) {
+    if (!ok[u]) {
+      cl[u] = NB_NONE;
+    } else if (st[u] == 0) {
+      if (decrement) {
+        atomicSub(&P.D[w[u]], 1);
+        x += 1;
+      }
+      cl[u] = NB_PRED;
+    } else if (FUSED && st[u] == code && rr[u] == l) {
+      cl[u] = same_key(P, w[u]) > hv[u] ? NB_PRED_SAME : NB_SUCC_SAME;
+    } else {
+      cl[u] = NB_SUCC_EARLIER;
+    }
+  }
+}
+
 __device__ __forceinline__ bool is_pred(int cl) { return cl == NB_PRED || cl == NB_PRED_SAME; }
 
 // Colour bitmap words of a vertex with np predecessors: bits for colours
@@ -862,38 +881,12 @@ __device__ __forceinline__ void jp_row(const Params& P, BmPool* pl, bool has, in
       ((unsigned long long)first << 24) | (ns < (long long)SP_NS_MAX ? (unsigned)ns : SP_NS_MAX);
 }
 
-// Wavefront: append the lanes' vertices with z set to the first JP level of
-// their round (list L0 at `base`, counter l0n[l]).
-__device__ __forceinline__ void l0_append(const Params& P, int l, long long base, bool z, int v) {
-  const uint64_t m = ballot(z);
-  if (!m) return;
-  const int leader = __ffsll((long long)m) - 1;
-  unsigned at = 0;
-  if (lane_id() == (unsigned)leader) at = atomicAdd(&P.l0n[l], (unsigned)__popcll(m));
-  at = readlane_u(at, leader);
-  if (z) P.L0[base + at + lanes_below(m)] = (unsigned)v;
-}
-
-// Wavefront-per-row kernels append one vertex at a time: they stage the
-// vertices in a register (lane k holds the k-th) and flush 64 with one atomic.
-struct L0Stage {
-  int v;
-  unsigned cnt;   // wave-uniform
-};
-__device__ __forceinline__ void l0_flush(const Params& P, L0Stage& s, int l, long long base) {
-  if (!s.cnt) return;
-  unsigned at = 0;
-  if (lane_id() == 0) at = atomicAdd(&P.l0n[l], s.cnt);
-  at = readlane_u(at, 0);
-  if (lane_id() < s.cnt) P.L0[base + at + lane_id()] = (unsigned)s.v;
-  s.cnt = 0;
-}
-// z and v wave-uniform
-__device__ __forceinline__ void l0_stage(const Params& P, L0Stage& s, int l, long long base, bool z, int v) {
-  if (!z) return;
-  if (lane_id() == s.cnt) s.v = v;
-  s.cnt += 1;
-  if (s.cnt == WAVE) l0_flush(P, s, l, base);
+// A vertex at position idx of its round's ORD slot (base) joins the round's
+// first JP level iff it has no same-round predecessor (z).  L0 is indexed
+// like the slot: it holds the vertex at that position, or ~0, so building
+// it needs no counter.
+__device__ __forceinline__ void l0_mark(const Params& P, long long base, long long idx, bool z, int v) {
+  P.L0[base + idx] = z ? (unsigned)v : ~0u;
 }
 
 // UPDATE for a wavefront's 64 rows of at most SMALL_DEG entries each (one
@@ -926,7 +919,7 @@ __device__ __forceinline__ int small_owner(const SmallRows& S, int pos) {
 
 template <bool FUSED>
 __device__ void update_small(const Params& P, BmPool* pl, SmallRows& S, int v, bool valid, int l,
-                             unsigned char code, unsigned& x) {
+                             unsigned char code, unsigned& x, long long idx0) {
   const unsigned lane = lane_id();
   long long b = 0, e = 0;
   if (valid) {
@@ -945,65 +938,56 @@ __device__ void update_small(const Params& P, BmPool* pl, SmallRows& S, int v, b
       S.run[lane][k] = 0;
     }
   wave_sync();
-  if (FUSED && UPDATE_ONE_PASS && !P.dec) {
-    // JP needs the predecessors from later rounds (front of the row) and
-    // the same-round successors (back of the row); same-round predecessors
-    // are only counted.  One pass: each entry goes straight to its place.
-    for (int p0 = 0; p0 < T; p0 += WAVE) {
-      const int pos = p0 + (int)lane;
-      if (pos < T) {
-        const int k = small_owner(S, pos);
-        const long long bk = S.b[k];
-        const int w = P.col[bk + (pos - S.off[k])];
-        const int cl = visit3<true>(P, w, l, code, S.hv[k], x, !P.pull);
-        if (cl == NB_PRED) {
-          P.dag[bk + atomicAdd(&S.run[k][NB_PRED], 1u)] = w;
-        } else if (cl == NB_SUCC_SAME) {
-          const long long ek = bk + (S.off[k + 1] - S.off[k]);
-          P.dag[ek - 1 - atomicAdd(&S.run[k][NB_SUCC_SAME], 1u)] = w;
-        } else if (cl == NB_PRED_SAME) {
-          atomicAdd(&S.run[k][NB_PRED_SAME], 1u);
-        }
-      }
+  for (int p0 = 0; p0 < T; p0 += WAVE * UPD_UNROLL) {
+    int w[UPD_UNROLL], k[UPD_UNROLL], cl[UPD_UNROLL];
+    bool ok[UPD_UNROLL];
+    unsigned long long hv[UPD_UNROLL];
+#pragma unroll
+    for (int u = 0; u < UPD_UNROLL; ++u) {
+      const int pos = p0 + u * WAVE + (int)lane;
+      ok[u] = pos < T;
+      k[u] = ok[u] ? small_owner(S, pos) : 0;
+      w[u] = ok[u] ? P.col[S.b[k[u]] + (pos - S.off[k[u]])] : 0;
+      hv[u] = S.hv[k[u]];
     }
-    wave_sync();
-    const long long nl = S.run[lane][NB_PRED], nps = S.run[lane][NB_PRED_SAME], ns = S.run[lane][NB_SUCC_SAME];
-    wave_sync();   // the LDS is rewritten by the wavefront's next group of rows
-    jp_row(P, pl, valid, v, e - ns, nl + nps, ns, nps);
-    l0_append(P, l, (long long)P.n - P.roundN[l], valid && nps == 0, v);
-    return;
-  }
-  for (int p0 = 0; p0 < T; p0 += WAVE) {
-    const int pos = p0 + (int)lane;
-    if (pos < T) {
-      const int k = small_owner(S, pos);
-      const int cl = visit3<FUSED>(P, P.col[S.b[k] + (pos - S.off[k])], l, code, S.hv[k], x, !P.pull);
-      if (FUSED) {
-        S.cls[pos] = (unsigned char)cl;
-        atomicAdd(&S.cnt[k][cl], 1u);
-      }
+    visit_n<FUSED>(P, w, ok, l, code, hv, x, !P.pull, cl);
+    if (FUSED) {
+#pragma unroll
+      for (int u = 0; u < UPD_UNROLL; ++u)
+        if (ok[u]) {
+          S.cls[p0 + u * WAVE + (int)lane] = (unsigned char)cl[u];
+          atomicAdd(&S.cnt[k[u]][cl[u]], 1u);
+        }
     }
   }
   if (!FUSED) return;
   wave_sync();
   const long long nl = S.cnt[lane][NB_PRED], nps = S.cnt[lane][NB_PRED_SAME], ns = S.cnt[lane][NB_SUCC_SAME];
   const long long np = nl + nps;
-  for (int p0 = 0; p0 < T; p0 += WAVE) {
-    const int pos = p0 + (int)lane;
-    const int cl = pos < T ? S.cls[pos] : NB_NONE;
-    if (cl != NB_NONE && cl != NB_SUCC_EARLIER) {   // earlier-round successors: never read back
-      const int k = small_owner(S, pos);
-      const long long bk = S.b[k];
-      const int w = P.col[bk + (pos - S.off[k])];
-      const long long r = atomicAdd(&S.run[k][cl], 1u);
-      const long long nlk = S.cnt[k][NB_PRED], npk = nlk + S.cnt[k][NB_PRED_SAME];
-      const long long at = cl == NB_PRED ? bk + r : cl == NB_PRED_SAME ? bk + nlk + r : bk + npk + r;
-      P.dag[at] = w;
+  for (int p0 = 0; p0 < T; p0 += WAVE * UPD_UNROLL) {
+    int w[UPD_UNROLL], k[UPD_UNROLL], cl[UPD_UNROLL];
+#pragma unroll
+    for (int u = 0; u < UPD_UNROLL; ++u) {
+      const int pos = p0 + u * WAVE + (int)lane;
+      cl[u] = pos < T ? S.cls[pos] : NB_NONE;
+      const bool keep = cl[u] != NB_NONE && cl[u] != NB_SUCC_EARLIER;   // earlier-round successors: never read back
+      k[u] = keep ? small_owner(S, pos) : 0;
+      w[u] = keep ? P.col[S.b[k[u]] + (pos - S.off[k[u]])] : 0;
+      if (!keep) cl[u] = NB_NONE;
     }
+#pragma unroll
+    for (int u = 0; u < UPD_UNROLL; ++u)
+      if (cl[u] != NB_NONE) {
+        const long long bk = S.b[k[u]];
+        const long long r = atomicAdd(&S.run[k[u]][cl[u]], 1u);
+        const long long nlk = S.cnt[k[u]][NB_PRED], npk = nlk + S.cnt[k[u]][NB_PRED_SAME];
+        const long long at = cl[u] == NB_PRED ? bk + r : cl[u] == NB_PRED_SAME ? bk + nlk + r : bk + npk + r;
+        P.dag[at] = w[u];
+      }
   }
   wave_sync();   // the LDS is rewritten by the wavefront's next group of rows
   jp_row(P, pl, valid, v, b + np, np, ns, nps);
-  l0_append(P, l, (long long)P.n - P.roundN[l], valid && nps == 0, v);
+  if (valid) l0_mark(P, (long long)P.n - P.roundN[l], idx0 + lane, nps == 0, v);
 }
 
 // Wave-per-vertex UPDATE for longer rows: count pass (with the decrements),
@@ -1013,13 +997,17 @@ __device__ void update_small(const Params& P, BmPool* pl, SmallRows& S, int v, b
 // predecessors from later rounds, same-round predecessors and same-round
 // successors (the rest are earlier-round successors).
 constexpr int ROW_CHUNKS = HUGE_DEG / WAVE;
+// Per hub row, HC holds the class counts [4] and placed counts [4]; earlier
+// successors are never placed, so their placed-count word holds instead the
+// hub's position in its round's ORD slot (for L0).
+constexpr int HC_SLOT = 4 + NB_SUCC_EARLIER;
 struct RowMasks {
   uint64_t m[ROW_CHUNKS][3];
 };
 
 template <bool FUSED>
-__device__ void update_big(const Params& P, BmPool* pl, L0Stage& l0s, RowMasks& rm, int v, int l,
-                           unsigned char code, unsigned& x) {
+__device__ void update_big(const Params& P, BmPool* pl, RowMasks& rm, int v, int l, unsigned char code,
+                           unsigned& x, long long idx) {
   const long long b = P.rp[v], e = P.rp[v + 1];
   if (e - b > HUGE_DEG) {  // a hub: its chunks are spread over the grid by k_update_huge_*
     if (lane_id() == 0) {
@@ -1029,6 +1017,8 @@ __device__ void update_big(const Params& P, BmPool* pl, L0Stage& l0s, RowMasks& 
       if (h < P.huge_cap) {
         P.HL[h] = (old & 0xffffffff00000000ull) | (unsigned)v;
         for (int k = 0; k < 8; ++k) P.HC[8 * (size_t)h + k] = 0;
+        P.HC[8 * (size_t)h + HC_SLOT] = (unsigned)idx;
+        if (FUSED) l0_mark(P, (long long)P.n - P.roundN[l], idx, false, v);   // set by the hub kernels
       } else {
         atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
       }
@@ -1038,40 +1028,31 @@ __device__ void update_big(const Params& P, BmPool* pl, L0Stage& l0s, RowMasks& 
   const unsigned long long hv = same_key(P, v);
   const unsigned lane = lane_id();
   long long nl = 0, nps = 0, ns = 0;
-  if (FUSED && UPDATE_ONE_PASS && !P.dec) {
-    // JP: predecessors from later rounds to the front, same-round
-    // successors to the back, same-round predecessors only counted; one pass
-    for (long long base = b; base < e; base += WAVE) {
-      const long long j = base + lane;
-      const bool ok = j < e;
-      const int w = ok ? P.col[j] : 0;
-      const int cl = ok ? visit3<true>(P, w, l, code, hv, x, !P.pull) : NB_NONE;
-      const uint64_t fm = ballot(cl == NB_PRED), gm = ballot(cl == NB_PRED_SAME), sm = ballot(cl == NB_SUCC_SAME);
-      if (cl == NB_PRED) P.dag[b + nl + lanes_below(fm)] = w;
-      else if (cl == NB_SUCC_SAME) P.dag[e - 1 - ns - lanes_below(sm)] = w;
-      nl += __popcll(fm);
-      nps += __popcll(gm);
-      ns += __popcll(sm);
-    }
-    jp_row(P, pl, lane == 0, v, e - ns, nl + nps, ns, nps);
-    l0_stage(P, l0s, l, (long long)P.n - P.roundN[l], nps == 0, v);
-    return;
-  }
   int ch = 0;
-  for (long long base = b; base < e; base += WAVE, ++ch) {
-    long long j = base + lane;
-    bool valid = j < e;
-    int w = valid ? P.col[j] : 0;
-    int cl = valid ? visit3<FUSED>(P, w, l, code, hv, x, !P.pull) : NB_NONE;
+  for (long long base = b; base < e; base += WAVE * UPD_UNROLL, ch += UPD_UNROLL) {
+    int w[UPD_UNROLL], cl[UPD_UNROLL];
+    bool ok[UPD_UNROLL];
+    unsigned long long hvs[UPD_UNROLL];
+#pragma unroll
+    for (int u = 0; u < UPD_UNROLL; ++u) {
+      const long long j = base + u * WAVE + lane;
+      ok[u] = j < e;
+      w[u] = ok[u] ? P.col[j] : 0;
+      hvs[u] = hv;
+    }
+    visit_n<FUSED>(P, w, ok, l, code, hvs, x, !P.pull, cl);
     if (FUSED) {
-      const uint64_t fm = ballot(cl == NB_PRED), gm = ballot(cl == NB_PRED_SAME), sm = ballot(cl == NB_SUCC_SAME);
-      nl += __popcll(fm);
-      nps += __popcll(gm);
-      ns += __popcll(sm);
-      if (lane == 0) {
-        rm.m[ch][0] = fm;
-        rm.m[ch][1] = gm;
-        rm.m[ch][2] = sm;
+#pragma unroll
+      for (int u = 0; u < UPD_UNROLL; ++u) {
+        const uint64_t fm = ballot(cl[u] == NB_PRED), gm = ballot(cl[u] == NB_PRED_SAME), sm = ballot(cl[u] == NB_SUCC_SAME);
+        nl += __popcll(fm);
+        nps += __popcll(gm);
+        ns += __popcll(sm);
+        if (lane == 0 && base + u * WAVE < e) {   // rows of at most HUGE_DEG entries: ch + u < ROW_CHUNKS
+          rm.m[ch + u][0] = fm;
+          rm.m[ch + u][1] = gm;
+          rm.m[ch + u][2] = sm;
+        }
       }
     }
   }
@@ -1080,25 +1061,32 @@ __device__ void update_big(const Params& P, BmPool* pl, L0Stage& l0s, RowMasks& 
   const long long np = nl + nps;
   long long fc = 0, gc = 0, sc = 0;
   ch = 0;
-  for (long long base = b; base < e; base += WAVE, ++ch) {
-    const uint64_t fm = rm.m[ch][0], gm = rm.m[ch][1], sm = rm.m[ch][2];
-    // earlier-round successors are never read back: a chunk of only those
-    // needs no pass at all
-    if (!(fm | gm | sm)) continue;
+  for (long long base = b; base < e; base += WAVE * UPD_UNROLL, ch += UPD_UNROLL) {
+    uint64_t fm[UPD_UNROLL], gm[UPD_UNROLL], sm[UPD_UNROLL];
+    int w[UPD_UNROLL];
     const uint64_t me = 1ull << lane;
-    if ((fm | gm | sm) & me) {
-      const int w = P.col[base + lane];
-      if (fm & me) P.dag[b + fc + lanes_below(fm)] = w;
-      else if (gm & me) P.dag[b + nl + gc + lanes_below(gm)] = w;
-      else P.dag[b + np + sc + lanes_below(sm)] = w;
+#pragma unroll
+    for (int u = 0; u < UPD_UNROLL; ++u) {
+      const bool in = base + u * WAVE < e;
+      fm[u] = in ? rm.m[ch + u][0] : 0;
+      gm[u] = in ? rm.m[ch + u][1] : 0;
+      sm[u] = in ? rm.m[ch + u][2] : 0;
+      // earlier-round successors are never read back: their lanes load nothing
+      w[u] = (fm[u] | gm[u] | sm[u]) & me ? P.col[base + u * WAVE + lane] : 0;
     }
-    fc += __popcll(fm);
-    gc += __popcll(gm);
-    sc += __popcll(sm);
+#pragma unroll
+    for (int u = 0; u < UPD_UNROLL; ++u) {
+      if (fm[u] & me) P.dag[b + fc + lanes_below(fm[u])] = w[u];
+      else if (gm[u] & me) P.dag[b + nl + gc + lanes_below(gm[u])] = w[u];
+      else if (sm[u] & me) P.dag[b + np + sc + lanes_below(sm[u])] = w[u];
+      fc += __popcll(fm[u]);
+      gc += __popcll(gm[u]);
+      sc += __popcll(sm[u]);
+    }
   }
   wave_sync();   // the masks are rewritten by the wavefront's next row
   jp_row(P, pl, lane == 0, v, b + np, np, ns, nps);
-  l0_stage(P, l0s, l, (long long)P.n - P.roundN[l], nps == 0, v);
+  if (lane == 0) l0_mark(P, (long long)P.n - P.roundN[l], idx, nps == 0, v);
 }
 
 template <bool FUSED>
@@ -1115,7 +1103,6 @@ __global__ __launch_bounds__(BS) void k_update(Params P, int l) {
   const long long gstride = (long long)gridDim.x * WPB;
   unsigned x = 0;
   BmPool pool = {0, 0};
-  L0Stage l0s = {0, 0};
   // per wavefront: the short rows' entry classes, or a long row's masks
   __shared__ union WaveUpd {
     SmallRows sr;
@@ -1128,15 +1115,13 @@ __global__ __launch_bounds__(BS) void k_update(Params P, int l) {
       long long idx = it * WAVE + lane_id();
       bool valid = idx < nRs;
       int v = valid ? RL[idx] : 0;
-      update_small<FUSED>(P, &pool, U.sr, v, valid, l, code, x);
+      update_small<FUSED>(P, &pool, U.sr, v, valid, l, code, x, it * WAVE);
     } else {
-      update_big<FUSED>(P, &pool, l0s, U.rm, RL[nRs + (it - nsg)], l, code, x);
+      const long long idx = nRs + (it - nsg);
+      update_big<FUSED>(P, &pool, U.rm, RL[idx], l, code, x, idx);
     }
   }
-  if (FUSED) {
-    l0_flush(P, l0s, l, (long long)P.n - P.roundN[l]);
-    pool_store(P, gw, pool);
-  }
+  if (FUSED) pool_store(P, gw, pool);
   unsigned long long xs = wave_sum((unsigned long long)x);
   if (lane_id() == 0) xred[threadIdx.x / WAVE] = xs;
   __syncthreads();
@@ -1241,13 +1226,25 @@ __global__ __launch_bounds__(BS) void k_update_huge_count(Params P, int l) {
     const long long c1 = c0 + HUGE_CHUNK < e ? c0 + HUGE_CHUNK : e;
     const unsigned long long hv = same_key(P, v);
     unsigned cnt[4] = {0, 0, 0, 0};
-    for (long long base = c0; base < c1; base += WAVE) {
-      const long long j = base + lane;
-      const int cl = j < c1 ? visit3<FUSED>(P, P.col[j], l, code, hv, x, !P.pull) : NB_NONE;
-      cnt[NB_PRED] += __popcll(ballot(cl == NB_PRED));
-      cnt[NB_PRED_SAME] += __popcll(ballot(cl == NB_PRED_SAME));
-      cnt[NB_SUCC_SAME] += __popcll(ballot(cl == NB_SUCC_SAME));
-      cnt[NB_SUCC_EARLIER] += __popcll(ballot(cl == NB_SUCC_EARLIER));
+    for (long long base = c0; base < c1; base += WAVE * UPD_UNROLL) {
+      int w[UPD_UNROLL], cl[UPD_UNROLL];
+      bool ok[UPD_UNROLL];
+      unsigned long long hvs[UPD_UNROLL];
+#pragma unroll
+      for (int u = 0; u < UPD_UNROLL; ++u) {
+        const long long j = base + u * WAVE + lane;
+        ok[u] = j < c1;
+        w[u] = ok[u] ? P.col[j] : 0;
+        hvs[u] = hv;
+      }
+      visit_n<FUSED>(P, w, ok, l, code, hvs, x, !P.pull, cl);
+#pragma unroll
+      for (int u = 0; u < UPD_UNROLL; ++u) {
+        cnt[NB_PRED] += __popcll(ballot(cl[u] == NB_PRED));
+        cnt[NB_PRED_SAME] += __popcll(ballot(cl[u] == NB_PRED_SAME));
+        cnt[NB_SUCC_SAME] += __popcll(ballot(cl[u] == NB_SUCC_SAME));
+        cnt[NB_SUCC_EARLIER] += __popcll(ballot(cl[u] == NB_SUCC_EARLIER));
+      }
     }
     if (FUSED && lane < 4) atomicAdd(&P.HC[8 * (size_t)h + lane], cnt[lane]);
   }
@@ -1281,27 +1278,43 @@ __global__ __launch_bounds__(BS) void k_update_huge_place(Params P, int l) {
     const long long nl = C[NB_PRED], nps = C[NB_PRED_SAME], ns = C[NB_SUCC_SAME];
     const long long np = nl + nps;
     const long long start[4] = {b, b + np, 0, b + nl};   // by class (earlier successors are not kept)
-    for (long long base = c0; base < c1; base += WAVE) {
-      const long long j = base + lane;
-      const int w = j < c1 ? P.col[j] : 0;
-      const int cl = j < c1 ? visit3<true>(P, w, l, code, hv, x, false) : NB_NONE;
+    for (long long base = c0; base < c1; base += WAVE * UPD_UNROLL) {
+      int w[UPD_UNROLL], cl[UPD_UNROLL];
+      bool ok[UPD_UNROLL];
+      unsigned long long hvs[UPD_UNROLL];
+#pragma unroll
+      for (int u = 0; u < UPD_UNROLL; ++u) {
+        const long long j = base + u * WAVE + lane;
+        ok[u] = j < c1;
+        w[u] = ok[u] ? P.col[j] : 0;
+        hvs[u] = hv;
+      }
+      visit_n<true>(P, w, ok, l, code, hvs, x, false, cl);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         if (q == NB_SUCC_EARLIER) continue;   // never read back
-        const uint64_t m = ballot(cl == q);
-        if (!m) continue;
+        // one reservation for the class's entries of all UPD_UNROLL chunks
+        uint64_t m[UPD_UNROLL];
+        unsigned tot = 0;
+#pragma unroll
+        for (int u = 0; u < UPD_UNROLL; ++u) {
+          m[u] = ballot(cl[u] == q);
+          tot += (unsigned)__popcll(m[u]);
+        }
+        if (!tot) continue;
         unsigned at = 0;
-        if (lane == 0) at = atomicAdd(&C[4 + q], (unsigned)__popcll(m));
+        if (lane == 0) at = atomicAdd(&C[4 + q], tot);
         at = readlane_u(at, 0);
-        if (cl == q) {
-          const long long o = at + lanes_below(m);
-          P.dag[start[q] + o] = w;
+#pragma unroll
+        for (int u = 0; u < UPD_UNROLL; ++u) {
+          if (cl[u] == q) P.dag[start[q] + at + lanes_below(m[u])] = w[u];
+          at += (unsigned)__popcll(m[u]);
         }
       }
     }
     if (k == first) {
       jp_row(P, nullptr, lane == 0, v, b + np, np, ns, nps);
-      l0_append(P, l, (long long)P.n - P.roundN[l], lane == 0 && nps == 0, v);
+      if (lane == 0) l0_mark(P, (long long)P.n - P.roundN[l], C[HC_SLOT], nps == 0, v);
     }
   }
 }
@@ -1322,7 +1335,6 @@ __global__ __launch_bounds__(BS) void k_part1(Params P) {
   const unsigned lane = lane_id();
   const long long groups = ((long long)P.n + WAVE - 1) / WAVE;
   BmPool pool = pool_load(P, gw);
-  L0Stage l0s = {0, 0};
   for (long long g = gw; g < groups; g += gstride) {
     long long idx = g * WAVE + lane;
     bool valid = idx < P.n;
@@ -1341,7 +1353,7 @@ __global__ __launch_bounds__(BS) void k_part1(Params P) {
       np = f - b;
     }
     jp_row(P, &pool, small, v, b + np, np, (e - b) - np, np);
-    l0_append(P, 1, 0, small && np == 0, v);
+    if (small) l0_mark(P, 0, v, np == 0, v);   // one pseudo-round: its slot is the identity
     uint64_t big = ballot(valid && !small);
     while (big) {
       int L = __ffsll((long long)big) - 1;
@@ -1362,10 +1374,9 @@ __global__ __launch_bounds__(BS) void k_part1(Params P) {
         sc += __popcll(sm);
       }
       jp_row(P, &pool, lane == 0, u, ub + fc, fc, sc, fc);
-      l0_stage(P, l0s, 1, 0, fc == 0, u);
+      if (lane == 0) l0_mark(P, 0, u, fc == 0, u);
     }
   }
-  l0_flush(P, l0s, 1, 0);
   pool_store(P, gw, pool);
 }
 
@@ -1435,9 +1446,7 @@ __device__ __forceinline__ bool level_ok(const Params& P, unsigned nf, unsigned 
   return false;
 }
 __device__ __forceinline__ bool round_ok(const Params& P, int r) {
-  if (r >= 1 && P.roundN[r] <= (unsigned)P.n && P.roundN[r + 1] <= P.roundN[r] &&
-      P.l0n[r] <= P.roundN[r] - P.roundN[r + 1])
-    return true;
+  if (r >= 1 && P.roundN[r] <= (unsigned)P.n && P.roundN[r + 1] <= P.roundN[r]) return true;
   raise_internal(P);
   return false;
 }
@@ -1714,15 +1723,16 @@ __device__ __forceinline__ void jp_xpull_items(const Params& P, WaveLds& W, int 
   }
 }
 
-// Level 0 of round r as global lists: its L0 vertices split into F and H.
+// Level 0 of round r as global lists: the vertices of its slot-indexed L0
+// split into F and H.
 __device__ __forceinline__ void jp_split_items(const Params& P, JpStage& st, int r, long long gw, long long gstride) {
-  const long long b = seg_begin(P, r), sz = P.l0n[r];
+  const long long b = seg_begin(P, r), sz = seg_size(P, r);
   const unsigned lane = lane_id();
   for (long long g = gw; g * WAVE < sz; g += gstride) {
     const long long i = g * WAVE + lane;
     const bool ok = i < sz;
-    int v = ok ? (int)P.L0[b + i] : 0;
-    const bool good = ok && vid_ok(P, v);
+    int v = ok ? (int)P.L0[b + i] : -1;   // -1: not in the first level
+    const bool good = v >= 0 && vid_ok(P, v);
     if (!good) v = 0;
     jp_append<SC_AGENT>(P, st, -1, good, v, good ? rec_pair(P, v) : JpRec{0, 0});
   }
@@ -2234,6 +2244,17 @@ __device__ __forceinline__ void narrow_load_fan(const Params& P, NarrowLds& Z, i
   for (unsigned i = threadIdx.x; i < n; i += NARROW_BS)
     narrow_put(P, Z, cur, at + i, (int)(unsigned)ld64<SC_AGENT>(&src[i]));
 }
+// Block-wide: the first level of a round of n <= NARROW_MAX vertices, from
+// the round's slot-indexed L0 (src), into LDS list `cur` (Z.cnt[cur] set; the
+// order inside a level does not matter).
+__device__ __forceinline__ void narrow_load_l0(const Params& P, NarrowLds& Z, int cur, const unsigned* src, unsigned n) {
+  static_assert(NARROW_MAX <= NARROW_BS, "a thread per slot entry");
+  if (threadIdx.x == 0) Z.cnt[cur] = 0;
+  __syncthreads();
+  const int v = threadIdx.x < n ? (int)ld32<SC_AGENT>(&src[threadIdx.x]) : -1;
+  if (v >= 0) narrow_put(P, Z, cur, atomicAdd(&Z.cnt[cur], 1u), v);
+  __syncthreads();
+}
 
 // Block-wide exclusive scans of two per-thread values (thread t: entry t).
 __device__ void narrow_scan2(NarrowLds& Z, unsigned a0, unsigned a1, unsigned nv) {
@@ -2379,169 +2400,10 @@ __device__ __forceinline__ bool narrow_level(const Params& P, NarrowLds& Z, JpSt
   return true;
 }
 
-// One block.  Finishes the state change of what the grid kernel has just
-// done, then runs every step one block can take (the later-round colours of
-// a small round, levels that fit) with the level lists in LDS, until JP ends
-// or a step needs the grid.
-__global__ __launch_bounds__(NARROW_BS) void k_jp_narrow(Params P, int max_steps) {
-  Ctrl* c = P.ctrl;
-  __shared__ JpState S;
-  __shared__ NarrowLds Z;
-  __shared__ int have;   // the current level is in LDS list `cur`
-  if (threadIdx.x == 0) {
-    S = c->js;
-    have = 0;
-    if (c->error) S.done = 1;   // raised by an earlier step: JP stops
-    // launches alternate (single-block, grid): the op posted by the previous
-    // single-block launch has been run by the grid launch between them
-    if (!S.done) {
-      const int op = c->grid_op;
-      c->grid_op = OP_NONE;
-      if (op == OP_XPULL) S.xpull = 0;
-      else if (op == OP_SPLIT) S.split = 0;
-      else if (op == OP_LEVEL) jp_next_level(S);
-    }
-  }
-  __syncthreads();
-  JpStage st{nullptr, nullptr, S.fcnt, S.hctr, S.psum, S.ssum, nullptr};
-  WaveLds& W = Z.wl[threadIdx.x / WAVE];
-  int cur = 0;
-  int handed = OP_NONE;
-  int checked = 0;          // the round whose sizes have been checked
-  bool in_global = false;   // the LDS level is also in the global lists
-  for (int step = 0; step < max_steps; ++step) {
-    if (S.done) break;
-    const int r = S.round;
-    const int l = S.level;
-    if (r != checked || !level_ok(P, S.fcnt[l % 3], (unsigned)S.hctr[l % 3])) {
-      // a round's sizes are checked once, when it starts
-      const bool ok = level_ok(P, S.fcnt[l % 3], (unsigned)S.hctr[l % 3]) && round_ok(P, r);
-      __syncthreads();
-      if (!ok) {
-        if (threadIdx.x == 0) S.done = 1;   // a broken state: stop (the error is raised)
-        __syncthreads();
-        break;
-      }
-      checked = r;
-    }
-    if (S.xpull) {
-      if (seg_size(P, r) > (long long)NARROW_XPULL) {
-        handed = OP_XPULL;
-        break;
-      }
-      jp_xpull_items<SC_AGENT>(P, W, r, threadIdx.x / WAVE, NARROW_BS / WAVE);
-      order_point();
-      __syncthreads();
-      if (threadIdx.x == 0) S.xpull = 0;
-      __syncthreads();
-      continue;
-    }
-    if (!have) {
-      if (S.split) {
-        // the round's first level, from L0
-        const unsigned n0 = P.l0n[r];
-        if (n0 > (unsigned)NARROW_MAX) {
-          handed = OP_SPLIT;
-          break;
-        }
-        narrow_load(P, Z, cur, P.L0 + seg_begin(P, r), n0);
-        in_global = false;
-        if (threadIdx.x == 0) {
-          Z.cnt[cur] = n0;
-          S.split = 0;
-          S.F += n0;
-        }
-      } else {
-        const unsigned nf = S.fcnt[l % 3], nh = (unsigned)S.hctr[l % 3];
-        if (nf + nh == 0) {  // round finished
-          __syncthreads();
-          if (threadIdx.x == 0) jp_begin_round(S, r - 1);
-          __syncthreads();
-          continue;
-        }
-        if (!jp_fits_narrow(nf + nh, S.psum[l % 3], S.ssum[l % 3])) {
-          handed = OP_LEVEL;
-          break;
-        }
-        narrow_load(P, Z, cur, P.F[l & 1], nf);
-        narrow_load_fan(P, Z, cur, P.H[l & 1], nh, nf);
-        in_global = true;
-        if (threadIdx.x == 0) Z.cnt[cur] = nf + nh;
-      }
-      if (threadIdx.x == 0) have = 1;
-      __syncthreads();
-    }
-    // process level l from LDS list `cur`
-    const int nx = cur ^ 1;
-    if (threadIdx.x == 0) Z.cnt[nx] = 0;
-    __syncthreads();
-    if (Z.cnt[cur] == 0) {  // nothing ready: the round is finished
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        jp_begin_round(S, r - 1);
-        have = 0;
-      }
-      __syncthreads();
-      continue;
-    }
-    if (!narrow_level(P, Z, st, cur, nx, l)) {
-      // too much work for one block: the level goes to the grid
-      if (!in_global) {
-        narrow_flush(P, Z, st, cur, l);
-        order_point();
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        S.psum[l % 3] = Z.woff[Z.cnt[cur]];
-        S.ssum[l % 3] = Z.soff[Z.cnt[cur]];
-        have = 0;
-      }
-      handed = OP_LEVEL;
-      break;
-    }
-    const unsigned nn = Z.cnt[nx];
-    const bool wide = nn > (unsigned)NARROW_MAX;
-    if (wide) {
-      // the next level goes to the grid: its overflow entries are already in
-      // the global lists; add the LDS ones
-      narrow_flush(P, Z, st, nx, l + 1);
-      order_point();
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      jp_next_level(S);
-      if (nn == 0) {
-        jp_begin_round(S, r - 1);
-        have = 0;
-      } else if (wide) {
-        have = 0;
-      }
-    }
-    __syncthreads();
-    cur = nx;
-    in_global = false;
-    if (wide) {
-      handed = OP_LEVEL;
-      break;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (have) {  // step bound reached with a level still in LDS: a broken state
-      atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
-      S.done = 1;
-    }
-    c->js = S;
-    c->grid_op = handed;
-    order_point();
-  }
-}
-
 // ---- JP steps of one launch: a leader block and helper blocks
 //
-// k_jp_steps replaces a launch of the single-block kernel.  Its first block
-// to start leads: it runs the JP state machine and every narrow step itself,
-// exactly as k_jp_narrow does (lists in LDS).  The other blocks that start in
+// Its first block to start leads: it runs the JP state machine and every
+// narrow step itself, with the level lists in LDS.  The other blocks that start in
 // time help: they wait for the leader's commands and take their share of
 // steps too wide for one block but far too narrow for a grid launch of their
 // own -- mid-sized levels, later-round colour pulls and first-level splits of
@@ -2734,9 +2596,12 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_steps(Params P, int max_steps)
     if (!S.done) {
       const int op = c->grid_op;
       c->grid_op = OP_NONE;
-      if (op == OP_XPULL) S.xpull = 0;
-      else if (op == OP_SPLIT) S.split = 0;
-      else if (op == OP_LEVEL) {
+      if (op == OP_XPULL) {
+        S.xpull = 0;
+      } else if (op == OP_SPLIT) {
+        S.split = 0;
+        S.F += S.fcnt[0] + (unsigned)S.hctr[0];
+      } else if (op == OP_LEVEL) {
         S.rv += S.fcnt[S.level % 3] + (unsigned)S.hctr[S.level % 3];
         jp_next_level(S);
       } else if (op == OP_RELAX) {
@@ -2860,12 +2725,12 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_steps(Params P, int max_steps)
     if (!have) {
       if (S.split) {
         // the round's first level, from L0
-        const unsigned n0 = P.l0n[r];
-        if (n0 > MID_MAX_SPLIT) {
+        const long long rs = seg_size(P, r);
+        if (rs > (long long)MID_MAX_SPLIT) {
           handed = OP_SPLIT;
           break;
         }
-        if (n0 > (unsigned)NARROW_MAX) {
+        if (rs > (long long)NARROW_MAX) {
           // split into the global lists of level 0 by all participants
           if (threadIdx.x == 0) {
             st32<SC_AGENT>(&c->js.fcnt[0], 0u);
@@ -2881,17 +2746,16 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_steps(Params P, int max_steps)
             S.psum[0] = ld64<SC_AGENT>(&c->js.psum[0]);
             S.ssum[0] = ld64<SC_AGENT>(&c->js.ssum[0]);
             S.split = 0;
-            S.F += n0;
+            S.F += S.fcnt[0] + (unsigned)S.hctr[0];
           }
           __syncthreads();
           continue;
         }
-        narrow_load(P, Z, cur, P.L0 + seg_begin(P, r), n0);
+        narrow_load_l0(P, Z, cur, P.L0 + seg_begin(P, r), (unsigned)rs);
         in_global = false;
         if (threadIdx.x == 0) {
-          Z.cnt[cur] = n0;
           S.split = 0;
-          S.F += n0;
+          S.F += Z.cnt[cur];
         }
       } else {
         const unsigned nf = S.fcnt[l % 3], nh = (unsigned)S.hctr[l % 3];
@@ -3033,7 +2897,7 @@ __global__ __launch_bounds__(BS) void k_jp_grid(Params P) {
       }
       items = t == 0 ? (seg_size(P, r) + WAVE - 1) / WAVE : (long long)nl;
     } else if (op == OP_SPLIT) {
-      items = ((long long)P.l0n[r] + WAVE - 1) / WAVE;
+      items = (seg_size(P, r) + WAVE - 1) / WAVE;
     } else {
       if (!level_ok(P, c->js.fcnt[l % 3], (unsigned)c->js.hctr[l % 3])) return;
       items = ((long long)c->js.fcnt[l % 3] + WAVE - 1) / WAVE + (long long)(c->js.hctr[l % 3] >> 32);
@@ -3060,7 +2924,6 @@ __global__ __launch_bounds__(BS) void k_jp_grid(Params P) {
   } else if (op == OP_SPLIT) {
     jp_split_items(P, st, r, gw, gstride);
     jp_stage_flush<SC_AGENT>(P, st, -1);
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&c->js.F, (unsigned long long)P.l0n[r]);
   } else if (op == OP_RELAX) {
     const int t = c->js.rit;
     // the fan-out staging area is free: it holds the wavefronts' bits of
@@ -3450,7 +3313,7 @@ namespace {
 
 struct Layout {
   size_t ctrl, bcount, boff, bsum, xpart, D, status, UL0, UL1, ORD, roundN, round, dag, xpred, nsr, cnt, rec, B,
-      bm_cap, L0, l0n, F0, F1, H0, H1, hub_cap, HL, HC, huge_cap, mhist, pool, pool_chunk, total;
+      bm_cap, L0, F0, F1, H0, H1, hub_cap, HL, HC, huge_cap, mhist, pool, pool_chunk, total;
 };
 
 constexpr int UPD_BLOCKS = 2048;
@@ -3529,7 +3392,6 @@ Layout make_layout(int64_t n, int64_t nnz) {
   bm_capacity(n, nnz, &L.bm_cap, &L.pool_chunk);
   L.B = take(4 * L.bm_cap);
   L.L0 = take(4 * nn);
-  L.l0n = take(4 * (nn + 4));
   L.F0 = take(4 * nn);
   L.F1 = take(4 * nn);
   // fan-out entries: vertices with more than JP_SMALL same-round successors
@@ -3631,7 +3493,6 @@ Params make_params(const adg_csr_t* g, void* ws, uint64_t p, uint64_t q, uint64_
   P.pool = (unsigned long long*)(base + L.pool);
   P.pool_chunk = (unsigned)L.pool_chunk;
   P.L0 = (unsigned*)(base + L.L0);
-  P.l0n = (unsigned*)(base + L.l0n);
   P.F[0] = (unsigned*)(base + L.F0);
   P.F[1] = (unsigned*)(base + L.F1);
   P.H[0] = (unsigned long long*)(base + L.H0);
@@ -3808,11 +3669,7 @@ int run_jp(Params& P, hipStream_t s, int rounds) {
       for (int k = 0; k < chunk; ++k) {
         {
           TIMED(KC_JP_NARROW, s);
-#if ADG_JP_STEPS
           hipLaunchKernelGGL(k_jp_steps, dim3(STEP_BLOCKS), dim3(NARROW_BS), 0, s, P, max_steps);
-#else
-          hipLaunchKernelGGL(k_jp_narrow, dim3(1), dim3(NARROW_BS), 0, s, P, max_steps);
-#endif
         }
         {
           TIMED(KC_JP, s);
