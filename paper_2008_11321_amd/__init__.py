@@ -48,7 +48,7 @@ class _Profile(ctypes.Structure):
 
 KERNEL_CLASSES = ["init", "stats", "count", "scan", "scatter", "update", "part1", "jp_prep", "jp", "finish",
                   "batched", "jp_narrow", "update_huge", "median_select", "order_sort", "dec_itr", "update_pull",
-                  "jp_phase", "dec_phase", "adg_phase"]
+                  "jp_phase", "dec_phase", "adg_phase", "update_sub"]
 
 # ADG variants (bit set): ADG-O's sorted rounds and ADG-M's median selection
 SORTED = 1

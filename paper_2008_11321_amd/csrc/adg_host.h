@@ -13,7 +13,7 @@ namespace adg {
 enum KClass {
   KC_INIT, KC_STATS, KC_COUNT, KC_SCAN, KC_SCATTER, KC_UPDATE, KC_PART1, KC_JP_PREP, KC_JP, KC_FINISH,
   KC_BATCH, KC_JP_NARROW, KC_UPDATE_HUGE, KC_MSEL, KC_ORDER, KC_DEC, KC_UPDATE_PULL, KC_JP_PHASE, KC_DEC_PHASE,
-  KC_ADG_PHASE, KC_NUM
+  KC_ADG_PHASE, KC_UPDATE_SUB, KC_NUM
 };
 
 // Event pair around one launch of class `cls` (or around a loop of

@@ -84,6 +84,17 @@ constexpr bool JP_RELAX = ADG_JP_RELAX;
 #define ADG_UPD_UNROLL 4
 #endif
 constexpr int UPD_UNROLL = ADG_UPD_UNROLL;   // 64-entry chunks of rows UPDATE reads at a time
+#ifndef ADG_SUB_BINNED
+#define ADG_SUB_BINNED 1
+#endif
+constexpr int SUB_SHIFT = 14;                   // D decrements by bins of 2^14 target vertices
+constexpr int SUB_SPAN = 1 << SUB_SHIFT;
+constexpr int SUB_MAX_BINS = 8192;              // (graphs up to 2^27 vertices; larger ones decrement at once)
+constexpr int SUB_BLOCKS = 256;                 // blocks of the count and scatter passes
+constexpr int SUB_BS = 1024;                    // their threads
+constexpr int SUB_CHUNK = 32768;                // targets an apply block takes at a time
+constexpr int SUB_APPLY_BLOCKS = 1024;
+constexpr int64_t SUB_MIN_NNZ = 1 << 22;        // smaller graphs decrement at once (the passes cost more than they save)
 #ifndef ADG_SMALL_DEG
 #define ADG_SMALL_DEG 32
 #endif
@@ -225,6 +236,10 @@ struct Ctrl {
   unsigned long long pjoin;
   // relaxation step the steps launch's participants run: round, step, list size, stamp
   unsigned rx[4];
+  // binned decrements of the current round: the targets overflow SB (then the
+  // scatter pass decrements at once), the apply chunks
+  int sub_direct;
+  unsigned sub_chunks;
 };
 
 struct Params {
@@ -242,6 +257,11 @@ struct Params {
   int dec;                     // DEC-ADG-ITR colours the partitions (bitmaps for all same-round neighbours)
   int pull;                    // UPDATE pulls: survivors lower their own D (k_update_pull)
   int relax_mode;              // RELAX_MODE_*: which rounds JP relaxes
+  int binned;                  // UPDATE's decrements of D go through target bins (k_sub_*), not one atomic each
+  unsigned* SB;                // the round's cut-edge targets ordered by bin
+  unsigned sb_cap;             // entries of SB
+  unsigned* SUBC;              // [SUB_BLOCKS][bins] targets per block and bin (then their offsets in the bin)
+  unsigned* SUBS;              // [bins + 1] first entry of each bin in SB, then [bins + 1] apply chunks before each bin
   unsigned* tent;              // DEC-ADG-ITR: colour each vertex tried in its latest iteration
   unsigned* mhist;             // [MSEL_BINS] radix selection histogram
   Ctrl* ctrl;
@@ -730,28 +750,16 @@ __device__ __forceinline__ unsigned long long same_key(const Params& P, int v) {
   return P.sorted ? ((unsigned long long)(unsigned)P.D[v] << 32) | h : h;
 }
 
-template <bool FUSED>
-__device__ __forceinline__ int visit3(const Params& P, int w, int l, unsigned char code, unsigned long long hv,
-                                      unsigned& x, bool decrement) {
-  unsigned char st = P.status[w];
-  if (st == 0) {
-    if (decrement) {
-      atomicSub(&P.D[w], 1);
-      x += 1;
-    }
-    return NB_PRED;
-  }
-  if (FUSED && st == code && P.round[w] == l)
-    return same_key(P, w) > hv ? NB_PRED_SAME : NB_SUCC_SAME;
-  return NB_SUCC_EARLIER;
-}
-
-// visit3 for UPD_UNROLL entries at once (ok[u]: entry u exists): the status
-// gathers first, then the round gathers of same-round candidates, then the
-// decisions, so that each kind of gather is in flight for all entries together.
+// Classify UPD_UNROLL neighbours w[u] (ok[u]: entry u exists) of a vertex of
+// R_l (same-round key hv[u]): NB_PRED for a neighbour still in U (a cut edge:
+// counted in x when `count`, and D[w] decremented at once when `decrement`;
+// otherwise the binned decrements below do it), same-round predecessor or
+// successor, or earlier-round successor.  The status gathers go first, then
+// the round gathers of same-round candidates, then the decisions, so that
+// each kind of gather is in flight for all entries together.
 template <bool FUSED>
 __device__ __forceinline__ void visit_n(const Params& P, const int* w, const bool* ok, int l, unsigned char code,
-                                        const unsigned long long* hv, unsigned& x, bool decrement, int* cl) {
+                                        const unsigned long long* hv, unsigned& x, bool count, bool decrement, int* cl) {
   unsigned char st[UPD_UNROLL];
 #pragma unroll
   for (int u = 0; u < UPD_UNROLL; ++u) st[u] = ok[u] ? P.status[w[u]] : 0;
@@ -763,8 +771,8 @@ __device__ __forceinline__ void visit_n(const Params& P, const int* w, const boo
     if (!ok[u]) {
       cl[u] = NB_NONE;
     } else if (st[u] == 0) {
-      if (decrement) {
-        atomicSub(&P.D[w[u]], 1);
+      if (count) {
+        if (decrement) atomicSub(&P.D[w[u]], 1);
         x += 1;
       }
       cl[u] = NB_PRED;
@@ -950,7 +958,7 @@ __device__ void update_small(const Params& P, BmPool* pl, SmallRows& S, int v, b
       w[u] = ok[u] ? P.col[S.b[k[u]] + (pos - S.off[k[u]])] : 0;
       hv[u] = S.hv[k[u]];
     }
-    visit_n<FUSED>(P, w, ok, l, code, hv, x, !P.pull, cl);
+    visit_n<FUSED>(P, w, ok, l, code, hv, x, !P.pull, !P.pull && !P.binned, cl);
     if (FUSED) {
 #pragma unroll
       for (int u = 0; u < UPD_UNROLL; ++u)
@@ -1040,7 +1048,7 @@ __device__ void update_big(const Params& P, BmPool* pl, RowMasks& rm, int v, int
       w[u] = ok[u] ? P.col[j] : 0;
       hvs[u] = hv;
     }
-    visit_n<FUSED>(P, w, ok, l, code, hvs, x, !P.pull, cl);
+    visit_n<FUSED>(P, w, ok, l, code, hvs, x, !P.pull, !P.pull && !P.binned, cl);
     if (FUSED) {
 #pragma unroll
       for (int u = 0; u < UPD_UNROLL; ++u) {
@@ -1237,7 +1245,7 @@ __global__ __launch_bounds__(BS) void k_update_huge_count(Params P, int l) {
         w[u] = ok[u] ? P.col[j] : 0;
         hvs[u] = hv;
       }
-      visit_n<FUSED>(P, w, ok, l, code, hvs, x, !P.pull, cl);
+      visit_n<FUSED>(P, w, ok, l, code, hvs, x, !P.pull, !P.pull && !P.binned, cl);
 #pragma unroll
       for (int u = 0; u < UPD_UNROLL; ++u) {
         cnt[NB_PRED] += __popcll(ballot(cl[u] == NB_PRED));
@@ -1289,7 +1297,7 @@ __global__ __launch_bounds__(BS) void k_update_huge_place(Params P, int l) {
         w[u] = ok[u] ? P.col[j] : 0;
         hvs[u] = hv;
       }
-      visit_n<true>(P, w, ok, l, code, hvs, x, false, cl);
+      visit_n<true>(P, w, ok, l, code, hvs, x, false, false, cl);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         if (q == NB_SUCC_EARLIER) continue;   // never read back
@@ -1633,6 +1641,262 @@ __device__ __forceinline__ int wave_colour(const Params& P, WaveLds& W, bool act
   }
   wave_sync();
   return col;
+}
+
+// ---- D decrements by bins
+//
+// Each cut edge (v removed in round l, w still in U) takes one off D[w].  As
+// one device atomic each, these decrements bound UPDATE: about 10^9 a second
+// on targets spread over the graph, while a round of R-MAT's has 10^8 or more
+// of them, concentrated on far fewer targets (hundreds per target on average
+// in the middle rounds, but too spread for a small table of hot targets to
+// catch most).  So UPDATE only counts them, and after it the targets -- the
+// later-round predecessors that UPDATE wrote at the front of each row of R_l
+// (xpred[v] of them) -- go through bins of SUB_SPAN vertices: a count pass
+// (block histograms in LDS), a scan (offsets per bin and block), a scatter
+// pass into SB in bin order, and an apply pass that sums each bin's targets
+// in LDS and subtracts the sums from D, one atomic per target and chunk.
+
+// The targets of round l as block blockIdx.x of SUB_BLOCKS walks them: its
+// contiguous share of R_l's rows up to HUGE_DEG entries (a wavefront takes 64
+// rows and spreads their targets over its lanes), then every SUB_BLOCKS-th
+// chunk of HUGE_CHUNK targets of the longer rows (the hubs), the whole block
+// on each.  Both passes walk the same targets in each block.  SCATTER = false:
+// count them per bin in lds; true: write each to SB at the bin cursor in lds
+// (or, with `direct`, decrement D at once).
+template <bool SCATTER>
+__device__ __forceinline__ void sub_walk(const Params& P, WaveLds& W, unsigned* lds, bool direct) {
+  Ctrl* c = P.ctrl;
+  const long long nR = (long long)c->nRs + c->nRb;
+  const int* RL = round_slot(P, c->N);
+  const long long lo = nR * blockIdx.x / gridDim.x, hi = nR * (blockIdx.x + 1) / gridDim.x;
+  const unsigned lane = lane_id();
+  const int nw = blockDim.x / WAVE;
+  for (long long g0 = lo + (long long)(threadIdx.x / WAVE) * WAVE; g0 < hi; g0 += (long long)nw * WAVE) {
+    const long long i = g0 + lane;
+    int k = 0;
+    long long b = 0;
+    if (i < hi) {
+      const int v = RL[i];
+      if (vid_ok(P, v)) {
+        const long long e = P.rp[v + 1];
+        b = P.rp[v];
+        if (e - b <= HUGE_DEG) {
+          k = P.xpred[v];
+          if (k < 0 || k > e - b) {
+            raise_internal(P);
+            k = 0;
+          }
+        }
+      }
+    }
+    int tot;
+    W.off[lane] = wave_excl_scan<int>(k, &tot);
+    W.pb[lane] = b;
+    if (lane == 0) W.off[WAVE] = tot;
+    wave_sync();
+    for (int e0 = 0; e0 < tot; e0 += WAVE * UPD_UNROLL) {
+      int w[UPD_UNROLL];
+#pragma unroll
+      for (int u = 0; u < UPD_UNROLL; ++u) {
+        const int e = e0 + u * WAVE + (int)lane;
+        w[u] = -1;
+        if (e < tot) {
+          const int own = wave_owner(W, e);
+          w[u] = P.dag[W.pb[own] + (e - W.off[own])];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UPD_UNROLL; ++u)
+        if (w[u] >= 0 && vid_ok(P, w[u])) {
+          if (!SCATTER) atomicAdd(&lds[w[u] >> SUB_SHIFT], 1u);
+          else if (direct) atomicSub(&P.D[w[u]], 1);
+          else P.SB[atomicAdd(&lds[w[u] >> SUB_SHIFT], 1u)] = (unsigned)w[u];
+        }
+    }
+    wave_sync();   // W is rewritten by the wavefront's next rows
+  }
+  const unsigned long long hc = c->huge_ctr;
+  const unsigned nh = (unsigned)hc < P.huge_cap ? (unsigned)hc : P.huge_cap, nch = (unsigned)(hc >> 32);
+  if (nh == 0) return;
+  for (long long kk = blockIdx.x; kk < nch; kk += gridDim.x) {
+    unsigned h;
+    const unsigned first = huge_entry(P, nh, (unsigned)kk, &h);
+    const int v = (int)(unsigned)P.HL[h];
+    if (!vid_ok(P, v) || first > kk) continue;
+    const long long b = P.rp[v], e = P.rp[v + 1];
+    long long k = P.xpred[v];
+    if (k < 0 || k > e - b) {
+      raise_internal(P);
+      k = 0;
+    }
+    const long long c0 = ((long long)kk - first) * HUGE_CHUNK;
+    const long long c1 = c0 + HUGE_CHUNK < k ? c0 + HUGE_CHUNK : k;
+    for (long long j = c0 + threadIdx.x; j < c1; j += blockDim.x) {
+      const int w = P.dag[b + j];
+      if (!vid_ok(P, w)) continue;
+      if (!SCATTER) atomicAdd(&lds[w >> SUB_SHIFT], 1u);
+      else if (direct) atomicSub(&P.D[w], 1);
+      else P.SB[atomicAdd(&lds[w >> SUB_SHIFT], 1u)] = (unsigned)w;
+    }
+  }
+}
+
+__device__ __forceinline__ int sub_bins(const Params& P) { return (P.n + SUB_SPAN - 1) >> SUB_SHIFT; }
+
+// Count pass: targets per bin of this block, to SUBC[block][bin].
+__global__ __launch_bounds__(SUB_BS) void k_sub_count(Params P) {
+  if (P.ctrl->done) return;
+  __shared__ unsigned hist[SUB_MAX_BINS];
+  __shared__ WaveLds wl[SUB_BS / WAVE];
+  const int nb = sub_bins(P);
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) hist[k] = 0;
+  __syncthreads();
+  sub_walk<false>(P, wl[threadIdx.x / WAVE], hist, false);
+  __syncthreads();
+  unsigned* out = P.SUBC + (size_t)blockIdx.x * nb;
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) out[k] = hist[k];
+}
+
+// Scan, first step: per bin (a thread each), each block's offset inside the
+// bin, in place in SUBC, and the bin's total to SUBS[bin] (saturated at
+// 2^32 - 1: the totals fit SB, whose size is below 2^32, or the targets are
+// decremented at once).
+__global__ __launch_bounds__(BS) void k_sub_scan_bins(Params P) {
+  if (P.ctrl->done) return;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nb = sub_bins(P);
+  if (k >= nb) return;
+  constexpr int Q = 16;   // loads in flight
+  unsigned long long t = 0;
+  for (int b0 = 0; b0 < SUB_BLOCKS; b0 += Q) {
+    unsigned x[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) x[q] = P.SUBC[(size_t)(b0 + q) * nb + k];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      P.SUBC[(size_t)(b0 + q) * nb + k] = (unsigned)t;
+      t += x[q];
+    }
+  }
+  P.SUBS[k] = t > 0xffffffffull ? 0xffffffffu : (unsigned)t;
+}
+
+// Exclusive scan of one value per thread of a SUB_BS-thread block (v in
+// LDS, replaced by its prefix; the total returned to every thread).
+__device__ __forceinline__ unsigned long long sub_block_scan(unsigned long long* v) {
+  __shared__ unsigned long long wt[SUB_BS / WAVE];
+  const unsigned lane = lane_id(), w = threadIdx.x / WAVE;
+  if (lane == 0) {
+    unsigned long long a = 0;
+    for (int i = 0; i < WAVE; ++i) {
+      const unsigned long long x = v[w * WAVE + i];
+      v[w * WAVE + i] = a;
+      a += x;
+    }
+    wt[w] = a;
+  }
+  __syncthreads();
+  unsigned long long before = 0, all = 0;
+  for (int k = 0; k < SUB_BS / WAVE; ++k) {
+    before += k < (int)w ? wt[k] : 0ull;
+    all += wt[k];
+  }
+  v[threadIdx.x] += before;
+  __syncthreads();
+  return all;
+}
+
+// Scan, second step (one block): each bin's first entry in SUBS, the apply
+// chunks of the bins as a prefix after them, and whether the targets fit SB.
+__global__ __launch_bounds__(SUB_BS) void k_sub_scan_total(Params P) {
+  Ctrl* c = P.ctrl;
+  if (c->done) return;
+  __shared__ unsigned long long part[SUB_BS], cpart[SUB_BS];
+  constexpr int PER = SUB_MAX_BINS / SUB_BS;   // bins per thread
+  const int nb = sub_bins(P);
+  unsigned long long tot[PER], chk[PER], mine = 0, mch = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int k = threadIdx.x * PER + q;
+    tot[q] = k < nb ? P.SUBS[k] : 0ull;
+    chk[q] = (tot[q] + SUB_CHUNK - 1) / SUB_CHUNK;
+    mine += tot[q];
+    mch += chk[q];
+  }
+  part[threadIdx.x] = mine;
+  cpart[threadIdx.x] = mch;
+  __syncthreads();
+  const unsigned long long all = sub_block_scan(part);
+  const unsigned long long chunks = sub_block_scan(cpart);
+  const bool fit = all <= (unsigned long long)P.sb_cap;
+  unsigned long long at = part[threadIdx.x], ct = cpart[threadIdx.x];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int k = threadIdx.x * PER + q;
+    if (k < nb) {
+      P.SUBS[k] = (unsigned)at;
+      P.SUBS[nb + 1 + k] = (unsigned)ct;
+    }
+    at += tot[q];
+    ct += chk[q];
+  }
+  if (threadIdx.x == 0) {
+    P.SUBS[nb] = (unsigned)all;
+    P.SUBS[nb + 1 + nb] = (unsigned)chunks;
+    c->sub_direct = fit ? 0 : 1;
+    c->sub_chunks = fit ? (unsigned)chunks : 0u;
+  }
+}
+
+// Scatter pass: every target to SB at its bin's cursor for this block.
+__global__ __launch_bounds__(SUB_BS) void k_sub_scatter(Params P) {
+  Ctrl* c = P.ctrl;
+  if (c->done) return;
+  __shared__ unsigned cur[SUB_MAX_BINS];
+  __shared__ WaveLds wl[SUB_BS / WAVE];
+  const int nb = sub_bins(P);
+  const bool direct = c->sub_direct != 0;
+  const unsigned* off = P.SUBC + (size_t)blockIdx.x * nb;
+  if (!direct)
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) cur[k] = P.SUBS[k] + off[k];
+  __syncthreads();
+  sub_walk<true>(P, wl[threadIdx.x / WAVE], cur, direct);
+}
+
+// Apply pass: chunk j of the bins' targets (chunks never span two bins)
+// summed per target in LDS, the sums taken off D.
+__global__ __launch_bounds__(SUB_BS) void k_sub_apply(Params P) {
+  Ctrl* c = P.ctrl;
+  if (c->done || c->sub_direct) return;
+  __shared__ unsigned cnt[SUB_SPAN];
+  const unsigned nch = c->sub_chunks;
+  const int nb = sub_bins(P);
+  const unsigned* cpre = P.SUBS + nb + 1;
+  for (unsigned j = blockIdx.x; j < nch; j += gridDim.x) {
+    // its bin: the last k with cpre[k] <= j
+    int lo = 0, hi = nb;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (cpre[mid] <= j) lo = mid;
+      else hi = mid;
+    }
+    const unsigned long long b0 = P.SUBS[lo] + (unsigned long long)(j - cpre[lo]) * SUB_CHUNK;
+    const unsigned long long bend = P.SUBS[lo + 1];
+    const unsigned long long b1 = b0 + SUB_CHUNK < bend ? b0 + SUB_CHUNK : bend;
+    for (int i = threadIdx.x; i < SUB_SPAN; i += blockDim.x) cnt[i] = 0;
+    __syncthreads();
+    const unsigned base = (unsigned)lo << SUB_SHIFT;
+    for (unsigned long long i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+      const unsigned w = P.SB[i];
+      if (w - base < (unsigned)SUB_SPAN) atomicAdd(&cnt[w - base], 1u);
+      else raise_internal(P);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < SUB_SPAN; i += blockDim.x)
+      if (cnt[i]) atomicSub(&P.D[base + i], (int)cnt[i]);
+    __syncthreads();   // cnt is cleared for the next chunk
+  }
 }
 
 // ---- grid-wide steps
@@ -3256,7 +3520,7 @@ namespace {
 const char* kclass_names[KC_NUM] = {"init", "stats", "count", "scan", "scatter", "update", "part1",
                                     "jp_prep", "jp", "finish", "batched", "jp_narrow", "update_huge",
                                     "median_select", "order_sort", "dec_itr", "update_pull", "jp_phase",
-                                    "dec_phase", "adg_phase"};
+                                    "dec_phase", "adg_phase", "update_sub"};
 static_assert(KC_NUM <= ADG_PROFILE_CLASSES, "profile classes do not fit adg_profile_t");
 struct ProfRec {
   int cls;
@@ -3313,7 +3577,7 @@ namespace {
 
 struct Layout {
   size_t ctrl, bcount, boff, bsum, xpart, D, status, UL0, UL1, ORD, roundN, round, dag, xpred, nsr, cnt, rec, B,
-      bm_cap, L0, F0, F1, H0, H1, hub_cap, HL, HC, huge_cap, mhist, pool, pool_chunk, total;
+      bm_cap, L0, F0, F1, H0, H1, hub_cap, sb_cap, SUBC, SUBS, HL, HC, huge_cap, mhist, pool, pool_chunk, total;
 };
 
 constexpr int UPD_BLOCKS = 2048;
@@ -3397,8 +3661,20 @@ Layout make_layout(int64_t n, int64_t nnz) {
   // fan-out entries: vertices with more than JP_SMALL same-round successors
   // in a level, at most m / JP_SMALL of them
   L.hub_cap = (size_t)nnz / (2 * JP_SMALL) + 64;
-  L.H0 = take(8 * L.hub_cap);
-  L.H1 = take(8 * L.hub_cap);
+  // JP's fan-out lists share their memory with ADG's binned cut-edge targets
+  // (at most one per undirected edge and round: m = nnz / 2)
+  {
+    const size_t sb = (size_t)nnz / 2 + 64;
+    const size_t bytes = std::max(16 * L.hub_cap, 4 * sb);
+    L.H0 = take(bytes);
+    L.H1 = L.H0 + 8 * L.hub_cap;
+    L.sb_cap = std::min<size_t>(bytes / 4, 0xffffffffull);
+  }
+  {
+    const size_t nb = ((size_t)n + SUB_SPAN - 1) >> SUB_SHIFT;
+    L.SUBC = take(4 * (size_t)SUB_BLOCKS * nb);
+    L.SUBS = take(4 * (2 * nb + 2));
+  }
   // rows longer than HUGE_DEG in one round: at most nnz / HUGE_DEG
   L.huge_cap = (size_t)nnz / HUGE_DEG + 64;
   L.HL = take(8 * L.huge_cap);
@@ -3497,6 +3773,11 @@ Params make_params(const adg_csr_t* g, void* ws, uint64_t p, uint64_t q, uint64_
   P.F[1] = (unsigned*)(base + L.F1);
   P.H[0] = (unsigned long long*)(base + L.H0);
   P.H[1] = (unsigned long long*)(base + L.H1);
+  P.SB = (unsigned*)(base + L.H0);
+  P.sb_cap = (unsigned)L.sb_cap;
+  P.SUBC = (unsigned*)(base + L.SUBC);
+  P.SUBS = (unsigned*)(base + L.SUBS);
+  P.binned = ADG_SUB_BINNED && !P.pull && g->n > 0 && g->n <= (int64_t)SUB_MAX_BINS * SUB_SPAN && g->nnz >= SUB_MIN_NNZ;
   P.hub_cap = (unsigned)L.hub_cap;
   P.HL = (unsigned long long*)(base + L.HL);
   P.HC = (unsigned*)(base + L.HC);
@@ -3595,16 +3876,18 @@ int run_adg(Params& P, hipStream_t s, bool fused, int* num_rounds_host) {
         hipLaunchKernelGGL(k_scatter, dim3(SEL_BLOCKS), dim3(BS), 0, s, P, l);
       }
       // (with pull UPDATE and no fusion, the push kernels have nothing to do)
-      if (fused || !P.pull) {
+      // the binned decrements read the rows' partition: the push kernels then partition even for ADG alone
+      const bool part = fused || P.binned;
+      if (part || !P.pull) {
         TIMED(KC_UPDATE, s);
-        if (fused)
+        if (part)
           hipLaunchKernelGGL(k_update<true>, dim3(P.upd_blocks), dim3(BS), 0, s, P, l);
         else
           hipLaunchKernelGGL(k_update<false>, dim3(P.upd_blocks), dim3(BS), 0, s, P, l);
       }
-      if (fused || !P.pull) {
+      if (part || !P.pull) {
         TIMED(KC_UPDATE_HUGE, s);
-        if (fused) {
+        if (part) {
           hipLaunchKernelGGL(k_update_huge_count<true>, dim3(HUGE_BLOCKS), dim3(BS), 0, s, P, l);
           hipLaunchKernelGGL(k_update_huge_place, dim3(HUGE_BLOCKS), dim3(BS), 0, s, P, l);
         } else {
@@ -3614,6 +3897,15 @@ int run_adg(Params& P, hipStream_t s, bool fused, int* num_rounds_host) {
       if (P.pull) {
         TIMED(KC_UPDATE_PULL, s);
         hipLaunchKernelGGL(k_update_pull, dim3(P.upd_blocks), dim3(BS), 0, s, P, l);
+      }
+      if (P.binned) {
+        TIMED(KC_UPDATE_SUB, s);
+        const int nb = (P.n + SUB_SPAN - 1) >> SUB_SHIFT;
+        hipLaunchKernelGGL(k_sub_count, dim3(SUB_BLOCKS), dim3(SUB_BS), 0, s, P);
+        hipLaunchKernelGGL(k_sub_scan_bins, dim3((nb + BS - 1) / BS), dim3(BS), 0, s, P);
+        hipLaunchKernelGGL(k_sub_scan_total, dim3(1), dim3(SUB_BS), 0, s, P);
+        hipLaunchKernelGGL(k_sub_scatter, dim3(SUB_BLOCKS), dim3(SUB_BS), 0, s, P);
+        hipLaunchKernelGGL(k_sub_apply, dim3(SUB_APPLY_BLOCKS), dim3(SUB_BS), 0, s, P);
       }
     }
     // one more stats call ends the loop on the device when U is empty
