@@ -90,8 +90,14 @@ constexpr int UPD_UNROLL = ADG_UPD_UNROLL;   // 64-entry chunks of rows UPDATE r
 constexpr int SUB_SHIFT = 14;                   // D decrements by bins of 2^14 target vertices
 constexpr int SUB_SPAN = 1 << SUB_SHIFT;
 constexpr int SUB_MAX_BINS = 8192;              // (graphs up to 2^27 vertices; larger ones decrement at once)
-constexpr int SUB_BLOCKS = 256;                 // blocks of the count and scatter passes
-constexpr int SUB_BS = 1024;                    // their threads
+#ifndef ADG_SUB_BLOCKS
+#define ADG_SUB_BLOCKS 1024
+#endif
+constexpr int SUB_BLOCKS = ADG_SUB_BLOCKS;      // blocks of the count and scatter passes
+#ifndef ADG_SUB_BS
+#define ADG_SUB_BS 1024
+#endif
+constexpr int SUB_BS = ADG_SUB_BS;              // their threads
 constexpr int SUB_CHUNK = 32768;                // targets an apply block takes at a time
 constexpr int SUB_APPLY_BLOCKS = 1024;
 constexpr int64_t SUB_MIN_NNZ = 1 << 22;        // smaller graphs decrement at once (the passes cost more than they save)
@@ -1537,6 +1543,21 @@ __device__ __forceinline__ void jp_stage_flush(const Params& P, JpStage& st, int
   __syncthreads();
 }
 
+// Block-wide, between the passes of a loop whose wavefronts append one
+// vertex per lane and pass (this wavefront has work in the pass: `any`):
+// false once no wavefront of the block has work; otherwise true, after the
+// block's staged vertices (level l + 1) have gone to the global list if
+// another pass could fill the staging buffer.  Without this, a long list
+// (a round's first level of tens of millions of vertices) would overflow the
+// buffer after a few passes, and every later wavefront would take its slots
+// with an atomic on the one global counter.
+__device__ __forceinline__ bool stage_pass(const Params& P, JpStage& st, int l, bool any) {
+  if (!st.buf) return any;
+  if (!__syncthreads_or(any)) return false;
+  if (*st.cnt + blockDim.x > (unsigned)FB_CAP) jp_stage_flush<SC_AGENT>(P, st, l);
+  return true;
+}
+
 // Mark colour c in the bitmap described by rec (if it can matter there).
 template <int S>
 __device__ __forceinline__ void bm_mark(const Params& P, unsigned long long rec, int c) {
@@ -1992,7 +2013,9 @@ __device__ __forceinline__ void jp_xpull_items(const Params& P, WaveLds& W, int 
 __device__ __forceinline__ void jp_split_items(const Params& P, JpStage& st, int r, long long gw, long long gstride) {
   const long long b = seg_begin(P, r), sz = seg_size(P, r);
   const unsigned lane = lane_id();
-  for (long long g = gw; g * WAVE < sz; g += gstride) {
+  for (long long g = gw;; g += gstride) {
+    if (!stage_pass(P, st, -1, g * WAVE < sz)) break;
+    if (g * WAVE >= sz) continue;
     const long long i = g * WAVE + lane;
     const bool ok = i < sz;
     int v = ok ? (int)P.L0[b + i] : -1;   // -1: not in the first level
@@ -2147,7 +2170,9 @@ __device__ __forceinline__ void jp_level_items(const Params& P, JpStage& st, Wav
 __device__ __forceinline__ void jp_relax_list(const Params& P, JpStage& st, int r, long long gw, long long gstride) {
   const long long b = seg_begin(P, r), sz = seg_size(P, r);
   const unsigned lane = lane_id();
-  for (long long g = gw; g * WAVE < sz; g += gstride) {
+  for (long long g = gw;; g += gstride) {
+    if (!stage_pass(P, st, 0, g * WAVE < sz)) break;
+    if (g * WAVE >= sz) continue;
     const long long i = g * WAVE + lane;
     int v = i < sz ? P.ORD[b + i] : -1;
     const bool ok = v >= 0 && vid_ok(P, v);
