@@ -333,11 +333,12 @@ def run_single(args, w):
     log("warm-up done")
     adg.profile_read()  # drop anything recorded so far
     # Kernel time, on the launch stream, during the timed steps: HIP events
-    # around every UPDATE launch, and one pair around each call's ADG round
+    # around every UPDATE launch (with its binned decrements), and one pair
+    # around each call's ADG round
     # loop and JP (or DEC-ADG-ITR) loop, counted as the launches issued in
     # it.  (An event pair around each of JP's thousands of short launches
     # would cost host time and slow the very steps being timed.)
-    adg.profile_enable(["update", "update_huge", "update_pull", "adg_phase", "jp_phase", "dec_phase"])
+    adg.profile_enable(["update", "update_huge", "update_pull", "update_sub", "adg_phase", "jp_phase", "dec_phase"])
     torch.cuda.synchronize()
     times, dt = time_steps(step, args.steps)
     adg.profile_enable([])
@@ -355,7 +356,7 @@ def run_single(args, w):
     jp_ms = (P("jp_phase")[0] + P("dec_phase")[0]) / args.steps
     jp_launches = (P("jp_phase")[1] + P("dec_phase")[1]) / args.steps
     adg_ms = P("adg_phase")[0] / args.steps
-    upd_ms = (P("update")[0] + P("update_huge")[0] + P("update_pull")[0]) / args.steps
+    upd_ms = (P("update")[0] + P("update_huge")[0] + P("update_pull")[0] + P("update_sub")[0]) / args.steps
     upd_launches = P("update")[1] / args.steps
     adg_b, jp_b = phase_bytes(n, nnz, st)
     phases = {"step": phase_record("step", adg_b + jp_b, ms_step),
