@@ -338,7 +338,8 @@ def run_single(args, w):
     # loop and JP (or DEC-ADG-ITR) loop, counted as the launches issued in
     # it.  (An event pair around each of JP's thousands of short launches
     # would cost host time and slow the very steps being timed.)
-    adg.profile_enable(["update", "update_huge", "update_pull", "update_sub", "adg_phase", "jp_phase", "dec_phase"])
+    adg.profile_enable(["update", "update_huge", "update_pull", "update_sub", "adg_phase", "jp_phase", "dec_phase",
+                        "batched"])
     torch.cuda.synchronize()
     times, dt = time_steps(step, args.steps)
     adg.profile_enable([])
@@ -364,8 +365,15 @@ def run_single(args, w):
               "jp": phase_record("jp", jp_b, jp_ms, jp_launches),
               "update": dict(phase_record("update", algorithmic_bytes("update", n, nnz, st), upd_ms,
                                           upd_launches), model="UPDATE's own traffic (see algorithmic_bytes)")}
-    # the dominant kernel class: the larger share of the step
-    if jp_ms >= adg_ms:
+    # the dominant kernel class: the larger share of the step (a graph of at
+    # most 2^17 entries and vertices runs as one launch of the one-graph engine)
+    if P("adg_phase")[1] == 0 and P("batched")[1] > 0:
+        kname = "k_batched"
+        dom_bytes = algorithmic_bytes("batched", n, nnz, st)
+        dom_ms, dom_launches = P("batched")[0] / args.steps, P("batched")[1] / args.steps
+        phases = {"step": phase_record("step", adg_b + jp_b, ms_step),
+                  "one_launch": phase_record("one_launch", dom_bytes, dom_ms, dom_launches)}
+    elif jp_ms >= adg_ms:
         kname = "k_dec_pull+k_dec_pick+k_dec_resolve" if variant & 4 else "k_jp_steps+k_jp_grid"
         dom_bytes, dom_ms, dom_launches = jp_b, jp_ms, jp_launches
     else:

@@ -52,7 +52,10 @@ constexpr int SMALL_ROW = 32;         // lane-per-vertex rows up to this length
 constexpr int SCHED_BS = 1024;        // threads of the schedule kernel
 constexpr int SCHED_BUCKETS = 64;     // work classes (floor(log2(work)))
 constexpr int WG = __HIP_MEMORY_SCOPE_WORKGROUP;
-constexpr int ONE_GRAPH_THREADS = 512;    // workgroup size when one graph is coloured alone
+#ifndef ADG_ONE_GRAPH_THREADS
+#define ADG_ONE_GRAPH_THREADS 1024
+#endif
+constexpr int ONE_GRAPH_THREADS = ADG_ONE_GRAPH_THREADS;   // workgroup size when one graph is coloured alone
 
 struct BCtrl {
   unsigned int next;              // queue head: graphs claimed so far
