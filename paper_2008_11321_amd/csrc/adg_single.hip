@@ -80,6 +80,11 @@ constexpr int SEL_BLOCKS = 2048;        // fixed grid of the selection kernels
 #define ADG_JP_RELAX 1   // deep rounds finished by relaxation
 #endif
 constexpr bool JP_RELAX = ADG_JP_RELAX;
+#ifndef ADG_JP_CORE
+#define ADG_JP_CORE 1   // small rounds whose levels colour a vertex or two: one block, in JP's order
+#endif
+constexpr bool JP_CORE = ADG_JP_CORE;
+constexpr int CORE_MAX = 4096;                  // rounds of at most this many vertices can take the core mode
 #ifndef ADG_UPD_UNROLL
 #define ADG_UPD_UNROLL 4
 #endif
@@ -2359,6 +2364,132 @@ __device__ __forceinline__ void jp_relax_items(const Params& P, JpStage& st, Wav
   }
 }
 
+// ---- the core mode of a small, dense round
+//
+// A round whose levels colour a vertex or two each (the near-cliques at the
+// top of a power-law graph's order) costs a level per vertex: the ready
+// vertex's bitmap, the push to its hundreds of successors, the next level,
+// each a dependent round trip.  Such a round of at most CORE_MAX vertices is
+// finished by one block instead: it lists the round's uncoloured vertices,
+// sorts them by JP's priority inside the round (largest first) and colours
+// them one after the other, each with the smallest colour in neither its
+// bitmap nor the colours of its same-round predecessors (read back from
+// the colour array).  Every predecessor comes earlier in that order (or was
+// coloured by a level before, and its colour is in the bitmap too), so this
+// is JP's colouring: the greedy colouring in priority order.
+struct CoreLds {
+  unsigned long long key[CORE_MAX];
+  int id[CORE_MAX];
+  unsigned bits[WAVE];           // a 2048-colour window of the current vertex
+  unsigned long long rec;        // the current vertex's JP record
+  long long p0, s0;              // its same-round predecessors: dag[p0, s0)
+  int found;                     // first clear bit of the window (block minimum)
+  unsigned cnt;                  // listed vertices
+};
+
+// JP's order inside the round (larger first): rho_R (after D at selection for
+// ADG-O); jp_color's one pseudo-round orders by <given rank, rho_R>.
+__device__ __forceinline__ unsigned long long core_key(const Params& P, int v) {
+  return P.ord_identity ? (unsigned long long)prio(P, v) : same_key(P, v);
+}
+
+// Block-wide: colour the uncoloured vertices of round r (at most CORE_MAX).
+__device__ __forceinline__ void jp_core_round(const Params& P, CoreLds& K, int r) {
+  const long long b = seg_begin(P, r), rs = seg_size(P, r);
+  const unsigned tid = threadIdx.x;
+  if (tid == 0) K.cnt = 0;
+  __syncthreads();
+  for (long long i = tid; i < rs; i += blockDim.x) {
+    const int v = P.ORD[b + i];
+    if (vid_ok(P, v) && done_colour(P, v) == 0) {
+      const unsigned at = atomicAdd(&K.cnt, 1u);
+      if (at < (unsigned)CORE_MAX) {
+        K.id[at] = v;
+        K.key[at] = core_key(P, v);
+      }
+    }
+  }
+  __syncthreads();
+  unsigned m = K.cnt;
+  if (m > (unsigned)CORE_MAX) {   // the round was checked to fit: a broken state
+    if (tid == 0) raise_internal(P);
+    m = CORE_MAX;
+  }
+  unsigned M = 1;
+  while (M < m) M <<= 1;
+  for (unsigned i = m + tid; i < M; i += blockDim.x) {
+    K.id[i] = -1;
+    K.key[i] = 0;
+  }
+  __syncthreads();
+  // bitonic sort, largest key first
+  for (unsigned k = 2; k <= M; k <<= 1)
+    for (unsigned j = k >> 1; j > 0; j >>= 1) {
+      for (unsigned i = tid; i < M; i += blockDim.x) {
+        const unsigned o = i ^ j;
+        if (o > i) {
+          const unsigned long long a = K.key[i], c = K.key[o];
+          if ((i & k) == 0 ? a < c : a > c) {
+            K.key[i] = c;
+            K.key[o] = a;
+            const int x = K.id[i];
+            K.id[i] = K.id[o];
+            K.id[o] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (unsigned t = 0; t < M; ++t) {
+    const int v = K.id[t];
+    if (v < 0) continue;   // padding (block-uniform)
+    if (tid == 0) {
+      const JpRec pr = rec_pair(P, v);
+      const int np = (int)(unsigned)pr.rec;
+      long long s0 = sp_first(pr.sp);
+      long long p0 = s0 - (np - P.xpred[v]);
+      if (!range_ok(P, p0, s0)) p0 = s0;
+      K.rec = pr.rec;
+      K.p0 = p0;
+      K.s0 = s0;
+      K.found = 0x7fffffff;
+    }
+    __syncthreads();
+    const unsigned long long rec = K.rec;
+    const long long p0 = K.p0, s0 = K.s0;
+    const int np = (int)(unsigned)rec;
+    const unsigned nw = bm_words(np);
+    int col = 0;
+    for (unsigned w0 = 0; w0 < nw; w0 += WAVE) {
+      if (tid < (unsigned)WAVE) K.bits[tid] = w0 + tid < nw ? bm_load(P, (rec >> 32) + w0 + tid) : ~0u;
+      __syncthreads();
+      const int lo = (int)(w0 * 32);
+      for (long long j = p0 + tid; j < s0; j += blockDim.x) {
+        const int u = P.dag[j];
+        const int c = vid_ok(P, u) ? done_colour(P, u) : 0;
+        const int bit = c - 1 - lo;   // colours outside 1 .. np+2 cannot be v's
+        if (c >= 1 && c <= np + 2 && bit >= 0 && bit < WAVE * 32) atomicOr(&K.bits[bit >> 5], 1u << (bit & 31));
+      }
+      __syncthreads();
+      if (tid < (unsigned)WAVE && ~K.bits[tid]) atomicMin(&K.found, (int)(w0 + tid) * 32 + __ffs((int)~K.bits[tid]) - 1);
+      __syncthreads();
+      if (K.found != 0x7fffffff) {
+        col = K.found + 1;
+        break;
+      }
+    }
+    if (!col) {   // unreachable: at most np of the np+2 colours are taken
+      if (tid == 0) raise_internal(P);
+      col = np + 1;
+    }
+    if (tid == 0) {
+      sti<SC_AGENT>(&P.color[v], col);
+      order_point();
+    }
+    __syncthreads();
+  }
+}
+
 // ---- JP state machine (plain accesses: the state is in LDS while the
 // single-block kernel runs, in the control block between kernels)
 
@@ -2794,7 +2925,11 @@ __device__ __forceinline__ void steps_lead(const Params& P, JpStage& gst, WaveLd
 __global__ __launch_bounds__(NARROW_BS) void k_jp_steps(Params P, int max_steps) {
   Ctrl* c = P.ctrl;
   __shared__ JpState S;
-  __shared__ NarrowLds Z;
+  __shared__ union StepsLds {
+    NarrowLds z;
+    CoreLds k;   // the core mode (the leader alone, with no level in LDS)
+  } SL;
+  NarrowLds& Z = SL.z;
   __shared__ unsigned fbuf[FB_CAP];
   __shared__ unsigned fcntl;
   __shared__ unsigned long long flds[FAN_LDS];
@@ -2956,6 +3091,22 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_steps(Params P, int max_steps)
       if (threadIdx.x == 0) {
         S.relax = 1;
         S.rit = 0;
+        have = 0;
+      }
+      __syncthreads();
+      in_global = false;
+      continue;
+    }
+    if (JP_CORE && P.relax_mode == RELAX_MODE_RULE && !S.relax && !S.split && S.level >= RELAX_AFTER &&
+        seg_size(P, r) <= (long long)CORE_MAX) {
+      // a small round that relaxation would not take (a dense core, or too
+      // small): the rest of it in JP's order, by this block alone (a level
+      // still in LDS is dropped; its vertices are uncoloured)
+      __syncthreads();
+      jp_core_round(P, SL.k, r);
+      if (threadIdx.x == 0) {
+        S.levels += 1;
+        jp_begin_round(S, r - 1);
         have = 0;
       }
       __syncthreads();
