@@ -2378,14 +2378,16 @@ __device__ __forceinline__ void jp_relax_items(const Params& P, JpStage& st, Wav
 // coloured by a level before, and its colour is in the bitmap too), so this
 // is JP's colouring: the greedy colouring in priority order.
 struct CoreLds {
-  unsigned long long key[CORE_MAX];
-  int id[CORE_MAX];
-  unsigned bits[WAVE];           // a 2048-colour window of the current vertex
-  unsigned long long rec;        // the current vertex's JP record
-  long long p0, s0;              // its same-round predecessors: dag[p0, s0)
-  int found;                     // first clear bit of the window (block minimum)
-  unsigned cnt;                  // listed vertices
+  unsigned long long key[CORE_MAX];   // sort keys (then scratch of the compaction)
+  int id[CORE_MAX];                   // the round's uncoloured vertices, in JP's order
+  int col[CORE_MAX];                  // their colours, by position
+  unsigned bits[WAVE];                // a 2048-colour window of the current vertex
+  unsigned long long rec[4];          // ring of the next vertices' JP records
+  long long p0[4], s0[4];             // and of their same-round predecessors: dag[p0, s0)
+  int found[2];                       // first clear bit of the window (block minimum), by parity
+  unsigned cnt;                       // listed vertices
 };
+constexpr int CORE_PF = CORE_MAX / NARROW_BS;   // predecessors a thread takes per vertex (a round has < CORE_MAX)
 
 // JP's order inside the round (larger first): rho_R (after D at selection for
 // ADG-O); jp_color's one pseudo-round orders by <given rank, rho_R>.
@@ -2393,7 +2395,29 @@ __device__ __forceinline__ unsigned long long core_key(const Params& P, int v) {
   return P.ord_identity ? (unsigned long long)prio(P, v) : same_key(P, v);
 }
 
-// Block-wide: colour the uncoloured vertices of round r (at most CORE_MAX).
+// Thread 0: the JP record of the vertex at position t into ring slot t % 4.
+__device__ __forceinline__ void core_rec(const Params& P, CoreLds& K, unsigned t, unsigned m, unsigned long long rec,
+                                         unsigned long long sp, int xp, int v) {
+  if (t >= m) return;
+  const int np = (int)(unsigned)rec;
+  const long long s0 = sp_first(sp);
+  long long p0 = s0 - (np - xp);
+  if (!range_ok(P, p0, s0)) p0 = s0;
+  K.rec[t & 3] = rec;
+  K.p0[t & 3] = p0;
+  K.s0[t & 3] = s0;
+  (void)v;
+}
+
+// Block-wide (NARROW_BS threads): colour the uncoloured vertices of round r
+// (at most CORE_MAX).  The vertices are listed and sorted; cnt[v] of each
+// becomes -(position + 1), which tells a predecessor's position from its id
+// (cnt is not read again in a round finished this way).  Then one vertex at
+// a time, in order, with the block's loads running ahead: the records of the
+// vertex three places on, the predecessor ids of the one two places on, and
+// the predecessors' positions of the next one, so that a vertex's own step
+// only reads LDS: its first 64 bitmap words (loaded two steps before) and
+// the colours of its predecessors by position.
 __device__ __forceinline__ void jp_core_round(const Params& P, CoreLds& K, int r) {
   const long long b = seg_begin(P, r), rs = seg_size(P, r);
   const unsigned tid = threadIdx.x;
@@ -2440,54 +2464,153 @@ __device__ __forceinline__ void jp_core_round(const Params& P, CoreLds& K, int r
       }
       __syncthreads();
     }
-  for (unsigned t = 0; t < M; ++t) {
-    const int v = K.id[t];
-    if (v < 0) continue;   // padding (block-uniform)
-    if (tid == 0) {
-      const JpRec pr = rec_pair(P, v);
-      const int np = (int)(unsigned)pr.rec;
-      long long s0 = sp_first(pr.sp);
-      long long p0 = s0 - (np - P.xpred[v]);
-      if (!range_ok(P, p0, s0)) p0 = s0;
-      K.rec = pr.rec;
-      K.p0 = p0;
-      K.s0 = s0;
-      K.found = 0x7fffffff;
+  // drop the padding (it sorted among the smallest keys), keeping the order
+  {
+    int* tmp = (int*)K.key;
+    constexpr int Q = CORE_MAX / NARROW_BS;
+    int x[Q], kept = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const unsigned i = tid * Q + q;
+      x[q] = i < M ? K.id[i] : -1;
+      kept += x[q] >= 0;
     }
+    int tot;
+    const int pre = wave_excl_scan<int>(kept, &tot);
+    __shared__ int wsum[NARROW_BS / WAVE];
+    if (lane_id() == 0) wsum[tid / WAVE] = tot;
     __syncthreads();
-    const unsigned long long rec = K.rec;
-    const long long p0 = K.p0, s0 = K.s0;
+    int at = pre;
+    for (unsigned w = 0; w < tid / WAVE; ++w) at += wsum[w];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      if (x[q] >= 0) tmp[at++] = x[q];
+    __syncthreads();
+    for (unsigned i = tid; i < m; i += blockDim.x) {
+      const int v = tmp[i];
+      K.id[i] = v;
+      sti<SC_AGENT>(&P.cnt[v], -(int)i - 1);   // its position, for its successors
+    }
+    order_point();
+    __syncthreads();
+  }
+  // prologue: records of positions 0..2, predecessor ids of 0 and 1, positions of 0's
+  unsigned long long arec = 0, asp = 0;
+  int axp = 0, av = -1;
+  if (tid < 4) {   // every ring slot starts as an empty range
+    K.rec[tid] = 0;
+    K.p0[tid] = 0;
+    K.s0[tid] = 0;
+  }
+  __syncthreads();
+  if (tid == 0)
+    for (unsigned t = 0; t < 3 && t < m; ++t) {
+      const int v = K.id[t];
+      const JpRec pr = rec_pair(P, v);
+      core_rec(P, K, t, m, pr.rec, pr.sp, P.xpred[v], v);
+    }
+  __syncthreads();
+  int ids1[CORE_PF], ids2[CORE_PF], pos0[CORE_PF], pos1[CORE_PF];
+  unsigned bw0 = ~0u, bw1 = ~0u, bw2 = ~0u;
+  auto load_ids = [&](unsigned t, int* ids, unsigned& bw) {
+#pragma unroll
+    for (int q = 0; q < CORE_PF; ++q) ids[q] = -1;
+    bw = ~0u;
+    if (t >= m) return;
+    long long p0 = K.p0[t & 3], s0 = K.s0[t & 3];
+    if (p0 < 0 || p0 > s0 || s0 > P.nnz) {   // core_rec checked it: a broken state
+      raise_internal(P);
+      p0 = s0 = 0;
+    }
+#pragma unroll
+    for (int q = 0; q < CORE_PF; ++q) {
+      const long long j = p0 + tid + (long long)q * NARROW_BS;
+      ids[q] = j < s0 ? P.dag[j] : -1;
+    }
+    const unsigned long long rec = K.rec[t & 3];
+    if (tid < (unsigned)WAVE && tid < bm_words((int)(unsigned)rec)) bw = bm_load(P, (rec >> 32) + tid);
+  };
+  auto load_pos = [&](const int* ids, int* pos) {
+#pragma unroll
+    for (int q = 0; q < CORE_PF; ++q) pos[q] = ids[q] >= 0 && vid_ok(P, ids[q]) ? ldi<SC_AGENT>(&P.cnt[ids[q]]) : 0;
+  };
+  load_ids(0, ids1, bw1);
+  load_pos(ids1, pos0);
+  bw0 = bw1;
+  load_ids(1, ids1, bw1);
+  for (unsigned t = 0; t < m; ++t) {
+    // run ahead: record of t + 3, predecessor ids of t + 2, positions of t + 1's
+    if (tid == 0 && t + 3 < m) {
+      av = K.id[t + 3];
+      const JpRec pr = rec_pair(P, av);
+      arec = pr.rec;
+      asp = pr.sp;
+      axp = P.xpred[av];
+    }
+    load_ids(t + 2, ids2, bw2);
+    load_pos(ids1, pos1);
+    // vertex t: its window of colours from LDS
+    const int v = K.id[t];
+    const unsigned long long rec = K.rec[t & 3];
     const int np = (int)(unsigned)rec;
     const unsigned nw = bm_words(np);
-    int col = 0;
-    for (unsigned w0 = 0; w0 < nw; w0 += WAVE) {
+    if (tid < (unsigned)WAVE) K.bits[tid] = bw0;
+    if (tid == 0) K.found[t & 1] = 0x7fffffff;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < CORE_PF; ++q)
+      if (pos0[q] < 0) {
+        const unsigned p = (unsigned)(-pos0[q] - 1);
+        const int c = p < t ? K.col[p] : 0;   // a predecessor comes earlier
+        if (c >= 1 && c <= np + 2 && c <= WAVE * 32) atomicOr(&K.bits[(c - 1) >> 5], 1u << ((c - 1) & 31));
+      }
+    __syncthreads();
+    if (tid < (unsigned)WAVE && ~K.bits[tid]) atomicMin(&K.found[t & 1], (int)tid * 32 + __ffs((int)~K.bits[tid]) - 1);
+    // the ring slot of t + 3 (its loads were issued at the start of this step);
+    // the barrier below publishes it before the next step reads it
+    if (tid == 0) core_rec(P, K, t + 3, m, arec, asp, axp, av);
+    __syncthreads();
+    int col = K.found[t & 1] != 0x7fffffff ? K.found[t & 1] + 1 : 0;
+    for (unsigned w0 = WAVE; !col && w0 < nw; w0 += WAVE) {
+      // past the first 2048 colours (rare): the next window, its words read now
+      __syncthreads();
       if (tid < (unsigned)WAVE) K.bits[tid] = w0 + tid < nw ? bm_load(P, (rec >> 32) + w0 + tid) : ~0u;
+      if (tid == 0) K.found[t & 1] = 0x7fffffff;
       __syncthreads();
       const int lo = (int)(w0 * 32);
-      for (long long j = p0 + tid; j < s0; j += blockDim.x) {
-        const int u = P.dag[j];
-        const int c = vid_ok(P, u) ? done_colour(P, u) : 0;
-        const int bit = c - 1 - lo;   // colours outside 1 .. np+2 cannot be v's
-        if (c >= 1 && c <= np + 2 && bit >= 0 && bit < WAVE * 32) atomicOr(&K.bits[bit >> 5], 1u << (bit & 31));
-      }
+#pragma unroll
+      for (int q = 0; q < CORE_PF; ++q)
+        if (pos0[q] < 0) {
+          const unsigned p = (unsigned)(-pos0[q] - 1);
+          const int c = p < t ? K.col[p] : 0;
+          const int bit = c - 1 - lo;
+          if (c >= 1 && c <= np + 2 && bit >= 0 && bit < WAVE * 32) atomicOr(&K.bits[bit >> 5], 1u << (bit & 31));
+        }
       __syncthreads();
-      if (tid < (unsigned)WAVE && ~K.bits[tid]) atomicMin(&K.found, (int)(w0 + tid) * 32 + __ffs((int)~K.bits[tid]) - 1);
+      if (tid < (unsigned)WAVE && ~K.bits[tid])
+        atomicMin(&K.found[t & 1], (int)(w0 + tid) * 32 + __ffs((int)~K.bits[tid]) - 1);
       __syncthreads();
-      if (K.found != 0x7fffffff) {
-        col = K.found + 1;
-        break;
-      }
+      if (K.found[t & 1] != 0x7fffffff) col = K.found[t & 1] + 1;
     }
     if (!col) {   // unreachable: at most np of the np+2 colours are taken
       if (tid == 0) raise_internal(P);
       col = np + 1;
     }
     if (tid == 0) {
+      K.col[t] = col;   // read by later steps after their first barrier
       sti<SC_AGENT>(&P.color[v], col);
-      order_point();
     }
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < CORE_PF; ++q) {
+      pos0[q] = pos1[q];
+      ids1[q] = ids2[q];
+    }
+    bw0 = bw1;
+    bw1 = bw2;
+    // (the next step's first barrier orders these LDS writes before their reads)
   }
+  order_point();
+  __syncthreads();
 }
 
 // ---- JP state machine (plain accesses: the state is in LDS while the
