@@ -48,7 +48,9 @@
 namespace adg {
 namespace batched {
 
+constexpr int SEL_Q = 4;              // vertices per thread in one selection pass
 constexpr int SMALL_ROW = 32;         // lane-per-vertex rows up to this length
+constexpr int ROW_BATCH = 8;          // entries of a lane's row whose loads are issued together
 constexpr int SCHED_BS = 1024;        // threads of the schedule kernel
 constexpr int SCHED_BUCKETS = 64;     // work classes (floor(log2(work)))
 constexpr int WG = __HIP_MEMORY_SCOPE_WORKGROUP;
@@ -234,11 +236,11 @@ struct Lds {
   int gid;
 };
 
-// Classify neighbour w of v (removed in round l): 1 = predecessor (w has a
-// higher priority), 0 = successor.  A neighbour still in U loses one degree.
-__device__ __forceinline__ bool visit(const BParams& P, const GraphCtx& C, int w, int l, uint32_t hv,
+// Classify neighbour w of v (removed in round l), whose round is rw (0: still
+// in U): 1 = predecessor (w has a higher priority), 0 = successor.  A
+// neighbour still in U loses one degree.
+__device__ __forceinline__ bool visit(const BParams& P, const GraphCtx& C, int w, int rw, int l, uint32_t hv,
                                       long long& x) {
-  const int rw = P.round[C.vo + w];
   if (rw == 0) {
     dec_wg(&P.D[C.vo + w]);
     ++x;
@@ -294,35 +296,54 @@ __device__ int adg_graph(const BParams& P, const GraphCtx& C, Lds<BB>& S, long l
     *act += (long long)N;
     // ---- selection: U_l -> R_l | U_{l+1}, stable
     long long nr = 0, nu = 0, sstay = 0;
-    for (long long b = 0; b < (long long)N; b += BB) {
-      const long long i = b + tid;
-      const bool valid = i < (long long)N;
-      int u = 0;
-      long long d = 0;
-      if (valid) {
-        if (l == 1) {
-          u = (int)i;
-          d = P.rp[C.vo + i + 1] - P.rp[C.vo + i];
-        } else {
-          u = Uin[i];
-          d = ld_dev(&P.D[C.vo + u]);
+    // SEL_Q consecutive vertices per thread, so that one block scan splits
+    // BB * SEL_Q of them and each thread's loads are in flight together
+    for (long long b = 0; b < (long long)N; b += (long long)BB * SEL_Q) {
+      const long long i0 = b + (long long)tid * SEL_Q;
+      int u[SEL_Q];
+      long long d[SEL_Q];
+#pragma unroll
+      for (int q = 0; q < SEL_Q; ++q) {
+        const long long i = i0 + q;
+        u[q] = 0;
+        d[q] = 0;
+        if (i < (long long)N) {
+          if (l == 1) {
+            u[q] = (int)i;
+            d[q] = P.rp[C.vo + i + 1] - P.rp[C.vo + i];
+          } else {
+            u[q] = Uin[i];
+          }
         }
       }
-      const bool inR = valid && (unsigned long long)d <= T;
-      const bool stay = valid && !inR;
+      if (l > 1) {
+#pragma unroll
+        for (int q = 0; q < SEL_Q; ++q)
+          if (i0 + q < (long long)N) d[q] = ld_dev(&P.D[C.vo + u[q]]);
+      }
       // two prefix sums packed in one: R count low, stay count high
+      long long mine = 0;
+#pragma unroll
+      for (int q = 0; q < SEL_Q; ++q)
+        if (i0 + q < (long long)N) mine += (unsigned long long)d[q] <= T ? 1LL : (1LL << 32);
       long long tot;
-      const long long pre = block_scan<BB>((inR ? 1LL : 0LL) | (stay ? (1LL << 32) : 0LL), S.red, &tot);
-      if (inR) {
-        P.RL[C.vo + rpos + nr + (pre & 0xffffffffLL)] = u;
-        P.round[C.vo + u] = l;
-      } else if (stay) {
-        Uout[nu + (pre >> 32)] = u;
-        if (l == 1) {
-          P.round[C.vo + u] = 0;
-          P.D[C.vo + u] = (int)d;
+      long long pre = block_scan<BB>(mine, S.red, &tot);
+#pragma unroll
+      for (int q = 0; q < SEL_Q; ++q) {
+        if (i0 + q >= (long long)N) continue;
+        if ((unsigned long long)d[q] <= T) {
+          P.RL[C.vo + rpos + nr + (pre & 0xffffffffLL)] = u[q];
+          P.round[C.vo + u[q]] = l;
+          pre += 1;
+        } else {
+          Uout[nu + (pre >> 32)] = u[q];
+          if (l == 1) {
+            P.round[C.vo + u[q]] = 0;
+            P.D[C.vo + u[q]] = (int)d[q];
+          }
+          sstay += d[q];
+          pre += 1LL << 32;
         }
-        sstay += d;
       }
       nr += tot & 0xffffffffLL;
       nu += tot >> 32;
@@ -341,10 +362,20 @@ __device__ int adg_graph(const BParams& P, const GraphCtx& C, Lds<BB>& S, long l
         if (r1 - r0 <= SMALL_ROW) {
           const uint32_t hv = tiebreak(P.hkey, (uint32_t)v);
           int np = 0, ns = 0;
-          for (long long e = r0; e < r1; ++e) {
-            const int w = P.col[e];
-            if (visit(P, C, w, l, hv, x)) P.dag[r0 + np++] = w;
-            else P.dag[r1 - 1 - ns++] = w;
+          // up to ROW_BATCH neighbours at a time: their ids, then their
+          // rounds, each group of loads in flight together
+          for (long long e0 = r0; e0 < r1; e0 += ROW_BATCH) {
+            int w[ROW_BATCH], rw[ROW_BATCH];
+#pragma unroll
+            for (int q = 0; q < ROW_BATCH; ++q) w[q] = e0 + q < r1 ? P.col[e0 + q] : 0;
+#pragma unroll
+            for (int q = 0; q < ROW_BATCH; ++q) rw[q] = e0 + q < r1 ? P.round[C.vo + w[q]] : 0;
+#pragma unroll
+            for (int q = 0; q < ROW_BATCH; ++q)
+              if (e0 + q < r1) {
+                if (visit(P, C, w[q], rw[q], l, hv, x)) P.dag[r0 + np++] = w[q];
+                else P.dag[r1 - 1 - ns++] = w[q];
+              }
           }
           finish_row<BB>(P, C, S, v, np);
         } else {
@@ -365,7 +396,7 @@ __device__ int adg_graph(const BParams& P, const GraphCtx& C, Lds<BB>& S, long l
           bool isp = false;
           if (valid) {
             w = P.col[e];
-            isp = visit(P, C, w, l, hv, x);
+            isp = visit(P, C, w, P.round[C.vo + w], l, hv, x);
           }
           const uint64_t pm = ballot(valid && isp);
           const uint64_t sm = ballot(valid && !isp);
