@@ -1593,12 +1593,15 @@ __device__ __forceinline__ unsigned bm_load(const Params& P, unsigned long long 
 // Colour of a finished vertex (also read at the coherence point).
 __device__ __forceinline__ int done_colour(const Params& P, int u) { return agent_load_i32(&P.color[u]); }
 
+constexpr int XW_WORDS = 2;   // bitmap words per vertex the cross-round pull gathers in LDS (colours 1..64)
+
 struct WaveLds {
   int off[WAVE + 1];           // exclusive scan of the lanes' item counts
   unsigned long long rec[WAVE];
   long long pb[WAVE];
   int ffree[WAVE];             // first clear bit found in the lanes' bitmaps (then the lanes' colours)
   int soff[WAVE + 1];          // exclusive scan of the lanes' same-round successor counts
+  unsigned xw[XW_WORDS * WAVE]; // cross-round pull: the first bitmap words of the lanes' vertices
 };
 
 // Lane k whose range [off[k], off[k+1]) holds position e.
@@ -1967,6 +1970,9 @@ __device__ __forceinline__ long long seg_size(const Params& P, int r) {
 // Bulk step at the start of round r: the colours of every predecessor from a
 // later round into the round's bitmaps.  Wavefronts take groups of 64 of the
 // round's vertices and spread each group's entries evenly over their lanes.
+// Colours 1..64 are ORed into LDS copies of the group's first two bitmap
+// words, which go out with one atomic per word; a higher colour goes
+// straight to the bitmap.
 template <int S>
 __device__ __forceinline__ void jp_xpull_items(const Params& P, WaveLds& W, int r, long long gw, long long gstride) {
   const long long b = seg_begin(P, r), sz = seg_size(P, r);
@@ -1975,9 +1981,11 @@ __device__ __forceinline__ void jp_xpull_items(const Params& P, WaveLds& W, int 
     const long long i = g * WAVE + lane;
     const bool ok = i < sz;
     int x = 0;
+    bool mine = false;   // the lane holds a vertex
     if (ok) {
       const int v = P.ORD[b + i];
       if (vid_ok(P, v)) {
+        mine = true;
         x = P.xpred[v];   // predecessors from later rounds
         W.rec[lane] = rec_of(P, v);
         W.pb[lane] = P.rp[v];
@@ -1987,6 +1995,8 @@ __device__ __forceinline__ void jp_xpull_items(const Params& P, WaveLds& W, int 
         }
       }
     }
+#pragma unroll
+    for (int k = 0; k < XW_WORDS; ++k) W.xw[k * WAVE + lane] = 0;
     int tot;
     W.off[lane] = wave_excl_scan<int>(x, &tot);
     if (lane == 0) W.off[WAVE] = tot;
@@ -2005,9 +2015,31 @@ __device__ __forceinline__ void jp_xpull_items(const Params& P, WaveLds& W, int 
       }
 #pragma unroll
       for (int t = 0; t < JP_UNROLL; ++t) c[t] = own[t] >= 0 && vid_ok(P, c[t]) ? done_colour(P, c[t]) : 0;
+      // colours 1..64 gather in LDS (most of them: a vertex with few
+      // predecessors has one or two words); the rest go to the bitmap
 #pragma unroll
       for (int t = 0; t < JP_UNROLL; ++t)
-        if (own[t] >= 0) bm_mark<S>(P, W.rec[own[t]], c[t]);
+        if (own[t] >= 0) {
+          const unsigned long long rec = W.rec[own[t]];
+          const int cb = c[t] - 1;
+          if (c[t] >= 1 && c[t] <= (int)(unsigned)rec + 2 && cb < XW_WORDS * 32)
+            atomicOr(&W.xw[(cb >> 5) * WAVE + own[t]], 1u << (cb & 31));
+          else
+            bm_mark<S>(P, rec, c[t]);
+        }
+    }
+    wave_sync();
+    if (mine) {   // one atomic per gathered word of the lane's vertex
+      const unsigned long long rec = W.rec[lane];
+#pragma unroll
+      for (int k = 0; k < XW_WORDS; ++k) {
+        const unsigned wd = W.xw[k * WAVE + lane];
+        if (wd) {
+          const unsigned long long at = (rec >> 32) + (unsigned)k;   // a set bit lies below np + 2: a word of v's bitmap
+          if (at < P.bm_cap) __hip_atomic_fetch_or(&P.B[at], wd, __ATOMIC_RELAXED, S);
+          else raise_internal(P);
+        }
+      }
     }
     wave_sync();
   }
