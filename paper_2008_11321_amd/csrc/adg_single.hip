@@ -245,6 +245,7 @@ struct Ctrl {
   unsigned long long preg;
   unsigned long long pcmd;
   unsigned long long pjoin;
+  unsigned long long pnum;     // participants, published by the leader once registration is closed
   // relaxation step the steps launch's participants run: round, step, list size, stamp
   unsigned rx[4];
   // binned decrements of the current round: the targets overflow SB (then the
@@ -1593,6 +1594,10 @@ __device__ __forceinline__ unsigned bm_load(const Params& P, unsigned long long 
 // Colour of a finished vertex (also read at the coherence point).
 __device__ __forceinline__ int done_colour(const Params& P, int u) { return agent_load_i32(&P.color[u]); }
 
+#ifndef ADG_XPULL_GMIN
+#define ADG_XPULL_GMIN 1
+#endif
+constexpr long long XPULL_GMIN = ADG_XPULL_GMIN;   // fewest vertices in a pull group
 constexpr int XW_WORDS = 2;   // bitmap words per vertex the cross-round pull gathers in LDS (colours 1..64)
 
 struct WaveLds {
@@ -1968,8 +1973,10 @@ __device__ __forceinline__ long long seg_size(const Params& P, int r) {
 }
 
 // Bulk step at the start of round r: the colours of every predecessor from a
-// later round into the round's bitmaps.  Wavefronts take groups of 64 of the
-// round's vertices and spread each group's entries evenly over their lanes.
+// later round into the round's bitmaps.  Wavefronts take groups of G
+// consecutive vertices of the round, G spreading the round evenly over the
+// wavefronts (up to 64: a small round of hubs keeps every wavefront busy),
+// and spread each group's entries evenly over their lanes.
 // Colours 1..64 are ORed into LDS copies of the group's first two bitmap
 // words, which go out with one atomic per word; a higher colour goes
 // straight to the bitmap.
@@ -1977,9 +1984,12 @@ template <int S>
 __device__ __forceinline__ void jp_xpull_items(const Params& P, WaveLds& W, int r, long long gw, long long gstride) {
   const long long b = seg_begin(P, r), sz = seg_size(P, r);
   const unsigned lane = lane_id();
-  for (long long g = gw; g * WAVE < sz; g += gstride) {
-    const long long i = g * WAVE + lane;
-    const bool ok = i < sz;
+  long long G = (sz + gstride - 1) / gstride;
+  if (G > WAVE) G = WAVE;
+  if (G < XPULL_GMIN) G = XPULL_GMIN;
+  for (long long g = gw; g * G < sz; g += gstride) {
+    const long long i = g * G + lane;
+    const bool ok = (long long)lane < G && i < sz;
     int x = 0;
     bool mine = false;   // the lane holds a vertex
     if (ok) {
@@ -3093,7 +3103,11 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_steps(Params P, int max_steps)
   constexpr int NW = NARROW_BS / WAVE;   // wavefronts per block
   WaveLds& W = Z.wl[threadIdx.x / WAVE];
   // ---- registration: one atomic per block on a word that the previous
-  // launch of the grid step (or k_jp_start) has cleared
+  // launch of the grid step (or k_jp_start) has cleared.  The leader
+  // publishes the participant count in pnum (cleared with preg): a block
+  // that comes after the close still adds to preg's count, so helpers do not
+  // take the count from there (another count than the leader's would split
+  // the work differently, and leave items no one takes).
   if (threadIdx.x == 0) {
     const unsigned long long old = __hip_atomic_fetch_add(&c->preg, REG_SEEN + 1ull, __ATOMIC_RELAXED, SC_AGENT);
     role = (old & REG_CLOSED) ? 0 : (old & 0xffff) == 0 ? 1 : 2;   // 0: leave, 1: lead, 2: help
@@ -3110,15 +3124,16 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_steps(Params P, int max_steps)
              wall_clock64() - t0 < REG_WAIT_TICKS)
         __builtin_amdgcn_s_sleep(2);
       nparts = (int)(__hip_atomic_fetch_or(&c->preg, REG_CLOSED, __ATOMIC_RELAXED, SC_AGENT) & 0xffff);
+      st64<SC_AGENT>(&c->pnum, (unsigned long long)nparts);   // >= 1: the leader counts itself
     } else if (role == 2) {
       unsigned long long w = 0;
       for (unsigned long long k = 0; k < POLL_MAX; ++k) {
-        w = ld64<SC_AGENT>(&c->preg);
-        if (w & REG_CLOSED) break;
+        w = ld64<SC_AGENT>(&c->pnum);
+        if (w) break;
         __builtin_amdgcn_s_sleep(2);
       }
-      if (!(w & REG_CLOSED)) {
-        raise_internal(P);
+      if (!w || (unsigned long long)pidx >= w) {   // a registered helper has an index below the count
+        if (!w) raise_internal(P);
         role = 0;
       }
       nparts = (int)(w & 0xffff);
@@ -3468,7 +3483,10 @@ __global__ __launch_bounds__(BS) void k_jp_grid(Params P) {
   Ctrl* c = P.ctrl;
   // launches alternate (steps, grid): every block of the steps launch before
   // this one has finished, so its registration word can be cleared for the next
-  if (blockIdx.x == 0 && threadIdx.x == 0) st64<SC_AGENT>(&c->preg, 0ull);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st64<SC_AGENT>(&c->preg, 0ull);
+    st64<SC_AGENT>(&c->pnum, 0ull);
+  }
   // Every block decides from state no block of this launch changes: blocks
   // may start after others have finished (other streams' kernels hold CUs).
   const int op = c->grid_op;
@@ -3480,7 +3498,7 @@ __global__ __launch_bounds__(BS) void k_jp_grid(Params P) {
     const int r = c->js.round, l = c->js.level;
     long long items;
     if (op == OP_XPULL) {
-      items = (seg_size(P, r) + WAVE - 1) / WAVE;
+      items = seg_size(P, r);   // groups of G >= 1 vertices: at most one per vertex
     } else if (op == OP_RELAX) {
       // step 0: groups of 64 of the round's vertices; later steps: a
       // wavefront per listed vertex
@@ -3549,6 +3567,7 @@ __global__ void k_jp_start(Params P, int rounds) {
   Ctrl* c = P.ctrl;
   c->grid_op = OP_NONE;
   c->preg = 0;   // the first steps launch registers from zero
+  c->pnum = 0;
   c->pcmd = 0;
   c->pjoin = 0;
   JpState& j = c->js;
