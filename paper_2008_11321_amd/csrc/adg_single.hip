@@ -2423,10 +2423,9 @@ struct CoreLds {
   unsigned long long key[CORE_MAX];   // sort keys (then scratch of the compaction)
   int id[CORE_MAX];                   // the round's uncoloured vertices, in JP's order
   int col[CORE_MAX];                  // their colours, by position
-  unsigned bits[WAVE];                // a 2048-colour window of the current vertex
+  unsigned bits[3][WAVE];             // 2048-colour windows: step t fills [t % 3], sets up [(t + 1) % 3]
   unsigned long long rec[4];          // ring of the next vertices' JP records
   long long p0[4], s0[4];             // and of their same-round predecessors: dag[p0, s0)
-  int found[2];                       // first clear bit of the window (block minimum), by parity
   unsigned cnt;                       // listed vertices
 };
 constexpr int CORE_PF = CORE_MAX / NARROW_BS;   // predecessors a thread takes per vertex (a round has < CORE_MAX)
@@ -2481,6 +2480,7 @@ __device__ __forceinline__ void jp_core_round(const Params& P, CoreLds& K, int r
     if (tid == 0) raise_internal(P);
     m = CORE_MAX;
   }
+  if (m == 0) return;   // (uniform: every thread read cnt after the barrier)
   unsigned M = 1;
   while (M < m) M <<= 1;
   for (unsigned i = m + tid; i < M; i += blockDim.x) {
@@ -2537,8 +2537,6 @@ __device__ __forceinline__ void jp_core_round(const Params& P, CoreLds& K, int r
     __syncthreads();
   }
   // prologue: records of positions 0..2, predecessor ids of 0 and 1, positions of 0's
-  unsigned long long arec = 0, asp = 0;
-  int axp = 0, av = -1;
   if (tid < 4) {   // every ring slot starts as an empty range
     K.rec[tid] = 0;
     K.p0[tid] = 0;
@@ -2552,105 +2550,158 @@ __device__ __forceinline__ void jp_core_round(const Params& P, CoreLds& K, int r
       core_rec(P, K, t, m, pr.rec, pr.sp, P.xpred[v], v);
     }
   __syncthreads();
-  int ids1[CORE_PF], ids2[CORE_PF], pos0[CORE_PF], pos1[CORE_PF];
-  unsigned bw0 = ~0u, bw1 = ~0u, bw2 = ~0u;
-  auto load_ids = [&](unsigned t, int* ids, unsigned& bw) {
-#pragma unroll
-    for (int q = 0; q < CORE_PF; ++q) ids[q] = -1;
-    bw = ~0u;
-    if (t >= m) return;
+  // The loads of the loop are straight-line code: an index out of range is
+  // replaced by a valid one and the value dropped afterwards (a branch
+  // around a load makes the compiler wait for every load in flight, also
+  // those issued for the steps ahead).  An id out of range is remembered and
+  // raised once, after the loop.
+  bool bad = false;
+  const unsigned long long bm_last = P.bm_cap ? P.bm_cap - 1 : 0;
+  auto load_ids = [&](unsigned t, int* ids) {
+    const bool live = t < m;
     long long p0 = K.p0[t & 3], s0 = K.s0[t & 3];
-    if (p0 < 0 || p0 > s0 || s0 > P.nnz) {   // core_rec checked it: a broken state
-      raise_internal(P);
-      p0 = s0 = 0;
-    }
+    const bool okr = p0 >= 0 && p0 <= s0 && s0 <= P.nnz;   // core_rec checked it
+    bad |= live && !okr;
+    if (!live || !okr) p0 = s0 = 0;
 #pragma unroll
     for (int q = 0; q < CORE_PF; ++q) {
       const long long j = p0 + tid + (long long)q * NARROW_BS;
-      ids[q] = j < s0 ? P.dag[j] : -1;
+      const bool in = j < s0;
+      const int x = P.dag[in ? j : 0];   // the round has edges: dag[0] exists
+      ids[q] = in ? x : -1;
     }
-    const unsigned long long rec = K.rec[t & 3];
-    if (tid < (unsigned)WAVE && tid < bm_words((int)(unsigned)rec)) bw = bm_load(P, (rec >> 32) + tid);
   };
   auto load_pos = [&](const int* ids, int* pos) {
 #pragma unroll
-    for (int q = 0; q < CORE_PF; ++q) pos[q] = ids[q] >= 0 && vid_ok(P, ids[q]) ? ldi<SC_AGENT>(&P.cnt[ids[q]]) : 0;
-  };
-  load_ids(0, ids1, bw1);
-  load_pos(ids1, pos0);
-  bw0 = bw1;
-  load_ids(1, ids1, bw1);
-  for (unsigned t = 0; t < m; ++t) {
-    // run ahead: record of t + 3, predecessor ids of t + 2, positions of t + 1's
-    if (tid == 0 && t + 3 < m) {
-      av = K.id[t + 3];
-      const JpRec pr = rec_pair(P, av);
-      arec = pr.rec;
-      asp = pr.sp;
-      axp = P.xpred[av];
+    for (int q = 0; q < CORE_PF; ++q) {
+      const bool okv = (unsigned)ids[q] < (unsigned)P.n;
+      bad |= ids[q] < -1 || ids[q] >= P.n;
+      const int x = ldi<SC_AGENT>(&P.cnt[okv ? ids[q] : 0]);
+      pos[q] = okv ? x : 0;
     }
-    load_ids(t + 2, ids2, bw2);
-    load_pos(ids1, pos1);
-    // vertex t: its window of colours from LDS
-    const int v = K.id[t];
+  };
+  // the first 64 bitmap words of position t, a word per lane of wavefront 0
+  auto load_bw = [&](unsigned t) -> unsigned {
+    const unsigned long long rec = K.rec[t & 3];
+    const unsigned nw = t < m ? bm_words((int)(unsigned)rec) : 0;
+    const bool win = tid < (unsigned)WAVE && tid < nw;
+    unsigned long long at = (rec >> 32) + (win ? tid : 0);
+    at = at <= bm_last ? at : bm_last;
+    const unsigned x = agent_load_u32(&P.B[at]);
+    return win ? x : ~0u;
+  };
+  // the JP record of position t (all threads load it; thread 0 files it)
+  auto load_rec = [&](unsigned t, unsigned long long& rec, unsigned long long& sp, int& xp) {
+    const int v = K.id[t < m ? t : m - 1];
+    const JpRec pr = rec_pair(P, v);
+    rec = pr.rec;
+    sp = pr.sp;
+    xp = P.xpred[v];
+  };
+  // the first clear bit of the window w (wavefront 0): its colour, 0 if none
+  auto first_clear = [&](const unsigned* w, unsigned w0) -> int {
+    const unsigned wd = w[tid];
+    const uint64_t fm = ballot(~wd != 0u);
+    if (!fm) return 0;
+    const int f = __ffsll((long long)fm) - 1;
+    const unsigned wf = (unsigned)__builtin_amdgcn_readlane((int)wd, f);
+    return (int)(w0 + (unsigned)f) * 32 + __ffs((int)~wf);
+  };
+  // Step t, two barriers.  Before the first, every thread ORs the colours of
+  // vertex t's same-round predecessors into its window (set up in the step
+  // before).  Between them, wavefront 0 takes the first clear bit as t's
+  // colour and sets up the window of t + 1.  A colour past the window
+  // (rare) is found after the second, by everyone.
+  // In: ids(t+1) and pos(t), loaded in the step before, bw(t+1) likewise,
+  // and the record of t+3.  Out, in the other register set: ids(t+2),
+  // pos(t+1), bw(t+2), the record of t+4.  The loop runs two steps per
+  // iteration with the sets' roles swapped, so that no register holding a
+  // load in flight is copied (a copy would wait for the load).
+  auto step = [&](unsigned t, const int* ids_c, int* ids_n, const int* pos_c, int* pos_n, unsigned bw_c,
+                  unsigned& bw_n, unsigned long long rec_f, unsigned long long sp_f, int xp_f,
+                  unsigned long long& rec_l, unsigned long long& sp_l, int& xp_l) {
+    load_rec(t + 4, rec_l, sp_l, xp_l);
+    load_ids(t + 2, ids_n);
+    load_pos(ids_c, pos_n);
+    bw_n = load_bw(t + 2);
     const unsigned long long rec = K.rec[t & 3];
     const int np = (int)(unsigned)rec;
     const unsigned nw = bm_words(np);
-    if (tid < (unsigned)WAVE) K.bits[tid] = bw0;
-    if (tid == 0) K.found[t & 1] = 0x7fffffff;
-    __syncthreads();
+    unsigned* win = K.bits[t % 3];
 #pragma unroll
     for (int q = 0; q < CORE_PF; ++q)
-      if (pos0[q] < 0) {
-        const unsigned p = (unsigned)(-pos0[q] - 1);
+      if (pos_c[q] < 0) {
+        const unsigned p = (unsigned)(-pos_c[q] - 1);
         const int c = p < t ? K.col[p] : 0;   // a predecessor comes earlier
-        if (c >= 1 && c <= np + 2 && c <= WAVE * 32) atomicOr(&K.bits[(c - 1) >> 5], 1u << ((c - 1) & 31));
+        if (c >= 1 && c <= np + 2 && c <= WAVE * 32) atomicOr(&win[(c - 1) >> 5], 1u << ((c - 1) & 31));
       }
+    // the ring slot of t + 3 (its record was loaded in the step before);
+    // the barriers below publish it before the next step reads it
+    if (tid == 0) core_rec(P, K, t + 3, m, rec_f, sp_f, xp_f, 0);
     __syncthreads();
-    if (tid < (unsigned)WAVE && ~K.bits[tid]) atomicMin(&K.found[t & 1], (int)tid * 32 + __ffs((int)~K.bits[tid]) - 1);
-    // the ring slot of t + 3 (its loads were issued at the start of this step);
-    // the barrier below publishes it before the next step reads it
-    if (tid == 0) core_rec(P, K, t + 3, m, arec, asp, axp, av);
+    if (tid < (unsigned)WAVE) {
+      const int col = first_clear(win, 0);
+      if (tid == 0) K.col[t] = col;   // 0: past the window, found below
+      K.bits[(t + 1) % 3][tid] = bw_c;
+    }
     __syncthreads();
-    int col = K.found[t & 1] != 0x7fffffff ? K.found[t & 1] + 1 : 0;
-    for (unsigned w0 = WAVE; !col && w0 < nw; w0 += WAVE) {
-      // past the first 2048 colours (rare): the next window, its words read now
-      __syncthreads();
-      if (tid < (unsigned)WAVE) K.bits[tid] = w0 + tid < nw ? bm_load(P, (rec >> 32) + w0 + tid) : ~0u;
-      if (tid == 0) K.found[t & 1] = 0x7fffffff;
-      __syncthreads();
-      const int lo = (int)(w0 * 32);
+    if (K.col[t] == 0) {   // (uniform) past the first 2048 colours: the next windows, their words read now
+      unsigned* sw = K.bits[(t + 2) % 3];   // free until the next step sets it up
+      int col = 0;
+      for (unsigned w0 = WAVE; !col && w0 < nw; w0 += WAVE) {
+        if (tid < (unsigned)WAVE) sw[tid] = w0 + tid < nw ? bm_load(P, (rec >> 32) + w0 + tid) : ~0u;
+        __syncthreads();
+        const int lo = (int)(w0 * 32);
 #pragma unroll
-      for (int q = 0; q < CORE_PF; ++q)
-        if (pos0[q] < 0) {
-          const unsigned p = (unsigned)(-pos0[q] - 1);
-          const int c = p < t ? K.col[p] : 0;
-          const int bit = c - 1 - lo;
-          if (c >= 1 && c <= np + 2 && bit >= 0 && bit < WAVE * 32) atomicOr(&K.bits[bit >> 5], 1u << (bit & 31));
+        for (int q = 0; q < CORE_PF; ++q)
+          if (pos_c[q] < 0) {
+            const unsigned p = (unsigned)(-pos_c[q] - 1);
+            const int c = p < t ? K.col[p] : 0;
+            const int bit = c - 1 - lo;
+            if (c >= 1 && c <= np + 2 && bit >= 0 && bit < WAVE * 32) atomicOr(&sw[bit >> 5], 1u << (bit & 31));
+          }
+        __syncthreads();
+        if (tid < (unsigned)WAVE) {
+          const int cf = first_clear(sw, w0);
+          if (tid == 0) K.col[t] = cf;
         }
-      __syncthreads();
-      if (tid < (unsigned)WAVE && ~K.bits[tid])
-        atomicMin(&K.found[t & 1], (int)(w0 + tid) * 32 + __ffs((int)~K.bits[tid]) - 1);
-      __syncthreads();
-      if (K.found[t & 1] != 0x7fffffff) col = K.found[t & 1] + 1;
+        __syncthreads();
+        col = K.col[t];
+        __syncthreads();   // sw is rewritten by the next window
+      }
+      if (!col) {   // unreachable: at most np of the np+2 colours are taken
+        if (tid == 0) {
+          raise_internal(P);
+          K.col[t] = np + 1;
+        }
+        __syncthreads();
+      }
     }
-    if (!col) {   // unreachable: at most np of the np+2 colours are taken
-      if (tid == 0) raise_internal(P);
-      col = np + 1;
-    }
-    if (tid == 0) {
-      K.col[t] = col;   // read by later steps after their first barrier
-      sti<SC_AGENT>(&P.color[v], col);
-    }
-#pragma unroll
-    for (int q = 0; q < CORE_PF; ++q) {
-      pos0[q] = pos1[q];
-      ids1[q] = ids2[q];
-    }
-    bw0 = bw1;
-    bw1 = bw2;
-    // (the next step's first barrier orders these LDS writes before their reads)
+  };
+  int idsA[CORE_PF], idsB[CORE_PF], posA[CORE_PF], posB[CORE_PF];
+  unsigned bwA, bwB = ~0u;
+  unsigned long long recA, spA, recB = 0, spB = 0;
+  int xpA, xpB = 0;
+  {   // set A for step 0: ids(1), pos(0), bw(1), the record of 3; the window of 0
+    int ids0[CORE_PF];
+    load_ids(0, ids0);
+    load_pos(ids0, posA);
+    load_ids(1, idsA);
+    const unsigned b0 = load_bw(0);
+    bwA = load_bw(1);
+    load_rec(3, recA, spA, xpA);
+    if (tid < (unsigned)WAVE) K.bits[0][tid] = b0;
+    __syncthreads();
   }
+  for (unsigned t = 0; t < m; t += 2) {
+    step(t, idsA, idsB, posA, posB, bwA, bwB, recA, spA, xpA, recB, spB, xpB);
+    if (t + 1 < m) step(t + 1, idsB, idsA, posB, posA, bwB, bwA, recB, spB, xpB, recA, spA, xpA);
+  }
+  if (bad) raise_internal(P);
+  __syncthreads();
+  // the colours, written once the round is done (nothing reads a colour of
+  // this round meanwhile: same-round predecessors are read back from LDS)
+  for (unsigned i = tid; i < m; i += blockDim.x) sti<SC_AGENT>(&P.color[K.id[i]], K.col[i]);
   order_point();
   __syncthreads();
 }
@@ -3268,7 +3319,7 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_steps(Params P, int max_steps)
       continue;
     }
     if (JP_CORE && P.relax_mode == RELAX_MODE_RULE && !S.relax && !S.split && S.level >= RELAX_AFTER &&
-        seg_size(P, r) <= (long long)CORE_MAX) {
+        seg_size(P, r) <= (long long)CORE_MAX && P.nnz > 0 && P.bm_cap > 0) {
       // a small round that relaxation would not take (a dense core, or too
       // small): the rest of it in JP's order, by this block alone (a level
       // still in LDS is dropped; its vertices are uncoloured)
