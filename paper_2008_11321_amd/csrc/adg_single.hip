@@ -80,6 +80,14 @@ constexpr int SEL_BLOCKS = 2048;        // fixed grid of the selection kernels
 #define ADG_JP_RELAX 1   // deep rounds finished by relaxation
 #endif
 constexpr bool JP_RELAX = ADG_JP_RELAX;
+#ifndef ADG_RELAX_COMPACT_MIN
+#define ADG_RELAX_COMPACT_MIN 65536
+#endif
+#ifndef ADG_RELAX_COMPACT_N
+#define ADG_RELAX_COMPACT_N 16777216
+#endif
+constexpr long long RELAX_COMPACT_MIN = ADG_RELAX_COMPACT_MIN;   // rounds of at least this many vertices relax by position,
+constexpr long long RELAX_COMPACT_N = ADG_RELAX_COMPACT_N;       // in graphs of at least this many vertices
 #ifndef ADG_JP_CORE
 #define ADG_JP_CORE 1   // small rounds whose levels colour a vertex or two: one block, in JP's order
 #endif
@@ -306,7 +314,8 @@ struct Params {
   unsigned long long* H[2];    // level lists, fan-out vertices: (first chunk << 32) | vertex
   unsigned hub_cap;
   int* color;
-  unsigned* rmark;             // relaxation: stamp of the step a vertex was last listed for
+  unsigned* rmark;             // relaxation: stamp of the step a position was last listed for
+  int* rcol;                   // relaxation: colours of the relaxed round's vertices, by position in the round
 };
 
 // Status byte of a vertex removed in round l.  Codes repeat every 255 rounds,
@@ -1972,6 +1981,12 @@ __device__ __forceinline__ long long seg_size(const Params& P, int r) {
   return (long long)P.roundN[r] - (long long)P.roundN[r + 1];
 }
 
+// The vertex at index idx of ORD.  jp_color's one pseudo-round is every
+// vertex in id order, and ORD is not written for it.
+__device__ __forceinline__ int ord_at(const Params& P, long long idx) {
+  return P.ord_identity ? (int)idx : P.ORD[idx];
+}
+
 // Bulk step at the start of round r: the colours of every predecessor from a
 // later round into the round's bitmaps.  Wavefronts take groups of G
 // consecutive vertices of the round, G spreading the round evenly over the
@@ -1993,7 +2008,7 @@ __device__ __forceinline__ void jp_xpull_items(const Params& P, WaveLds& W, int 
     int x = 0;
     bool mine = false;   // the lane holds a vertex
     if (ok) {
-      const int v = P.ORD[b + i];
+      const int v = ord_at(P, b + i);
       if (vid_ok(P, v)) {
         mine = true;
         x = P.xpred[v];   // predecessors from later rounds
@@ -2213,27 +2228,95 @@ __device__ __forceinline__ void jp_level_items(const Params& P, JpStage& st, Wav
 // wavefronts may rewrite them, but every change lists its successors for the
 // next step, so whatever a vertex last read was final once the lists run dry.
 
-// Step 0: the round's uncoloured vertices (lane per vertex) into list 1.
+// A large relaxed round of a large graph works on positions in the round
+// (its slice of ORD) instead of vertex ids: colours in rcol and marks in
+// rmark, both indexed by position, stay small enough for the caches, where
+// the colour and mark of a vertex id are scattered over arrays of n entries
+// (a small round's scattered lines fit the caches anyway, and a graph of a
+// few million vertices keeps its arrays in the Infinity Cache: there the
+// rewrite below costs more than it saves).  Step 0 stores each
+// vertex's position in cnt (free once the round's levels have stopped) and
+// its colour in rcol.  In step 1 every listed vertex replaces the vertex ids
+// of its own same-round predecessors and successors in the DAG by their
+// positions (cnt), as it reads them: step 1 lists every uncoloured vertex,
+// and each of them changes colour (from 0), so it reads both ranges.  Later
+// steps read positions.  A colour that changes is stored in rcol and in the
+// colour array (which nothing reads before the round ends).  Marks from an
+// earlier round's positions hold older stamps, so they never look current.
+// The DAG is no longer read-only here, and a later step may run on another
+// XCD, whose L2 can still hold a line from before step 1: so step 1 always
+// ends a launch (a grid step does anyway; the steps launch ends after it),
+// and the launch boundary makes the new entries visible to plain loads.
+
+// A position read from a list or the DAG: below the round's size (in a
+// round relaxed by vertex id: below n).
+__device__ __forceinline__ bool pos_ok(const Params& P, int p, unsigned sz) {
+  if ((unsigned)p < sz) return true;
+  raise_internal(P);
+  return false;
+}
+
+// How round r is relaxed: by position (compact) or by vertex id.
+struct RelaxIdx {
+  bool compact;
+  long long b;        // the round's first index in ORD
+  unsigned lim;       // bound of the list entries and DAG values: round size, or n
+  int* cols;          // colours by list entry: rcol, or the colour array
+};
+__device__ __forceinline__ RelaxIdx relax_idx(const Params& P, int r) {
+  RelaxIdx x;
+  const long long sz = seg_size(P, r);
+  x.compact = sz >= RELAX_COMPACT_MIN && (long long)P.n >= RELAX_COMPACT_N;
+  x.b = seg_begin(P, r);
+  x.lim = x.compact ? (unsigned)sz : (unsigned)P.n;
+  x.cols = x.compact ? P.rcol : P.color;
+  return x;
+}
+
+// Step 0: the uncoloured vertices of the round (lane per vertex) go into
+// list 1; by position, every vertex of the round gets its position (cnt)
+// and colour (rcol).
 __device__ __forceinline__ void jp_relax_list(const Params& P, JpStage& st, int r, long long gw, long long gstride) {
   const long long b = seg_begin(P, r), sz = seg_size(P, r);
+  const bool compact = relax_idx(P, r).compact;
   const unsigned lane = lane_id();
   for (long long g = gw;; g += gstride) {
     if (!stage_pass(P, st, 0, g * WAVE < sz)) break;
     if (g * WAVE >= sz) continue;
     const long long i = g * WAVE + lane;
-    int v = i < sz ? P.ORD[b + i] : -1;
+    int v = i < sz ? ord_at(P, b + i) : -1;
     const bool ok = v >= 0 && vid_ok(P, v);
-    const bool open = ok && done_colour(P, v) == 0;
-    jp_append<SC_AGENT>(P, st, 0, open, open ? v : 0, JpRec{0, 0});
+    int c = 0;
+    if (ok) {
+      c = done_colour(P, v);
+      if (compact) {
+        sti<SC_AGENT>(&P.cnt[v], (int)i);
+        sti<SC_AGENT>(&P.rcol[i], c);
+      }
+    }
+    const bool open = ok && c == 0;
+    jp_append<SC_AGENT>(P, st, 0, open, open ? (compact ? (int)i : v) : 0, JpRec{0, 0});
   }
+}
+
+// RELAX_UNROLL same-round neighbours u[k] read from dag[j[k]] (-1: none):
+// in step 1 (tr) vertex ids, turned into positions and written back.
+__device__ __forceinline__ void relax_translate(const Params& P, int (&u)[RELAX_UNROLL], const long long (&j)[RELAX_UNROLL]) {
+#pragma unroll
+  for (int k = 0; k < RELAX_UNROLL; ++k) u[k] = u[k] >= 0 && vid_ok(P, u[k]) ? ldi<SC_AGENT>(&P.cnt[u[k]]) : -1;
+#pragma unroll
+  for (int k = 0; k < RELAX_UNROLL; ++k)
+    if (j[k] >= 0) P.dag[j[k]] = u[k];
 }
 
 // The colour equation of one vertex v (bitmap rec, np predecessors, the
 // same-round ones at dag[p0, s0)), solved by the whole wavefront: windows of
 // 2048 colours, each filled from v's bitmap words and then from the current
-// colours of its same-round predecessors, until one has a clear bit.
+// colours of its same-round predecessors, until one has a clear bit.  (In
+// step 1 the first window translates the range; a lane reads back in later
+// windows what it wrote itself.)
 __device__ __forceinline__ int relax_wave(const Params& P, WaveLds& W, unsigned long long rec, int np, long long p0,
-                                          long long s0) {
+                                          long long s0, bool tr, const RelaxIdx& X) {
   const unsigned lane = lane_id();
   unsigned* bits = (unsigned*)W.ffree;
   const unsigned nw = bm_words(np);
@@ -2245,13 +2328,16 @@ __device__ __forceinline__ int relax_wave(const Params& P, WaveLds& W, unsigned 
     const int lo = (int)(w0 * 32);
     for (long long j0 = p0; j0 < s0; j0 += WAVE * RELAX_UNROLL) {
       int u[RELAX_UNROLL];
+      long long jj[RELAX_UNROLL];
 #pragma unroll
       for (int k = 0; k < RELAX_UNROLL; ++k) {
         const long long j = j0 + k * WAVE + lane;
+        jj[k] = j < s0 ? j : -1;
         u[k] = j < s0 ? P.dag[j] : -1;
       }
+      if (tr && w0 == 0) relax_translate(P, u, jj);
 #pragma unroll
-      for (int k = 0; k < RELAX_UNROLL; ++k) u[k] = u[k] >= 0 && vid_ok(P, u[k]) ? done_colour(P, u[k]) : 0;
+      for (int k = 0; k < RELAX_UNROLL; ++k) u[k] = u[k] >= 0 && pos_ok(P, u[k], X.lim) ? agent_load_i32(&X.cols[u[k]]) : 0;
 #pragma unroll
       for (int k = 0; k < RELAX_UNROLL; ++k) {
         const int bit = u[k] - 1 - lo;   // colours outside 1 .. np+2 cannot be v's
@@ -2271,34 +2357,44 @@ __device__ __forceinline__ int relax_wave(const Params& P, WaveLds& W, unsigned 
   return col;
 }
 
-// The same-round successors [s0, s1) of a vertex whose colour changed, by
-// the whole wavefront, RELAX_UNROLL widths at a time: each is listed for
+// Marks and list entries for RELAX_UNROLL same-round successors w[k]
+// (positions, -1: none) of a vertex whose colour changed: each is listed for
 // the next step unless a mark at its stamp says it already is (most are:
 // listed by another changed predecessor).  A plain read of the mark, which
 // can only lag behind, spares most of the atomics.
+__device__ __forceinline__ void relax_mark(const Params& P, JpStage& ast, int t, unsigned stamp, unsigned lim,
+                                           const int (&w)[RELAX_UNROLL]) {
+  bool mk[RELAX_UNROLL];
+#pragma unroll
+  for (int k = 0; k < RELAX_UNROLL; ++k) mk[k] = w[k] >= 0 && pos_ok(P, w[k], lim) && P.rmark[w[k]] < stamp;
+#pragma unroll
+  for (int k = 0; k < RELAX_UNROLL; ++k)
+    mk[k] = mk[k] && __hip_atomic_fetch_max(&P.rmark[w[k]], stamp, __ATOMIC_RELAXED, SC_AGENT) < stamp;
+#pragma unroll
+  for (int k = 0; k < RELAX_UNROLL; ++k) jp_append<SC_AGENT>(P, ast, t, mk[k], mk[k] ? w[k] : 0, JpRec{0, 0});
+}
+
+// The same-round successors [s0, s1) of a vertex whose colour changed, by
+// the whole wavefront, RELAX_UNROLL widths at a time (translated in step 1).
 __device__ __forceinline__ void relax_push_wave(const Params& P, JpStage& ast, int t, unsigned stamp, long long s0,
-                                                long long s1) {
+                                                long long s1, bool tr, unsigned lim) {
   const unsigned lane = lane_id();
   for (long long j0 = s0; j0 < s1; j0 += WAVE * RELAX_UNROLL) {
     int w[RELAX_UNROLL];
-    bool mk[RELAX_UNROLL];
+    long long jj[RELAX_UNROLL];
 #pragma unroll
     for (int k = 0; k < RELAX_UNROLL; ++k) {
       const long long j = j0 + k * WAVE + lane;
+      jj[k] = j < s1 ? j : -1;
       w[k] = j < s1 ? P.dag[j] : -1;
     }
-#pragma unroll
-    for (int k = 0; k < RELAX_UNROLL; ++k) mk[k] = w[k] >= 0 && vid_ok(P, w[k]) && P.rmark[w[k]] < stamp;
-#pragma unroll
-    for (int k = 0; k < RELAX_UNROLL; ++k)
-      mk[k] = mk[k] && __hip_atomic_fetch_max(&P.rmark[w[k]], stamp, __ATOMIC_RELAXED, SC_AGENT) < stamp;
-#pragma unroll
-    for (int k = 0; k < RELAX_UNROLL; ++k) jp_append<SC_AGENT>(P, ast, t, mk[k], mk[k] ? w[k] : 0, JpRec{0, 0});
+    if (tr) relax_translate(P, w, jj);
+    relax_mark(P, ast, t, stamp, lim, w);
   }
 }
 
-// Step t >= 1 over its list of nl vertices.  A list no longer than
-// 2 gstride goes a wavefront per vertex (relax_wave, relax_push_wave).
+// Step t >= 1 of round r over its list of nl positions.  A list no longer
+// than 2 gstride goes a wavefront per vertex (relax_wave, relax_push_wave).
 // Longer lists go G entries per wavefront, G spreading the list evenly over
 // the wavefronts (up to 64), with lb the wavefront's LDS area of
 // 64 x RELAX_LW words: a light vertex (at most RELAX_LK same-round
@@ -2306,26 +2402,33 @@ __device__ __forceinline__ void relax_push_wave(const Params& P, JpStage& ast, i
 // pushed by its lane alone, in its own words of lb (word w of lane k at
 // lb[64 w + k]); the others by the whole wavefront, one after the other.
 __device__ __forceinline__ void jp_relax_items(const Params& P, JpStage& st, WaveLds& W, unsigned* lb, int t, unsigned nl,
-                                               unsigned stamp, long long gw, long long gstride) {
+                                               unsigned stamp, long long gw, long long gstride, int r) {
   const unsigned lane = lane_id();
   const unsigned* Lin = P.F[t & 1];
+  const RelaxIdx X = relax_idx(P, r);
+  const bool tr = X.compact && t == 1;
   JpStage ast = st;
   ast.acc = nullptr;   // a relaxation list keeps no work sums
   if (!lb || (long long)nl <= 2 * gstride) {
     for (long long i = gw; i < (long long)nl; i += gstride) {
-      const int v = __builtin_amdgcn_readfirstlane((int)ld32<SC_AGENT>(&Lin[i]));
+      const int p = __builtin_amdgcn_readfirstlane((int)ld32<SC_AGENT>(&Lin[i]));
+      if (!pos_ok(P, p, X.lim)) continue;
+      const int v = X.compact ? __builtin_amdgcn_readfirstlane(ord_at(P, X.b + p)) : p;
       if (!vid_ok(P, v)) continue;
       const JpRec pr = rec_pair(P, v);
-      const int old = __builtin_amdgcn_readfirstlane(done_colour(P, v));
+      const int old = __builtin_amdgcn_readfirstlane(agent_load_i32(&X.cols[p]));
       const int np = (int)(unsigned)pr.rec;
       const long long s0 = sp_first(pr.sp);
       const long long s1 = s0 + sp_count(P, v, pr.sp);
       const long long p0 = s0 - (np - P.xpred[v]);   // same-round predecessors: [p0, s0)
       if (!range_ok(P, p0, s0) || !range_ok(P, s0, s1)) continue;
-      const int col = relax_wave(P, W, pr.rec, np, p0, s0);
-      if (col == old) continue;
-      if (lane == 0) sti<SC_AGENT>(&P.color[v], col);
-      relax_push_wave(P, ast, t, stamp, s0, s1);
+      const int col = relax_wave(P, W, pr.rec, np, p0, s0, tr, X);
+      if (col == old) continue;   // (never in step 1: every listed colour is 0)
+      if (lane == 0) {
+        sti<SC_AGENT>(&X.cols[p], col);
+        if (X.compact) sti<SC_AGENT>(&P.color[v], col);
+      }
+      relax_push_wave(P, ast, t, stamp, s0, s1, tr, X.lim);
     }
     return;
   }
@@ -2333,14 +2436,19 @@ __device__ __forceinline__ void jp_relax_items(const Params& P, JpStage& st, Wav
   if (G > WAVE) G = WAVE;
   for (long long g = gw; g * G < (long long)nl; g += gstride) {
     const long long i = g * G + lane;
-    const int v = lane < G && i < (long long)nl ? (int)ld32<SC_AGENT>(&Lin[i]) : -1;
-    bool act = v >= 0 && vid_ok(P, v);
+    const int p = lane < G && i < (long long)nl ? (int)ld32<SC_AGENT>(&Lin[i]) : -1;
+    bool act = p >= 0 && pos_ok(P, p, X.lim);
+    int v = -1;
+    if (act) {
+      v = X.compact ? ord_at(P, X.b + p) : p;
+      act = vid_ok(P, v);
+    }
     JpRec pr{0, 0};
     long long p0 = 0, s0 = 0, s1 = 0;
     int np = 0, old = 0;
     if (act) {
       pr = rec_pair(P, v);
-      old = done_colour(P, v);
+      old = agent_load_i32(&X.cols[p]);
       np = (int)(unsigned)pr.rec;
       s0 = sp_first(pr.sp);
       s1 = s0 + sp_count(P, v, pr.sp);
@@ -2358,10 +2466,15 @@ __device__ __forceinline__ void jp_relax_items(const Params& P, JpStage& st, Wav
       lb[w * WAVE + lane] = lite && w < nw ? bm_load(P, (pr.rec >> 32) + (unsigned)w) : ~0u;
     for (int j0 = 0; j0 < kmax; j0 += RELAX_UNROLL) {
       int u[RELAX_UNROLL];
+      long long jj[RELAX_UNROLL];
 #pragma unroll
-      for (int k = 0; k < RELAX_UNROLL; ++k) u[k] = j0 + k < kp ? P.dag[p0 + j0 + k] : -1;
+      for (int k = 0; k < RELAX_UNROLL; ++k) {
+        jj[k] = j0 + k < kp ? p0 + j0 + k : -1;
+        u[k] = j0 + k < kp ? P.dag[p0 + j0 + k] : -1;
+      }
+      if (tr) relax_translate(P, u, jj);
 #pragma unroll
-      for (int k = 0; k < RELAX_UNROLL; ++k) u[k] = u[k] >= 0 && vid_ok(P, u[k]) ? done_colour(P, u[k]) : 0;
+      for (int k = 0; k < RELAX_UNROLL; ++k) u[k] = u[k] >= 0 && pos_ok(P, u[k], X.lim) ? agent_load_i32(&X.cols[u[k]]) : 0;
 #pragma unroll
       for (int k = 0; k < RELAX_UNROLL; ++k)
         if (u[k] >= 1 && u[k] <= np + 2) lb[((u[k] - 1) >> 5) * WAVE + lane] |= 1u << ((u[k] - 1) & 31);
@@ -2378,30 +2491,34 @@ __device__ __forceinline__ void jp_relax_items(const Params& P, JpStage& st, Wav
       }
     }
     const bool lchanged = lite && col != old;
-    if (lchanged) sti<SC_AGENT>(&P.color[v], col);
+    if (lchanged) {
+      sti<SC_AGENT>(&X.cols[p], col);
+      if (X.compact) sti<SC_AGENT>(&P.color[v], col);
+    }
     const int ks = lchanged ? (int)(s1 - s0) : 0;
     const int smax = wave_max(ks);
     for (int j0 = 0; j0 < smax; j0 += RELAX_UNROLL) {
       int w[RELAX_UNROLL];
-      bool mk[RELAX_UNROLL];
+      long long jj[RELAX_UNROLL];
 #pragma unroll
-      for (int k = 0; k < RELAX_UNROLL; ++k) w[k] = j0 + k < ks ? P.dag[s0 + j0 + k] : -1;
-#pragma unroll
-      for (int k = 0; k < RELAX_UNROLL; ++k) mk[k] = w[k] >= 0 && vid_ok(P, w[k]) && P.rmark[w[k]] < stamp;
-#pragma unroll
-      for (int k = 0; k < RELAX_UNROLL; ++k)
-        mk[k] = mk[k] && __hip_atomic_fetch_max(&P.rmark[w[k]], stamp, __ATOMIC_RELAXED, SC_AGENT) < stamp;
-#pragma unroll
-      for (int k = 0; k < RELAX_UNROLL; ++k) jp_append<SC_AGENT>(P, ast, t, mk[k], mk[k] ? w[k] : 0, JpRec{0, 0});
+      for (int k = 0; k < RELAX_UNROLL; ++k) {
+        jj[k] = j0 + k < ks ? s0 + j0 + k : -1;
+        w[k] = j0 + k < ks ? P.dag[s0 + j0 + k] : -1;
+      }
+      if (tr) relax_translate(P, w, jj);
+      relax_mark(P, ast, t, stamp, X.lim, w);
     }
     // the others: the whole wavefront, one after the other
     for (uint64_t m = ballot(act && !lite); m; m &= m - 1) {
       const int src = __ffsll((long long)m) - 1;
       const long long hs0 = readlane_i64(s0, src), hs1 = readlane_i64(s1, src);
-      const int c = relax_wave(P, W, readlane_u64(pr.rec, src), readlane_i(np, src), readlane_i64(p0, src), hs0);
+      const int c = relax_wave(P, W, readlane_u64(pr.rec, src), readlane_i(np, src), readlane_i64(p0, src), hs0, tr, X);
       if (c == readlane_i(old, src)) continue;
-      if (lane == 0) sti<SC_AGENT>(&P.color[readlane_i(v, src)], c);
-      relax_push_wave(P, ast, t, stamp, hs0, hs1);
+      if (lane == 0) {
+        sti<SC_AGENT>(&X.cols[readlane_i(p, src)], c);
+        if (X.compact) sti<SC_AGENT>(&P.color[readlane_i(v, src)], c);
+      }
+      relax_push_wave(P, ast, t, stamp, hs0, hs1, tr, X.lim);
     }
   }
 }
@@ -2465,7 +2582,7 @@ __device__ __forceinline__ void jp_core_round(const Params& P, CoreLds& K, int r
   if (tid == 0) K.cnt = 0;
   __syncthreads();
   for (long long i = tid; i < rs; i += blockDim.x) {
-    const int v = P.ORD[b + i];
+    const int v = ord_at(P, b + i);
     if (vid_ok(P, v) && done_colour(P, v) == 0) {
       const unsigned at = atomicAdd(&K.cnt, 1u);
       if (at < (unsigned)CORE_MAX) {
@@ -3103,7 +3220,7 @@ __device__ __forceinline__ void steps_command(const Params& P, JpStage& st, Wave
     const int rr = (int)ld32<SC_AGENT>(&c->rx[0]);
     const int t = (int)ld32<SC_AGENT>(&c->rx[1]);
     if (t == 0) jp_relax_list(P, st, rr, gw, gstride);
-    else jp_relax_items(P, st, W, nullptr, t, ld32<SC_AGENT>(&c->rx[2]), ld32<SC_AGENT>(&c->rx[3]), gw, gstride);
+    else jp_relax_items(P, st, W, nullptr, t, ld32<SC_AGENT>(&c->rx[2]), ld32<SC_AGENT>(&c->rx[3]), gw, gstride, rr);
     jp_stage_flush<SC_AGENT>(P, st, t);
   }
 }
@@ -3381,6 +3498,7 @@ __global__ __launch_bounds__(NARROW_BS) void k_jp_steps(Params P, int max_steps)
         S.levels += 1;
       }
       __syncthreads();
+      if (t == 1 && relax_idx(P, r).compact) break;   // step 1 rewrote the DAG: the next steps run in a new launch
       continue;
     }
     if (!have) {
@@ -3595,7 +3713,7 @@ __global__ __launch_bounds__(BS) void k_jp_grid(Params P) {
     static_assert(sizeof(flds) >= WPB * WAVE * RELAX_LW * 4, "relaxation buffers");
     if (t == 0) jp_relax_list(P, st, r, gw, gstride);
     else jp_relax_items(P, st, W, (unsigned*)flds + (threadIdx.x / WAVE) * WAVE * RELAX_LW, t, c->js.fcnt[t % 3],
-                        c->js.rstamp, gw, gstride);
+                        c->js.rstamp, gw, gstride, r);
     jp_stage_flush<SC_AGENT>(P, st, t);
   } else {
     const int l = c->js.level;
@@ -4185,6 +4303,7 @@ Params make_params(const adg_csr_t* g, void* ws, uint64_t p, uint64_t q, uint64_
   P.huge_cap = (unsigned)L.huge_cap;
   P.color = color;
   P.rmark = (unsigned*)(base + L.UL0);   // ADG's active lists are free once JP starts
+  P.rcol = (int*)(base + L.UL1);
   // Round-count bound from the ADG depth lemma: |U| shrinks by a factor
   // 1/(1+eps) per round, so L <= ceil(log n / log(1+eps)) + 1; +1 margin.
   long long bound = (long long)g->n + 1;

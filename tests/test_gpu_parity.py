@@ -147,6 +147,24 @@ def test_adg_order_and_jp_color_separately(dev):
         check_jp(rp, col, ranking, 12, gc.cpu().numpy())
 
 
+def test_jp_color_on_a_zeroed_workspace(dev):
+    """jp_color colours every vertex as one pseudo-round in id order (its
+    own ORD slot is never written): on a workspace of zeros, with the ADG
+    ranking of an R-MAT graph deep enough for the relaxation of the
+    pseudo-round, the colours still equal the oracle's JP (Algorithm 3)."""
+    import torch
+    rp, col = graphgen.rmat_config(16, seed=5)
+    rho, L, _ = oracle.adg(rp, col, 1, 10)
+    color, k = oracle.jp(rp, col, rho, 11)
+    g = dev.Graph(rp, col)
+    ws = torch.zeros(dev.workspace_bytes(g.n, g.nnz), dtype=torch.uint8, device="cuda")
+    for _ in range(2):   # and again on what the first call left
+        gc, gk = dev.jp_color(g, torch.from_numpy(rho.astype(np.int32)).cuda(), 11, workspace=ws)
+        torch.cuda.synchronize()
+        assert dev.get_stats(ws)["error"] == 0
+        assert int(gk.item()) == k and np.array_equal(gc.cpu().numpy(), color)
+
+
 def test_repeatable(dev):
     import torch
     rp, col = graphgen.rmat_config(17, seed=7)
