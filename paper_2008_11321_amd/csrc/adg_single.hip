@@ -2457,28 +2457,41 @@ __device__ __forceinline__ void jp_relax_items(const Params& P, JpStage& st, Wav
     }
     const int nw = act ? (int)bm_words(np) : 0;
     const bool lite = act && s0 - p0 <= RELAX_LK && s1 - s0 <= RELAX_LK && nw <= RELAX_LW;
-    int col = 0;
-    // light vertices: a lane each
-    const int kp = lite ? (int)(s0 - p0) : 0;
-    const int kmax = wave_max(kp);
+    // light vertices: a vertex's words of lb belong to its lane; the
+    // group's predecessor entries (then its successor entries) are spread
+    // evenly over the lanes (a prefix sum of the counts and a search for
+    // the owner), so that a lane with many entries does not hold the others
 #pragma unroll
     for (int w = 0; w < RELAX_LW; ++w)
       lb[w * WAVE + lane] = lite && w < nw ? bm_load(P, (pr.rec >> 32) + (unsigned)w) : ~0u;
-    for (int j0 = 0; j0 < kmax; j0 += RELAX_UNROLL) {
-      int u[RELAX_UNROLL];
-      long long jj[RELAX_UNROLL];
+    {
+      int tot;
+      W.off[lane] = wave_excl_scan<int>(lite ? (int)(s0 - p0) : 0, &tot);
+      if (lane == 0) W.off[WAVE] = tot;
+      W.pb[lane] = p0;
+      W.rec[lane] = (unsigned long long)(unsigned)np;
+      wave_sync();
+      for (int e0 = 0; e0 < tot; e0 += WAVE * RELAX_UNROLL) {
+        int u[RELAX_UNROLL], own[RELAX_UNROLL];
+        long long jj[RELAX_UNROLL];
 #pragma unroll
-      for (int k = 0; k < RELAX_UNROLL; ++k) {
-        jj[k] = j0 + k < kp ? p0 + j0 + k : -1;
-        u[k] = j0 + k < kp ? P.dag[p0 + j0 + k] : -1;
+        for (int k = 0; k < RELAX_UNROLL; ++k) {
+          const int e = e0 + k * WAVE + (int)lane;
+          own[k] = e < tot ? wave_owner(W, e) : -1;
+          jj[k] = own[k] >= 0 ? W.pb[own[k]] + (e - W.off[own[k]]) : -1;
+          u[k] = own[k] >= 0 ? P.dag[jj[k]] : -1;
+        }
+        if (tr) relax_translate(P, u, jj);
+#pragma unroll
+        for (int k = 0; k < RELAX_UNROLL; ++k) u[k] = u[k] >= 0 && pos_ok(P, u[k], X.lim) ? agent_load_i32(&X.cols[u[k]]) : 0;
+#pragma unroll
+        for (int k = 0; k < RELAX_UNROLL; ++k)
+          if (u[k] >= 1 && u[k] <= (int)W.rec[own[k]] + 2)
+            atomicOr(&lb[((u[k] - 1) >> 5) * WAVE + own[k]], 1u << ((u[k] - 1) & 31));
       }
-      if (tr) relax_translate(P, u, jj);
-#pragma unroll
-      for (int k = 0; k < RELAX_UNROLL; ++k) u[k] = u[k] >= 0 && pos_ok(P, u[k], X.lim) ? agent_load_i32(&X.cols[u[k]]) : 0;
-#pragma unroll
-      for (int k = 0; k < RELAX_UNROLL; ++k)
-        if (u[k] >= 1 && u[k] <= np + 2) lb[((u[k] - 1) >> 5) * WAVE + lane] |= 1u << ((u[k] - 1) & 31);
+      wave_sync();
     }
+    int col = 0;
     if (lite) {
 #pragma unroll
       for (int w = RELAX_LW - 1; w >= 0; --w) {
@@ -2495,18 +2508,26 @@ __device__ __forceinline__ void jp_relax_items(const Params& P, JpStage& st, Wav
       sti<SC_AGENT>(&X.cols[p], col);
       if (X.compact) sti<SC_AGENT>(&P.color[v], col);
     }
-    const int ks = lchanged ? (int)(s1 - s0) : 0;
-    const int smax = wave_max(ks);
-    for (int j0 = 0; j0 < smax; j0 += RELAX_UNROLL) {
-      int w[RELAX_UNROLL];
-      long long jj[RELAX_UNROLL];
+    {
+      int tot;
+      W.off[lane] = wave_excl_scan<int>(lchanged ? (int)(s1 - s0) : 0, &tot);
+      if (lane == 0) W.off[WAVE] = tot;
+      W.pb[lane] = s0;
+      wave_sync();
+      for (int e0 = 0; e0 < tot; e0 += WAVE * RELAX_UNROLL) {
+        int w[RELAX_UNROLL];
+        long long jj[RELAX_UNROLL];
 #pragma unroll
-      for (int k = 0; k < RELAX_UNROLL; ++k) {
-        jj[k] = j0 + k < ks ? s0 + j0 + k : -1;
-        w[k] = j0 + k < ks ? P.dag[s0 + j0 + k] : -1;
+        for (int k = 0; k < RELAX_UNROLL; ++k) {
+          const int e = e0 + k * WAVE + (int)lane;
+          const int own = e < tot ? wave_owner(W, e) : -1;
+          jj[k] = own >= 0 ? W.pb[own] + (e - W.off[own]) : -1;
+          w[k] = own >= 0 ? P.dag[jj[k]] : -1;
+        }
+        if (tr) relax_translate(P, w, jj);
+        relax_mark(P, ast, t, stamp, X.lim, w);
       }
-      if (tr) relax_translate(P, w, jj);
-      relax_mark(P, ast, t, stamp, X.lim, w);
+      wave_sync();   // W is rewritten below
     }
     // the others: the whole wavefront, one after the other
     for (uint64_t m = ballot(act && !lite); m; m &= m - 1) {
