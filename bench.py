@@ -127,17 +127,22 @@ def source_digest(kernel):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, launches_per_step):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel sources; else None."""
+    taken on the current kernel sources; else None.  The counters give bytes
+    per call; the number of launches a call takes depends on timing (the JP
+    steps launch ends early when blocks start late), so the per-call bytes
+    are divided by this run's own launches per call."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
             rec = json.load(fh).get("%s/%s" % (kernel, workload))
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("source_digest") != source_digest(kernel):
+    if not rec or rec.get("source_digest") != source_digest(kernel) or not launches_per_step:
         return None
+    if "bytes_per_call" in rec:
+        return int(rec["bytes_per_call"] / launches_per_step)
     return rec.get("bytes_per_launch")
 
 
@@ -243,7 +248,7 @@ def roofline_record(tot_ms, launches, steps, step_bytes, kname, workload, extra=
     bytes_per_launch = step_bytes / launches_per_step
     achieved = bytes_per_launch / (per_launch_ms * 1e-3) / 1e9
     r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname, workload), "kernel": kname,
+         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname, workload, launches_per_step), "kernel": kname,
          "avg_launch_ms": round(per_launch_ms, 4), "launches_per_step": launches_per_step,
          "algorithmic_bytes_per_launch": int(bytes_per_launch)}
     if extra:
