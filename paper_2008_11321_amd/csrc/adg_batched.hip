@@ -231,7 +231,7 @@ struct Lds {
   int big[BB];               // UPDATE: rows handled by a whole wavefront
   unsigned nbig;
   unsigned f0;               // JP level-0 vertices found during ADG
-  unsigned fnext;            // next level's size
+  unsigned fnext[2];         // next level's size, by the parity of the level that fills it
   unsigned extc;             // extension words handed out
   int gid;
 };
@@ -473,6 +473,15 @@ __device__ int jp_graph(const BParams& P, const GraphCtx& C, Lds<BB>& S, unsigne
     if (tid == 0) atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
     nf = 0;
   }
+  // Three block barriers per level (of at most BB vertices): the scan's
+  // first, which also orders the vertices' LDS entries before the reads of
+  // the wavefront sums; a second after the successor offsets are written;
+  // a third after the pushes, before the next level's count is read.  The
+  // count a level fills alternates by level parity and is cleared by the
+  // level before (after that level's first barrier, by which time every
+  // thread has read it as its own level's size).
+  int par = 0;
+  if (tid == 0) S.fnext[0] = 0;
   while (nf > 0) {
     ++*levels;
     done += nf;
@@ -480,7 +489,6 @@ __device__ int jp_graph(const BParams& P, const GraphCtx& C, Lds<BB>& S, unsigne
       if (tid == 0) atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
       break;
     }
-    if (tid == 0) S.fnext = 0;
     for (unsigned b = 0; b < nf; b += BB) {
       const unsigned i = b + tid;
       long long cnt = 0;
@@ -497,8 +505,23 @@ __device__ int jp_graph(const BParams& P, const GraphCtx& C, Lds<BB>& S, unsigne
         S.sb[tid] = sb;
         S.cl[tid] = c;
       }
-      long long tot;
-      const long long pre = block_scan<BB>(cnt, S.red, &tot);   // barrier: sb, cl visible
+      // block prefix sum of the successor counts, the offsets written
+      // before its second barrier
+      constexpr int NW = BB / WAVE;
+      const unsigned lane = lane_id();
+      const int w = tid / WAVE;
+      const long long incl = wave_incl_scan<false>(cnt, OpAdd());
+      if (lane == WAVE - 1) S.red[w] = incl;
+      __syncthreads();
+      if (b == 0 && tid == 0) S.fnext[par ^ 1] = 0;   // the next level's count (read by all before this barrier)
+      long long pre = 0, tot = 0;
+#pragma unroll 4
+      for (int k = 0; k < NW; ++k) {
+        const long long t = S.red[k];
+        pre += k < w ? t : 0;
+        tot += t;
+      }
+      pre += incl - cnt;
       S.start[tid] = pre;
       if (tid == BB - 1) S.start[BB] = pre + cnt;
       __syncthreads();
@@ -515,18 +538,18 @@ __device__ int jp_graph(const BParams& P, const GraphCtx& C, Lds<BB>& S, unsigne
         unsigned long long mask;
         if (touch(P, C, u, S.cl[lo], &mask)) {
           const int cu = mask == JP_MASK ? 0 : __ffsll((long long)~mask);
-          const unsigned pos = atomicAdd(&S.fnext, 1u);
+          const unsigned pos = atomicAdd(&S.fnext[par], 1u);
           if (pos < (unsigned)C.n) Fn[pos] = ((unsigned long long)cu << 32) | (unsigned)u;
         }
       }
-      __syncthreads();
+      __syncthreads();   // S.red, S.start, S.sb and S.cl are rewritten next; the count is complete
     }
-    nf = S.fnext;
+    nf = S.fnext[par];
     if (nf > (unsigned)C.n) {
       if (tid == 0) atomicExch(&P.ctrl->error, ADG_ERR_INTERNAL);
       break;
     }
-    __syncthreads();   // everyone has read fnext before it is cleared
+    par ^= 1;
     unsigned long long* t = Fc;
     Fc = Fn;
     Fn = t;
