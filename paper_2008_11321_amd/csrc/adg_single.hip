@@ -1035,9 +1035,8 @@ struct RowMasks {
 };
 
 template <bool FUSED>
-__device__ void update_big(const Params& P, BmPool* pl, RowMasks& rm, int v, int l, unsigned char code,
-                           unsigned& x, long long idx) {
-  const long long b = P.rp[v], e = P.rp[v + 1];
+__device__ void update_big(const Params& P, BmPool* pl, RowMasks& rm, int v, long long b, long long e, int l,
+                           unsigned char code, unsigned& x, long long idx) {
   if (e - b > HUGE_DEG) {  // a hub: its chunks are spread over the grid by k_update_huge_*
     if (lane_id() == 0) {
       const unsigned long long nch = (unsigned long long)((e - b + HUGE_CHUNK - 1) / HUGE_CHUNK);
@@ -1139,15 +1138,29 @@ __global__ __launch_bounds__(BS) void k_update(Params P, int l) {
   } wu[WPB];
   WaveUpd& U = wu[threadIdx.x / WAVE];
   if (FUSED) pool = pool_load(P, gw);
-  for (long long it = gw; it < items; it += gstride) {
-    if (it < nsg) {
-      long long idx = it * WAVE + lane_id();
-      bool valid = idx < nRs;
-      int v = valid ? RL[idx] : 0;
-      update_small<FUSED>(P, &pool, U.sr, v, valid, l, code, x, it * WAVE);
-    } else {
-      const long long idx = nRs + (it - nsg);
-      update_big<FUSED>(P, &pool, U.rm, RL[idx], l, code, x, idx);
+  long long it = gw;
+  for (; it < items && it < nsg; it += gstride) {
+    long long idx = it * WAVE + lane_id();
+    bool valid = idx < nRs;
+    int v = valid ? RL[idx] : 0;
+    update_small<FUSED>(P, &pool, U.sr, v, valid, l, code, x, it * WAVE);
+  }
+  // The long rows, one after the other per wavefront, with the next ones'
+  // metadata in flight: the vertex of the row after next and the bounds of
+  // the next row are loaded while a row is walked.
+  if (it < items) {
+    auto vert = [&](long long k) { return k < items ? RL[nRs + (k - nsg)] : 0; };
+    int v0 = vert(it);
+    long long b0 = P.rp[v0], e0 = P.rp[v0 + 1];
+    int v1 = vert(it + gstride);
+    for (; it < items; it += gstride) {
+      const int v2 = vert(it + 2 * gstride);
+      const long long b1 = P.rp[v1], e1 = P.rp[v1 + 1];
+      update_big<FUSED>(P, &pool, U.rm, v0, b0, e0, l, code, x, nRs + (it - nsg));
+      v0 = v1;
+      b0 = b1;
+      e0 = e1;
+      v1 = v2;
     }
   }
   if (FUSED) pool_store(P, gw, pool);
