@@ -427,7 +427,7 @@ __global__ void k_stats(Params P, int l) {
   red[threadIdx.x] = x;
   __syncthreads();
   for (int s = BS / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    if (threadIdx.x < (unsigned)s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
   if (threadIdx.x != 0) return;
@@ -597,7 +597,7 @@ __global__ __launch_bounds__(BS) void k_msel(Params P, int l, int pass) {
   part[threadIdx.x] = run;
   __syncthreads();
   for (int off = 1; off < BS; off <<= 1) {
-    const unsigned v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    const unsigned v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0;
     __syncthreads();
     part[threadIdx.x] += v;
     __syncthreads();
@@ -678,8 +678,8 @@ __global__ __launch_bounds__(BS) void k_scan(Params P, int l) {
   for (int off = 1; off < BS; off <<= 1) {
     unsigned long long v[3];
     unsigned long long sv = 0;
-    for (int j = 0; j < 3; ++j) v[j] = threadIdx.x >= off ? part[j][threadIdx.x - off] : 0;
-    if (threadIdx.x >= off) sv = sums[threadIdx.x - off];
+    for (int j = 0; j < 3; ++j) v[j] = threadIdx.x >= (unsigned)off ? part[j][threadIdx.x - off] : 0;
+    if (threadIdx.x >= (unsigned)off) sv = sums[threadIdx.x - off];
     __syncthreads();
     for (int j = 0; j < 3; ++j) part[j][threadIdx.x] += v[j];
     sums[threadIdx.x] += sv;
