@@ -2371,7 +2371,8 @@ __device__ __forceinline__ int relax_wave(const Params& P, WaveLds& W, unsigned 
 }
 
 // Marks and list entries for RELAX_UNROLL same-round successors w[k]
-// (positions, -1: none) of a vertex whose colour changed: each is listed for
+// (positions, or vertex ids in a round relaxed by id; -1: none) of a vertex
+// whose colour changed: each is listed for
 // the next step unless a mark at its stamp says it already is (most are:
 // listed by another changed predecessor).  A plain read of the mark, which
 // can only lag behind, spares most of the atomics.
@@ -2406,14 +2407,15 @@ __device__ __forceinline__ void relax_push_wave(const Params& P, JpStage& ast, i
   }
 }
 
-// Step t >= 1 of round r over its list of nl positions.  A list no longer
-// than 2 gstride goes a wavefront per vertex (relax_wave, relax_push_wave).
-// Longer lists go G entries per wavefront, G spreading the list evenly over
-// the wavefronts (up to 64), with lb the wavefront's LDS area of
-// 64 x RELAX_LW words: a light vertex (at most RELAX_LK same-round
-// predecessors and successors, at most RELAX_LW bitmap words) is solved and
-// pushed by its lane alone, in its own words of lb (word w of lane k at
-// lb[64 w + k]); the others by the whole wavefront, one after the other.
+// Step t >= 1 of round r over its list of nl entries (positions, or vertex
+// ids: relax_idx).  A list no longer than 2 gstride goes a wavefront per
+// vertex (relax_wave, relax_push_wave).  Longer lists go G entries per
+// wavefront, G spreading the list evenly over the wavefronts (up to 64),
+// with lb the wavefront's LDS area of 64 x RELAX_LW words: a light vertex
+// (at most RELAX_LK same-round predecessors and successors, at most
+// RELAX_LW bitmap words) gets its colour from its lane's own words of lb
+// (word w of lane k at lb[64 w + k]), the group's entries spread over the
+// lanes; the others are solved by the whole wavefront, one after the other.
 __device__ __forceinline__ void jp_relax_items(const Params& P, JpStage& st, WaveLds& W, unsigned* lb, int t, unsigned nl,
                                                unsigned stamp, long long gw, long long gstride, int r) {
   const unsigned lane = lane_id();
@@ -2605,11 +2607,11 @@ __device__ __forceinline__ void core_rec(const Params& P, CoreLds& K, unsigned t
 // (at most CORE_MAX).  The vertices are listed and sorted; cnt[v] of each
 // becomes -(position + 1), which tells a predecessor's position from its id
 // (cnt is not read again in a round finished this way).  Then one vertex at
-// a time, in order, with the block's loads running ahead: the records of the
-// vertex three places on, the predecessor ids of the one two places on, and
-// the predecessors' positions of the next one, so that a vertex's own step
-// only reads LDS: its first 64 bitmap words (loaded two steps before) and
-// the colours of its predecessors by position.
+// a time, in order, with the block's loads running ahead: the record of the
+// vertex four places on, the predecessor ids of the one two places on, and
+// the predecessors' positions and first 64 bitmap words of the next one, so
+// that a vertex's own step only reads LDS: its window of colours (set up in
+// the step before) and the colours of its predecessors by position.
 __device__ __forceinline__ void jp_core_round(const Params& P, CoreLds& K, int r) {
   const long long b = seg_begin(P, r), rs = seg_size(P, r);
   const unsigned tid = threadIdx.x;
