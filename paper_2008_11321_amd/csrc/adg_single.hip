@@ -168,7 +168,7 @@ constexpr unsigned RELAX_MIN_V = ADG_RELAX_MIN_V;   // smaller rounds keep their
 #endif
 constexpr unsigned RELAX_DENSE = ADG_RELAX_DENSE;   // vertices per level below which a round keeps its levels
 #ifndef ADG_RELAX_MID
-#define ADG_RELAX_MID 2048
+#define ADG_RELAX_MID 8192
 #endif
 constexpr unsigned RELAX_MID = ADG_RELAX_MID;   // relaxation lists the steps launch takes (larger: the grid)
 constexpr int RELAX_UNROLL = 4;                 // predecessor colours per lane in flight
