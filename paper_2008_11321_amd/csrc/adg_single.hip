@@ -100,9 +100,12 @@ constexpr int UPD_UNROLL = ADG_UPD_UNROLL;   // 64-entry chunks of rows UPDATE r
 #ifndef ADG_SUB_BINNED
 #define ADG_SUB_BINNED 1
 #endif
-constexpr int SUB_SHIFT = 14;                   // D decrements by bins of 2^14 target vertices
+#ifndef ADG_SUB_SHIFT
+#define ADG_SUB_SHIFT 15
+#endif
+constexpr int SUB_SHIFT = ADG_SUB_SHIFT;        // D decrements by bins of 2^SUB_SHIFT target vertices
 constexpr int SUB_SPAN = 1 << SUB_SHIFT;
-constexpr int SUB_MAX_BINS = 8192;              // (graphs up to 2^27 vertices; larger ones decrement at once)
+constexpr int SUB_MAX_BINS = 8192;              // (graphs up to 2^28 vertices; larger ones decrement at once)
 #ifndef ADG_SUB_BLOCKS
 #define ADG_SUB_BLOCKS 1024
 #endif
@@ -1921,11 +1924,14 @@ __global__ __launch_bounds__(SUB_BS) void k_sub_scatter(Params P) {
 }
 
 // Apply pass: chunk j of the bins' targets (chunks never span two bins)
-// summed per target in LDS, the sums taken off D.
+// summed per target in LDS, the sums taken off D.  The sums are 16-bit, two
+// to a word: a chunk holds fewer than 2^16 targets, so a half never carries
+// into the other.
+static_assert(SUB_CHUNK < 65536, "16-bit sums per chunk");
 __global__ __launch_bounds__(SUB_BS) void k_sub_apply(Params P) {
   Ctrl* c = P.ctrl;
   if (c->done || c->sub_direct) return;
-  __shared__ unsigned cnt[SUB_SPAN];
+  __shared__ unsigned cnt[SUB_SPAN / 2];
   const unsigned nch = c->sub_chunks;
   const int nb = sub_bins(P);
   const unsigned* cpre = P.SUBS + nb + 1;
@@ -1940,17 +1946,20 @@ __global__ __launch_bounds__(SUB_BS) void k_sub_apply(Params P) {
     const unsigned long long b0 = P.SUBS[lo] + (unsigned long long)(j - cpre[lo]) * SUB_CHUNK;
     const unsigned long long bend = P.SUBS[lo + 1];
     const unsigned long long b1 = b0 + SUB_CHUNK < bend ? b0 + SUB_CHUNK : bend;
-    for (int i = threadIdx.x; i < SUB_SPAN; i += blockDim.x) cnt[i] = 0;
+    for (int i = threadIdx.x; i < SUB_SPAN / 2; i += blockDim.x) cnt[i] = 0;
     __syncthreads();
     const unsigned base = (unsigned)lo << SUB_SHIFT;
     for (unsigned long long i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
-      const unsigned w = P.SB[i];
-      if (w - base < (unsigned)SUB_SPAN) atomicAdd(&cnt[w - base], 1u);
+      const unsigned t = P.SB[i] - base;
+      if (t < (unsigned)SUB_SPAN) atomicAdd(&cnt[t >> 1], 1u << ((t & 1) * 16));
       else raise_internal(P);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < SUB_SPAN; i += blockDim.x)
-      if (cnt[i]) atomicSub(&P.D[base + i], (int)cnt[i]);
+    for (int i = threadIdx.x; i < SUB_SPAN / 2; i += blockDim.x) {
+      const unsigned x = cnt[i];   // non-zero halves belong to targets, so to vertices below n
+      if (x & 0xffffu) atomicSub(&P.D[base + 2 * i], (int)(x & 0xffffu));
+      if (x >> 16) atomicSub(&P.D[base + 2 * i + 1], (int)(x >> 16));
+    }
     __syncthreads();   // cnt is cleared for the next chunk
   }
 }
