@@ -114,7 +114,10 @@ constexpr int SUB_BLOCKS = ADG_SUB_BLOCKS;      // blocks of the count and scatt
 #define ADG_SUB_BS 1024
 #endif
 constexpr int SUB_BS = ADG_SUB_BS;              // their threads
-constexpr int SUB_CHUNK = 32768;                // targets an apply block takes at a time
+#ifndef ADG_SUB_CHUNK
+#define ADG_SUB_CHUNK 65535
+#endif
+constexpr int SUB_CHUNK = ADG_SUB_CHUNK;        // targets an apply block takes at a time
 constexpr int SUB_APPLY_BLOCKS = 1024;
 constexpr int64_t SUB_MIN_NNZ = 1 << 22;        // smaller graphs decrement at once (the passes cost more than they save)
 #ifndef ADG_SMALL_DEG

@@ -220,17 +220,17 @@ def test_hub_rows_longer_than_the_chunk_threshold(dev):
 def binned_limit_graph():
     """A graph for the binned decrements of D (taken at 2^22 entries and
     more): two hubs with adjacent ids, 65536 and 65537, so that their sums
-    share one LDS word of the apply pass, each losing 40000 leaves in round 1
-    -- a chunk of 32768 targets of their bin then holds over 26000 of one
-    hub's decrements, close to a 16-bit half's limit.  n = 3 * 2^15 + 17
-    leaves the last bin ragged; random edges among the other vertices make
-    up the entry count."""
+    share one LDS word of the apply pass, each losing 60000 leaves in round 1
+    -- a chunk of 65535 targets of their bin then holds over 47000 of one
+    hub's decrements, past 2^15 in a 16-bit half.  n = 4 * 2^15 + 17 leaves
+    the last bin ragged; random edges among the other vertices make up the
+    entry count."""
     rng = np.random.default_rng(23)
-    n = 3 * 2 ** 15 + 17
+    n = 4 * 2 ** 15 + 17
     a, b = 65536, 65537
-    la = np.arange(0, 40_000)
-    lb = np.arange(20_000, 60_000)
-    rnd = rng.integers(60_000, n, size=(2, 2_300_000))
+    la = np.arange(0, 60_000)
+    lb = np.concatenate([np.arange(30_000, 60_000), np.arange(66_000, 96_000)])
+    rnd = rng.integers(96_000, n, size=(2, 2_300_000))
     src = np.concatenate([np.full(la.size, a), np.full(lb.size, b), rnd[0]])
     dst = np.concatenate([la, lb, rnd[1]])
     return graphgen.from_edges(n, src, dst)
@@ -240,5 +240,6 @@ def test_binned_decrements_at_the_sum_limit(dev):
     rp, col = binned_limit_graph()
     assert col.size >= 2 ** 22
     rho, _, _ = oracle.adg(rp, col, 1, 10)
-    assert rho[65536] > 1 and rho[65537] > 1 and (rho[:60_000] == 1).all()
+    leaves = np.concatenate([np.arange(0, 60_000), np.arange(66_000, 96_000)])
+    assert rho[65536] > 1 and rho[65537] > 1 and (rho[leaves] == 1).all()
     _compare(dev, rp, col, 1, 10, 3, "binned sum limit")
