@@ -1726,6 +1726,10 @@ __device__ __forceinline__ int wave_colour(const Params& P, WaveLds& W, bool act
 // on each.  Both passes walk the same targets in each block.  SCATTER = false:
 // count them per bin in lds; true: write each to SB at the bin cursor in lds
 // (or, with `direct`, decrement D at once).
+#ifndef ADG_SUB_UNROLL
+#define ADG_SUB_UNROLL 16
+#endif
+constexpr int SUB_UNROLL = ADG_SUB_UNROLL;   // 64-target chunks the binning walks load at a time
 template <bool SCATTER>
 __device__ __forceinline__ void sub_walk(const Params& P, WaveLds& W, unsigned* lds, bool direct) {
   Ctrl* c = P.ctrl;
@@ -1757,10 +1761,10 @@ __device__ __forceinline__ void sub_walk(const Params& P, WaveLds& W, unsigned* 
     W.pb[lane] = b;
     if (lane == 0) W.off[WAVE] = tot;
     wave_sync();
-    for (int e0 = 0; e0 < tot; e0 += WAVE * UPD_UNROLL) {
-      int w[UPD_UNROLL];
+    for (int e0 = 0; e0 < tot; e0 += WAVE * SUB_UNROLL) {
+      int w[SUB_UNROLL];
 #pragma unroll
-      for (int u = 0; u < UPD_UNROLL; ++u) {
+      for (int u = 0; u < SUB_UNROLL; ++u) {
         const int e = e0 + u * WAVE + (int)lane;
         w[u] = -1;
         if (e < tot) {
@@ -1769,7 +1773,7 @@ __device__ __forceinline__ void sub_walk(const Params& P, WaveLds& W, unsigned* 
         }
       }
 #pragma unroll
-      for (int u = 0; u < UPD_UNROLL; ++u)
+      for (int u = 0; u < SUB_UNROLL; ++u)
         if (w[u] >= 0 && vid_ok(P, w[u])) {
           if (!SCATTER) atomicAdd(&lds[w[u] >> SUB_SHIFT], 1u);
           else if (direct) atomicSub(&P.D[w[u]], 1);
